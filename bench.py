@@ -1,0 +1,267 @@
+"""Benchmark of the compositing hot path on one MI355X.
+
+Prints ONE JSON line.  `value` is the device-resident rate of the depth
+workload (N=128 members of 8192x8192 uint8 -> count u32, sum u32, max u8),
+inputs already in HBM: one step folds all 128 members into the working
+composite with one kernel launch (the composite keeps accumulating across
+steps, as the paper's iterative composite does).  The streamed (PCIe-inclusive)
+rates of the streamed mask workload (N=256 of 4096x4096 from pinned host memory,
+chunks of 8 through two staging slots) and of the depth workload are reported
+beside it, with the plain host-to-device copy rate of the same chunks as the
+efficiency denominator, the single-buffer control and the tiled layout.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-streamed]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpixel-members/s composited (resident & streamed) at bit-exact; p50/p99 req latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def closed_form(levels, kind):
+    """Composite of members drawn from one elevation field, per elevation value
+    (used to confirm the benchmark's own output is exact)."""
+    cnt = np.zeros(256, np.int64)
+    tot = np.zeros(256, np.int64)
+    mx = np.zeros(256, np.int64)
+    lv = np.asarray(levels, np.int64)
+    for e in range(256):
+        d = lv - e
+        d = d[d > 0]
+        cnt[e] = d.size
+        tot[e] = d.size if kind == "mask" else int(np.minimum(d, 255).sum())
+        mx[e] = (1 if d.size else 0) if kind == "mask" else (int(min(d.max(), 255)) if d.size else 0)
+    return {"count": cnt, "sum": tot, "max": mx}
+
+
+def device_members(torch, ens, e):
+    from paper_2104_14667_amd import synth
+    et = torch.from_numpy(e).to("cuda:0")
+    out = torch.empty((ens.N, ens.H, ens.W), dtype=torch.uint8, device="cuda:0")
+    for i, L in enumerate(ens.levels()):
+        synth.member_torch(et, int(L), ens.kind, out=out[i])
+    torch.cuda.synchronize()
+    return out
+
+
+def verify(comp, ens, e, reps):
+    """Output after `reps` identical batches equals reps x the closed form
+    (max: once)."""
+    lut = closed_form(ens.levels(), ens.kind)
+    ok = True
+    for name in ens.outputs:
+        got = comp.read(name).astype(np.int64)
+        exp = lut[name][e] * (1 if name == "max" else reps)
+        ok = ok and bool(np.array_equal(got, exp))
+    return ok
+
+
+def run_resident(torch, ens, e, steps, warmup):
+    from paper_2104_14667_amd.composite import Composite
+    dev = device_members(torch, ens, e)
+    ptrs = [dev[i] for i in range(ens.N)]
+    with Composite(ens.W, ens.H, ens.outputs, ens.count_bits, profile=1) as c:
+        for _ in range(warmup):
+            c.add_device(ptrs)
+        c.sync()
+        c.kernel_stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            c.add_device(ptrs)
+        c.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        launches, kms = c.kernel_stats(reset=True)
+        exact = verify(c, ens, e, steps + warmup)
+    del dev, ptrs
+    torch.cuda.empty_cache()
+    return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact)
+
+
+def h2d_copy_rate(torch, host, chunk, reps):
+    """Plain pinned host-to-device copy of the same bytes in the same chunks
+    into two alternating device buffers: the efficiency denominator."""
+    n = host.shape[0]
+    plane = host[0].numel()
+    bufs = [torch.empty((chunk, plane), dtype=torch.uint8, device="cuda:0") for _ in range(2)]
+    s = torch.cuda.Stream()
+    flat = host.view(n, plane)
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s):
+            for k, i in enumerate(range(0, n, chunk)):
+                j = min(n, i + chunk)
+                bufs[k % 2][: j - i].copy_(flat[i:j], non_blocking=True)
+        s.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    del bufs
+    return best
+
+
+def run_streamed(torch, ens, e, reps, variants):
+    from paper_2104_14667_amd.composite import CMP_TILED, Composite
+    dev = device_members(torch, ens, e)
+    host = torch.empty(dev.shape, dtype=torch.uint8, pin_memory=True)
+    host.copy_(dev)
+    del dev
+    torch.cuda.empty_cache()
+    maps = [host[i] for i in range(ens.N)]
+    res = {}
+    nbytes = ens.N * ens.H * ens.W
+    copy_s = h2d_copy_rate(torch, host, 8, reps)
+    res["h2d_copy_GBps"] = nbytes / copy_s / 1e9
+    for name, kw in variants.items():
+        kw = dict(kw)
+        if kw.get("layout") == "tiled":
+            kw["layout"] = CMP_TILED
+        times = []
+        with Composite(ens.W, ens.H, ens.outputs, ens.count_bits, profile=1, **kw) as c:
+            exact = True
+            for r in range(reps + 1):
+                c.clear()
+                c.sync()
+                c.kernel_stats(reset=True)
+                t0 = time.perf_counter()
+                c.add(maps)
+                c.sync()
+                t1 = time.perf_counter()
+                if r > 0:       # first pass allocates the staging ring
+                    times.append(t1 - t0)
+                launches, kms = c.kernel_stats(reset=True)
+            exact = verify(c, ens, e, 1)
+        best = min(times)
+        rate = nbytes / best / 1e9
+        res[name] = dict(gpx_member_per_s=round(rate, 3), ms=round(best * 1e3, 3),
+                         efficiency_vs_copy=round(rate / res["h2d_copy_GBps"], 4),
+                         kernel_ms_per_pass=round(kms, 3), launches_per_pass=launches,
+                         exact=exact)
+    res["h2d_copy_GBps"] = round(res["h2d_copy_GBps"], 3)
+    del maps, host
+    return res
+
+
+def cpu_baseline(ens, e, seconds):
+    """The oracle as it stands, single-threaded numpy, on bands of rows of the
+    same workload until about `seconds` of CPU work; scaled to px-members/s."""
+    import oracle
+    from paper_2104_14667_amd import synth
+    lv = ens.levels()
+    make = synth.mask if ens.kind == "mask" else synth.depth
+    rows = 64
+    done_px = 0
+    spent = 0.0
+    y = 0
+    while spent < seconds and y < ens.H:
+        band = e[y:y + rows]
+        members = [make(band, int(L)) for L in lv]
+        t0 = time.perf_counter()
+        oracle.accumulate(members, shape=band.shape, outputs=ens.outputs)
+        spent += time.perf_counter() - t0
+        done_px += band.size * len(lv)
+        y += rows
+    return dict(value=round(done_px / spent / 1e9, 4), unit="Gpixel-members/s", cores=1,
+                kind="oracle",
+                sample=f"{y} of {ens.H} rows x all {ens.N} members of the value workload "
+                       f"({done_px / 1e9:.3f} G px-members, {spent:.1f} s), numpy single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--stream-reps", type=int, default=3)
+    ap.add_argument("--no-streamed", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the compositing path "
+              "has no multi-GPU mode in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2104_14667_amd import synth
+
+    ens = synth.DEPTH
+    log("elevation", ens.name)
+    e = ens.elevation()
+    log("resident", ens.name)
+    r = run_resident(torch, ens, e, args.steps, args.warmup)
+    px = ens.N * ens.H * ens.W
+    value = px * args.steps / r["seconds"] / 1e9
+    kavg_s = r["kernel_ms"] / max(r["launches"], 1) / 1e3
+    algo_bytes = px + 2 * ens.H * ens.W * (4 + 4 + 1)
+    achieved = algo_bytes / kavg_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gpixel-members/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["seconds"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "depth ensemble N=128 x 8192x8192 uint8 -> count u32, sum u32, "
+                               "max u8; device-resident, one launch per step",
+                   "members": ens.N, "W": ens.W, "H": ens.H, "seed": ens.seed},
+        "bit_exact": r["exact"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": "k_composite<count|sum|max> (linear)",
+                     "kernel_avg_ms": round(kavg_s * 1e3, 4),
+                     "algorithmic_bytes_per_launch": algo_bytes},
+    }
+    if not args.no_streamed:
+        log("streamed", synth.STREAMED.name)
+        e1 = synth.STREAMED.elevation()
+        out["streamed"] = {
+            "workload": "streamed masks N=256 x 4096x4096 uint8 -> count u32, pinned host, "
+                        "chunk 8, PCIe-inclusive",
+            **run_streamed(torch, synth.STREAMED, e1, args.stream_reps, {
+                "dual_buffer_linear": dict(nbuf=2, chunk_depth=8),
+                "single_buffer_linear": dict(nbuf=1, chunk_depth=8),
+                "dual_buffer_tiled": dict(nbuf=2, chunk_depth=8, layout="tiled"),
+            })}
+        log("streamed", ens.name)
+        out["streamed_depth"] = {
+            "workload": "depth N=128 x 8192x8192 from pinned host, chunk 8, PCIe-inclusive",
+            **run_streamed(torch, ens, e, max(1, args.stream_reps - 1), {
+                "dual_buffer_linear": dict(nbuf=2, chunk_depth=8)})}
+    log("cpu baseline")
+    out["cpu_baseline"] = cpu_baseline(ens, e, args.cpu_seconds)
+    out["host"] = {"cpu": platform.processor() or platform.machine(),
+                   "os_cpu_count": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

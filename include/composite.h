@@ -1,0 +1,181 @@
+/* composite.h -- C ABI of libcomposite.so: ensemble compositing of uint8
+ * rasters on an AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Johnson & Jankun-Kelly, arXiv 2104.14667): N input surfaces
+ * are combined into one composite image whose value grows with their overlap,
+ * and the user adds surfaces to, and removes them from, the working set in
+ * real time (Section 2 and the caption of Figure 1).  The composite is built
+ * iteratively: accumulators are cleared, then each input is uploaded and folded
+ * in by an accumulation kernel (Section 4, the single- and dual-buffer
+ * listings, Figures 2 and 3); with two staging buffers the upload of one input
+ * overlaps the processing of the previous one (Section 4, Figure 4).
+ *
+ * Per pixel p, over the current multiset M of members m (W x H uint8 rasters,
+ * row-major, pitch W):
+ *     count[p] = #{m in M : m[p] != 0}          (uint16 or uint32)
+ *     sum[p]   = sum of m[p] over M               (uint32)
+ *     max[p]   = max({0} U {m[p] : m in M})       (uint8)
+ * Results are exact; a call that could make a stored value overflow is refused
+ * with CMP_ERANGE before anything is enqueued.
+ *
+ * Conventions for every function below:
+ *   - The return value is CMP_OK (0) or a negative cmp_status.  No function
+ *     aborts, throws, or prints.
+ *   - Every argument is validated before any work is enqueued; on an error
+ *     return the context is unchanged.
+ *   - A HIP runtime failure returns CMP_EDEVICE and poisons the context: every
+ *     later call on it returns CMP_EDEVICE, except composite_free.
+ *   - The caller owns all input rasters and output buffers.  The library owns
+ *     the device composite, its staging buffers, streams and events.
+ *   - A context is used by one host thread at a time; distinct contexts are
+ *     independent.
+ */
+#ifndef COMPOSITE_H
+#define COMPOSITE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum cmp_status {
+  CMP_OK = 0,
+  CMP_EINVAL = -1,       /* bad argument: null pointer, size, window, flag   */
+  CMP_ENOMEM = -2,       /* device or pinned host allocation failed          */
+  CMP_ERANGE = -3,       /* the call could overflow a stored composite value */
+  CMP_ENOTMEMBER = -4,   /* remove of an id the working set does not hold    */
+  CMP_EUNSUPPORTED = -5, /* valid request this configuration cannot serve    */
+  CMP_EDEVICE = -6,      /* no usable GPU, or a HIP call failed (poisoned)   */
+  CMP_EBUSY = -7,        /* resource is in use                               */
+  CMP_ETIMEDOUT = -8     /* a bounded wait expired                           */
+};
+
+/* Output selection bits (composite_init `outputs`, composite_read `which`). */
+enum cmp_outputs { CMP_COUNT = 1, CMP_SUM = 2, CMP_MAX = 4 };
+
+/* Layout of staged members on the device.  CMP_LINEAR reads the staged
+ * rasters row-major as uploaded (the paper's buffers).  CMP_TILED first
+ * repacks each staged raster into tiles of tile_w bytes x tile_h rows, stored
+ * tile after tile, and composites from the tiled copy (the counterpart of the
+ * paper's buffer-to-image transform and image reads, Section 4, third
+ * implementation method).  Results are identical. */
+enum cmp_layout { CMP_LINEAR = 0, CMP_TILED = 1 };
+
+typedef struct cmp_opts {
+  int32_t nbuf;           /* staging slots for composite_add: 1 or 2.  1 is the
+                             single-buffer control (upload and compositing
+                             alternate), 2 the dual-buffer pipeline.  Default 2 */
+  int32_t chunk_depth;    /* members uploaded per staging slot, 1..256.
+                             Default 8 */
+  int32_t layout;         /* cmp_layout.  Default CMP_LINEAR */
+  int32_t tile_w;         /* CMP_TILED tile width in bytes: 16, 32, 64 or 128.
+                             Default 64 */
+  int32_t tile_h;         /* CMP_TILED tile height in rows, 1..256.  Default 64 */
+  int32_t device;         /* HIP device ordinal.  Default 0 */
+  void *copy_stream;      /* hipStream_t for uploads, or NULL: the library
+                             creates a default-priority stream */
+  void *compute_stream;   /* hipStream_t for kernels, or NULL (as above) */
+  int32_t retain_members; /* 1: remember the device pointer of every member
+                             added with composite_add_device, so a remove can
+                             recompute max.  The caller keeps those rasters
+                             alive while they are members.  Default 0 */
+  int32_t debug_poison;   /* 1: fill each staging slot with 0xA5 once the
+                             kernel that read it is done (hazard testing).
+                             Default 0 */
+  int32_t profile;        /* 1: time every compositing kernel with HIP events
+                             on the compute stream (composite_kernel_stats).
+                             Default 0 */
+  int32_t reserved[5];    /* must be zero */
+} cmp_opts;
+
+typedef struct cmp_ctx cmp_ctx;
+
+/* Fills *opts with the defaults above.  NULL is ignored. */
+void composite_default_opts(cmp_opts *opts);
+
+/* Creates a context holding a cleared W x H composite on the device.
+ * outputs: non-empty OR of cmp_outputs.  count_bits: 16 or 32 (ignored
+ * without CMP_COUNT).  opts: NULL for defaults.  W, H >= 1 and W*H < 2^40.
+ * Returns CMP_EDEVICE when no GPU is usable, CMP_ENOMEM when the composite
+ * does not fit.  On success *out owns the context (composite_free). */
+int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs,
+                   int32_t count_bits, const cmp_opts *opts);
+
+/* Clears the composite and forgets every member (both listings, step 1). */
+int composite_clear(cmp_ctx *ctx);
+
+/* Streams n members from host memory into the composite.
+ * host_maps[i]: W*H bytes, row-major.  Pinned memory (hipHostMalloc or
+ * torch pin_memory) is uploaded by the copy engine at full link rate; pageable
+ * memory works but is staged by the runtime.  Members are uploaded in chunks of
+ * chunk_depth into nbuf staging slots on the copy stream; the compute stream
+ * waits for each chunk's upload and the copy stream waits for a slot to be
+ * released by the kernel that read it, so no host synchronisation happens
+ * inside the loop.  ids: NULL, or n ids recorded in the member registry
+ * (needed to remove by id).  Returns when the library no longer reads
+ * host_maps; compositing may still run (composite_sync / composite_read wait
+ * for it).  n == 0 is a no-op. */
+int composite_add(cmp_ctx *ctx, const uint8_t *const *host_maps,
+                  const int64_t *ids, int32_t n);
+
+/* Composites n members that are already in device memory (one kernel pass over
+ * all of them, no staging).  dev_maps[i]: device pointers to W*H bytes, any
+ * alignment.  The rasters must stay valid until composite_sync returns, and,
+ * with retain_members, for as long as they are members.  Returns without
+ * waiting for the device. */
+int composite_add_device(cmp_ctx *ctx, const uint8_t *const *dev_maps,
+                         const int64_t *ids, int32_t n);
+
+/* Removes n members: count and sum are decremented exactly; max, when
+ * selected, is recomputed from the retained members (retain_members = 1 and
+ * every member added with composite_add_device), else CMP_EUNSUPPORTED.
+ * maps: the rasters removed (host memory if maps_on_device == 0, else device
+ * memory), or NULL with retain_members = 1 and ids given: the retained rasters
+ * of those ids are used.  ids: NULL, or n ids; an id the registry does not
+ * hold (counting multiplicity) gives CMP_ENOTMEMBER.  Without ids the caller
+ * vouches that the rasters are members. */
+int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps,
+                     const int64_t *ids, int32_t n, int32_t maps_on_device);
+
+/* Copies the window [x0, x0+w) x [y0, y0+h) of one output (`which` is exactly
+ * one of CMP_COUNT, CMP_SUM, CMP_MAX and must have been selected at init) to
+ * dst, row by row with dst_pitch_bytes between rows (>= w * element size:
+ * 2 or 4 bytes for count, 4 for sum, 1 for max).  dst is host memory if
+ * dst_on_device == 0, else device memory.  Waits for all work enqueued on the
+ * context before it and returns when dst holds the data. */
+int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0,
+                   int32_t w, int32_t h, void *dst, int64_t dst_pitch_bytes,
+                   int32_t dst_on_device);
+
+/* Waits for all work enqueued on the context. */
+int composite_sync(cmp_ctx *ctx);
+
+/* Number of members currently composited (with multiplicity). */
+int composite_members(const cmp_ctx *ctx, int64_t *n_out);
+
+/* Device address of one output of the composite (row-major, pitch W elements),
+ * valid until composite_free.  For zero-copy consumers; the caller orders its
+ * own accesses after composite_sync. */
+int composite_device_buffer(cmp_ctx *ctx, uint32_t which, void **dev_ptr);
+
+/* With opts.profile = 1: number of compositing kernel launches and their
+ * summed duration in milliseconds (HIP events around each launch on the
+ * compute stream) since init or the last reset (reset != 0 clears them after
+ * reading).  Synchronises the context. */
+int composite_kernel_stats(cmp_ctx *ctx, int64_t *launches, double *total_ms,
+                           int32_t reset);
+
+/* Static description of a status code; never NULL. */
+const char *composite_strerror(int status);
+
+/* Waits for in-flight work, then releases everything the context owns.
+ * NULL is ignored. */
+void composite_free(cmp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COMPOSITE_H */

@@ -1,0 +1,272 @@
+"""Python binding of libcomposite.so (include/composite.h).
+
+Argument marshalling only: every step of the compositing path runs in the HIP
+library.  The functions carry the C names; ``Composite`` is a small owner
+object over one context.  If the library is missing the import of this module
+fails loudly; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcomposite.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "composite.h")
+
+CMP_OK, CMP_EINVAL, CMP_ENOMEM, CMP_ERANGE, CMP_ENOTMEMBER = 0, -1, -2, -3, -4
+CMP_EUNSUPPORTED, CMP_EDEVICE, CMP_EBUSY, CMP_ETIMEDOUT = -5, -6, -7, -8
+CMP_COUNT, CMP_SUM, CMP_MAX = 1, 2, 4
+CMP_LINEAR, CMP_TILED = 0, 1
+OUTPUT_BITS = {"count": CMP_COUNT, "sum": CMP_SUM, "max": CMP_MAX}
+
+
+class cmp_opts(C.Structure):
+    _fields_ = [("nbuf", C.c_int32), ("chunk_depth", C.c_int32), ("layout", C.c_int32),
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("device", C.c_int32),
+                ("copy_stream", C.c_void_p), ("compute_stream", C.c_void_p),
+                ("retain_members", C.c_int32), ("debug_poison", C.c_int32),
+                ("profile", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+class CompositeError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {composite_strerror(status)} ({status})")
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "or python -m paper_2104_14667_amd.build")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_vp, _i32, _i64, _u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+_P = C.POINTER
+_SIGS = {
+    "composite_default_opts": (None, [_P(cmp_opts)]),
+    "composite_init": (C.c_int, [_P(_vp), _i32, _i32, _u32, _i32, _P(cmp_opts)]),
+    "composite_clear": (C.c_int, [_vp]),
+    "composite_add": (C.c_int, [_vp, _P(_vp), _P(_i64), _i32]),
+    "composite_add_device": (C.c_int, [_vp, _P(_vp), _P(_i64), _i32]),
+    "composite_remove": (C.c_int, [_vp, _P(_vp), _P(_i64), _i32, _i32]),
+    "composite_read": (C.c_int, [_vp, _u32, _i32, _i32, _i32, _i32, _vp, _i64, _i32]),
+    "composite_sync": (C.c_int, [_vp]),
+    "composite_members": (C.c_int, [_vp, _P(_i64)]),
+    "composite_device_buffer": (C.c_int, [_vp, _u32, _P(_vp)]),
+    "composite_kernel_stats": (C.c_int, [_vp, _P(_i64), _P(C.c_double), _i32]),
+    "composite_strerror": (C.c_char_p, [C.c_int]),
+    "composite_free": (None, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def header_functions(path: str = HEADER) -> list:
+    """Names of the functions include/composite.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(composite_\w+)\s*\(", text)))
+
+
+def composite_strerror(status: int) -> str:
+    return lib.composite_strerror(int(status)).decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != CMP_OK:
+        raise CompositeError(rc, what)
+
+
+def composite_default_opts() -> cmp_opts:
+    o = cmp_opts()
+    lib.composite_default_opts(C.byref(o))
+    return o
+
+
+def _ptr(x) -> int:
+    """Address of a torch tensor, numpy array or integer."""
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _ptr_array(maps) -> C.Array:
+    return (C.c_void_p * len(maps))(*[_ptr(m) for m in maps])
+
+
+def _ids_array(ids, n):
+    if ids is None:
+        return None
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int64))
+    if ids.size != n:
+        raise ValueError("one id per map")
+    return (C.c_int64 * n)(*ids.tolist())
+
+
+def composite_init(W: int, H: int, outputs: int, count_bits: int = 32,
+                   opts: Optional[cmp_opts] = None) -> int:
+    h = C.c_void_p()
+    _check(lib.composite_init(C.byref(h), int(W), int(H), int(outputs), int(count_bits),
+                              C.byref(opts) if opts is not None else None), "composite_init")
+    return h.value
+
+
+def composite_clear(ctx: int) -> None:
+    _check(lib.composite_clear(ctx), "composite_clear")
+
+
+def composite_add(ctx: int, host_maps: Sequence, ids=None) -> None:
+    n = len(host_maps)
+    _check(lib.composite_add(ctx, _ptr_array(host_maps), _ids_array(ids, n), n), "composite_add")
+
+
+def composite_add_device(ctx: int, dev_maps: Sequence, ids=None) -> None:
+    n = len(dev_maps)
+    _check(lib.composite_add_device(ctx, _ptr_array(dev_maps), _ids_array(ids, n), n),
+           "composite_add_device")
+
+
+def composite_remove(ctx: int, maps: Optional[Sequence], ids=None, n: Optional[int] = None,
+                     maps_on_device: bool = False) -> None:
+    if maps is not None:
+        n = len(maps)
+    elif n is None:
+        n = len(ids)
+    arr = _ptr_array(maps) if maps is not None else None
+    _check(lib.composite_remove(ctx, arr, _ids_array(ids, n), n, int(bool(maps_on_device))),
+           "composite_remove")
+
+
+def composite_read(ctx: int, which: int, x0: int, y0: int, w: int, h: int, dst,
+                   dst_pitch_bytes: int, dst_on_device: bool = False) -> None:
+    _check(lib.composite_read(ctx, int(which), int(x0), int(y0), int(w), int(h), _ptr(dst),
+                              int(dst_pitch_bytes), int(bool(dst_on_device))), "composite_read")
+
+
+def composite_sync(ctx: int) -> None:
+    _check(lib.composite_sync(ctx), "composite_sync")
+
+
+def composite_members(ctx: int) -> int:
+    n = C.c_int64()
+    _check(lib.composite_members(ctx, C.byref(n)), "composite_members")
+    return n.value
+
+
+def composite_device_buffer(ctx: int, which: int) -> int:
+    p = C.c_void_p()
+    _check(lib.composite_device_buffer(ctx, int(which), C.byref(p)), "composite_device_buffer")
+    return p.value
+
+
+def composite_kernel_stats(ctx: int, reset: bool = False):
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(lib.composite_kernel_stats(ctx, C.byref(n), C.byref(ms), int(bool(reset))),
+           "composite_kernel_stats")
+    return n.value, ms.value
+
+
+def composite_free(ctx: int) -> None:
+    lib.composite_free(ctx)
+
+
+_DT = {CMP_SUM: np.uint32, CMP_MAX: np.uint8}
+
+
+class Composite:
+    """One compositing context (owner of a device composite)."""
+
+    def __init__(self, W: int, H: int, outputs=("count",), count_bits: int = 32, **opts):
+        self.W, self.H = int(W), int(H)
+        self.outputs = tuple(outputs)
+        self.count_bits = int(count_bits)
+        o = composite_default_opts()
+        for k, v in opts.items():
+            if k in ("copy_stream", "compute_stream") and v is not None and not isinstance(v, int):
+                v = int(v.cuda_stream)          # torch.cuda.Stream
+            setattr(o, k, v)
+        self.opts = o
+        bits = 0
+        for name in self.outputs:
+            bits |= OUTPUT_BITS[name]
+        self.ctx = composite_init(W, H, bits, count_bits, o)
+
+    def close(self) -> None:
+        if self.ctx:
+            composite_free(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self):
+        composite_clear(self.ctx)
+
+    def add(self, host_maps, ids=None):
+        composite_add(self.ctx, host_maps, ids)
+
+    def add_device(self, dev_maps, ids=None):
+        composite_add_device(self.ctx, dev_maps, ids)
+
+    def remove(self, maps=None, ids=None, on_device=False):
+        composite_remove(self.ctx, maps, ids, None, on_device)
+
+    def sync(self):
+        composite_sync(self.ctx)
+
+    def members(self) -> int:
+        return composite_members(self.ctx)
+
+    def kernel_stats(self, reset=False):
+        return composite_kernel_stats(self.ctx, reset)
+
+    def dtype(self, name: str):
+        if name == "count":
+            return np.uint16 if self.count_bits == 16 else np.uint32
+        return _DT[OUTPUT_BITS[name]]
+
+    def read(self, name: str, window=None, out: Optional[np.ndarray] = None) -> np.ndarray:
+        """Window (x0, y0, w, h) of one output into host memory (numpy)."""
+        x0, y0, w, h = window if window is not None else (0, 0, self.W, self.H)
+        dt = self.dtype(name)
+        if out is None:
+            out = np.empty((h, w), dtype=dt)
+        if out.dtype != dt or out.shape != (h, w) or not out.flags.c_contiguous:
+            raise ValueError("out must be a C-contiguous (h, w) array of the output's dtype")
+        composite_read(self.ctx, OUTPUT_BITS[name], x0, y0, w, h, out, w * out.itemsize)
+        return out
+
+    def read_device(self, name: str, dst, window=None, pitch_bytes: Optional[int] = None):
+        """Window of one output into device memory (a torch tensor or address)."""
+        x0, y0, w, h = window if window is not None else (0, 0, self.W, self.H)
+        eb = np.dtype(self.dtype(name)).itemsize
+        composite_read(self.ctx, OUTPUT_BITS[name], x0, y0, w, h, dst,
+                       pitch_bytes if pitch_bytes is not None else w * eb, True)
+
+    def device_buffer(self, name: str) -> int:
+        return composite_device_buffer(self.ctx, OUTPUT_BITS[name])

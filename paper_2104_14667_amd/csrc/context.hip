@@ -1,0 +1,672 @@
+// Compositing context: device composite, staging ring, streams, events and
+// the member registry behind the C ABI in include/composite.h.
+//
+// The streamed path is the paper's dual-buffer algorithm (Section 4, Figure 3,
+// "2b final" of the third implementation method): permanent receiving buffers
+// on the device are filled from host memory by the copy engine while the
+// previous chunk is composited; ordering uses events only (Section 4, last
+// paragraph; Section 7.1), never a host wait inside the loop.
+//   copy stream:    wait slot_free[k % nbuf]; H2D chunk k; record copied[k % nbuf]
+//   compute stream: wait copied[k % nbuf]; [repack to tiles]; composite;
+//                   record slot_free[k % nbuf]
+// nbuf = 1 gives the single-buffer control (Figure 2): every upload waits for
+// the kernel that read the previous one.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/composite.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int64_t kMaxPixels = (int64_t(1) << 32) - 16;  // 32-bit pixel indices
+constexpr int64_t kSumGuard = 16843009;  // floor((2^32 - 1) / 255): members whose sum fits u32
+
+struct Timed {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+struct cmp_ctx {
+  int dev = 0;
+  int32_t W = 0, H = 0;
+  int64_t npix = 0;
+  uint32_t outs = 0;
+  int count_bits = 32;
+  cmp_opts o{};
+  bool poisoned = false;
+
+  hipStream_t copy_s = nullptr, comp_s = nullptr;
+  bool own_copy = false, own_comp = false;
+
+  cmp::Outputs out;
+  void *d_count = nullptr;
+  uint32_t *d_sum = nullptr;
+  uint8_t *d_max = nullptr;
+
+  // Staging ring (allocated on the first streamed call).
+  int64_t stage_stride = 0;          // bytes between members in a slot
+  int64_t tiled_stride = 0;          // bytes between members in a tiled slot
+  uint8_t *d_stage[2] = {nullptr, nullptr};
+  uint8_t *d_tiled[2] = {nullptr, nullptr};
+  const uint8_t **d_slot_tab[2] = {nullptr, nullptr};  // member pointers of each slot
+  hipEvent_t ev_copied[2] = {nullptr, nullptr};
+  hipEvent_t ev_free[2] = {nullptr, nullptr};
+  hipEvent_t ev_host_done = nullptr;  // last upload done: host maps reusable
+
+  // Pointer tables for device-resident members: two pinned halves, each with
+  // the event that marks its last upload done.
+  const uint8_t **h_tab[2] = {nullptr, nullptr};
+  const uint8_t **d_tab[2] = {nullptr, nullptr};
+  int64_t tab_cap = 0;
+  int tab_half = 0;
+  hipEvent_t ev_tab[2] = {nullptr, nullptr};
+
+  // Registry: members with multiplicity (anonymous ones under id -1) and,
+  // with retain_members, their device pointers.
+  int64_t members = 0;
+  int64_t host_members = 0;  // members that came through composite_add
+  std::unordered_map<int64_t, std::vector<const uint8_t *>> held;
+
+  // Profiling of compositing kernels.
+  std::vector<Timed> timed;
+  size_t timed_used = 0;
+  double timed_ms = 0.0;
+  int64_t timed_launches = 0;
+};
+
+namespace {
+
+#define CMP_TRY(call)                          \
+  do {                                         \
+    if ((call) != hipSuccess) {                \
+      ctx->poisoned = true;                    \
+      return CMP_EDEVICE;                      \
+    }                                          \
+  } while (0)
+
+int elem_bytes(const cmp_ctx *ctx, uint32_t which) {
+  if (which == CMP_COUNT) return ctx->count_bits / 8;
+  if (which == CMP_SUM) return 4;
+  if (which == CMP_MAX) return 1;
+  return 0;
+}
+
+hipError_t set_device(const cmp_ctx *ctx) { return hipSetDevice(ctx->dev); }
+
+// Range guard: refuse any add that could overflow a stored value.
+bool fits(const cmp_ctx *ctx, int64_t add) {
+  const int64_t total = ctx->members + add;
+  if ((ctx->outs & CMP_COUNT) && total > ((int64_t(1) << ctx->count_bits) - 1)) return false;
+  if ((ctx->outs & CMP_SUM) && total > kSumGuard) return false;
+  return total <= (int64_t(1) << 40);
+}
+
+void free_all(cmp_ctx *ctx) {
+  hipSetDevice(ctx->dev);
+  if (ctx->comp_s) hipStreamSynchronize(ctx->comp_s);
+  if (ctx->copy_s) hipStreamSynchronize(ctx->copy_s);
+  hipFree(ctx->d_count);
+  hipFree(ctx->d_sum);
+  hipFree(ctx->d_max);
+  for (int i = 0; i < 2; ++i) {
+    hipFree(ctx->d_stage[i]);
+    hipFree(ctx->d_tiled[i]);
+    hipFree(ctx->d_slot_tab[i]);
+    hipFree(ctx->d_tab[i]);
+    if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
+    if (ctx->ev_copied[i]) hipEventDestroy(ctx->ev_copied[i]);
+    if (ctx->ev_free[i]) hipEventDestroy(ctx->ev_free[i]);
+    if (ctx->ev_tab[i]) hipEventDestroy(ctx->ev_tab[i]);
+  }
+  if (ctx->ev_host_done) hipEventDestroy(ctx->ev_host_done);
+  for (auto &t : ctx->timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  if (ctx->own_copy && ctx->copy_s) hipStreamDestroy(ctx->copy_s);
+  if (ctx->own_comp && ctx->comp_s) hipStreamDestroy(ctx->comp_s);
+}
+
+hipError_t clear_outputs(cmp_ctx *ctx) {
+  hipError_t e = hipSuccess;
+  if (ctx->d_count && e == hipSuccess)
+    e = cmp::launch_fill(ctx->d_count, 0, ctx->npix * (ctx->count_bits / 8), ctx->comp_s);
+  if (ctx->d_sum && e == hipSuccess) e = cmp::launch_fill(ctx->d_sum, 0, ctx->npix * 4, ctx->comp_s);
+  if (ctx->d_max && e == hipSuccess) e = cmp::launch_fill(ctx->d_max, 0, ctx->npix, ctx->comp_s);
+  return e;
+}
+
+// Brackets a compositing launch with events when profiling.
+hipError_t timed_begin(cmp_ctx *ctx, Timed **t) {
+  *t = nullptr;
+  if (!ctx->o.profile) return hipSuccess;
+  if (ctx->timed_used == ctx->timed.size()) {
+    Timed n;
+    hipError_t e = hipEventCreate(&n.a);
+    if (e == hipSuccess) e = hipEventCreate(&n.b);
+    if (e != hipSuccess) return e;
+    ctx->timed.push_back(n);
+  }
+  *t = &ctx->timed[ctx->timed_used++];
+  return hipEventRecord((*t)->a, ctx->comp_s);
+}
+hipError_t timed_end(cmp_ctx *ctx, Timed *t) {
+  return t ? hipEventRecord(t->b, ctx->comp_s) : hipSuccess;
+}
+hipError_t harvest_timing(cmp_ctx *ctx) {
+  for (size_t i = 0; i < ctx->timed_used; ++i) {
+    hipError_t e = hipEventSynchronize(ctx->timed[i].b);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ctx->timed[i].a, ctx->timed[i].b);
+    if (e != hipSuccess) return e;
+    ctx->timed_ms += ms;
+    ctx->timed_launches += 1;
+  }
+  ctx->timed_used = 0;
+  return hipSuccess;
+}
+
+hipError_t composite_pass(cmp_ctx *ctx, const uint8_t *const *d_tab, int n, bool sub,
+                          uint32_t outs, bool tiled) {
+  Timed *t = nullptr;
+  hipError_t e = timed_begin(ctx, &t);
+  if (e != hipSuccess) return e;
+  if (tiled) {
+    cmp::Tiling tl{ctx->W, ctx->H, ctx->o.tile_w, ctx->o.tile_h};
+    e = cmp::launch_composite_tiled(d_tab, n, tl, ctx->out, outs, sub, ctx->comp_s);
+  } else {
+    e = cmp::launch_composite_linear(d_tab, n, ctx->npix, ctx->out, outs, sub, ctx->comp_s);
+  }
+  if (e != hipSuccess) return e;
+  return timed_end(ctx, t);
+}
+
+void drop_staging(cmp_ctx *ctx) {
+  for (int i = 0; i < 2; ++i) {
+    hipFree(ctx->d_stage[i]);
+    hipFree(ctx->d_tiled[i]);
+    hipFree(ctx->d_slot_tab[i]);
+    ctx->d_stage[i] = ctx->d_tiled[i] = nullptr;
+    ctx->d_slot_tab[i] = nullptr;
+  }
+}
+
+int alloc_staging(cmp_ctx *ctx);
+
+// Allocates the staging ring on first use; on failure nothing is kept.
+int ensure_staging(cmp_ctx *ctx) {
+  if (ctx->d_stage[0]) return CMP_OK;
+  const int rc = alloc_staging(ctx);
+  if (rc != CMP_OK) drop_staging(ctx);
+  return rc;
+}
+
+int alloc_staging(cmp_ctx *ctx) {
+  const int d = ctx->o.chunk_depth;
+  ctx->stage_stride = (ctx->npix + 255) / 256 * 256;
+  const bool tiled = ctx->o.layout == CMP_TILED;
+  if (tiled) {
+    cmp::Tiling tl{ctx->W, ctx->H, ctx->o.tile_w, ctx->o.tile_h};
+    ctx->tiled_stride = (tl.plane() + 255) / 256 * 256;
+  }
+  for (int sidx = 0; sidx < ctx->o.nbuf; ++sidx) {
+    if (hipMalloc(&ctx->d_stage[sidx], ctx->stage_stride * d) != hipSuccess) return CMP_ENOMEM;
+    if (tiled && hipMalloc(&ctx->d_tiled[sidx], ctx->tiled_stride * d) != hipSuccess) return CMP_ENOMEM;
+    if (hipMalloc(&ctx->d_slot_tab[sidx], sizeof(void *) * d) != hipSuccess) return CMP_ENOMEM;
+    std::vector<const uint8_t *> tab(d);
+    uint8_t *base = tiled ? ctx->d_tiled[sidx] : ctx->d_stage[sidx];
+    const int64_t stride = tiled ? ctx->tiled_stride : ctx->stage_stride;
+    for (int j = 0; j < d; ++j) tab[j] = base + j * stride;
+    if (hipMemcpy(ctx->d_slot_tab[sidx], tab.data(), sizeof(void *) * d, hipMemcpyHostToDevice) != hipSuccess)
+      return CMP_EDEVICE;
+  }
+  return CMP_OK;
+}
+
+// Uploads a device pointer table through the pinned double buffer and returns
+// its device address (valid for work enqueued on the compute stream next).
+int upload_table(cmp_ctx *ctx, const uint8_t *const *ptrs, int64_t n, const uint8_t ***d_out) {
+  if (n > ctx->tab_cap) {
+    for (int i = 0; i < 2; ++i) {
+      if (ctx->ev_tab[i] && hipEventSynchronize(ctx->ev_tab[i]) != hipSuccess) return CMP_EDEVICE;
+      if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
+      hipFree(ctx->d_tab[i]);
+      ctx->h_tab[i] = nullptr;
+      ctx->d_tab[i] = nullptr;
+    }
+    // the compute stream may still read the old device tables
+    if (hipStreamSynchronize(ctx->comp_s) != hipSuccess) return CMP_EDEVICE;
+    int64_t cap = std::max<int64_t>(n, 4096);
+    for (int i = 0; i < 2; ++i) {
+      if (hipHostMalloc((void **)&ctx->h_tab[i], cap * sizeof(void *), hipHostMallocDefault) != hipSuccess)
+        return CMP_ENOMEM;
+      if (hipMalloc((void **)&ctx->d_tab[i], cap * sizeof(void *)) != hipSuccess) return CMP_ENOMEM;
+    }
+    ctx->tab_cap = cap;
+  }
+  const int h = ctx->tab_half;
+  ctx->tab_half ^= 1;
+  // the pinned half may still be the source of an upload two calls ago
+  if (hipEventSynchronize(ctx->ev_tab[h]) != hipSuccess) return CMP_EDEVICE;
+  std::memcpy(ctx->h_tab[h], ptrs, n * sizeof(void *));
+  if (hipMemcpyAsync(ctx->d_tab[h], ctx->h_tab[h], n * sizeof(void *), hipMemcpyHostToDevice,
+                     ctx->comp_s) != hipSuccess)
+    return CMP_EDEVICE;
+  if (hipEventRecord(ctx->ev_tab[h], ctx->comp_s) != hipSuccess) return CMP_EDEVICE;
+  *d_out = ctx->d_tab[h];
+  return CMP_OK;
+}
+
+// Streams n host rasters through the staging slots with op add or sub.
+int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub, uint32_t outs) {
+  int rc = ensure_staging(ctx);
+  if (rc != CMP_OK) return rc;
+  const int d = ctx->o.chunk_depth;
+  const int nb = ctx->o.nbuf;
+  const bool tiled = ctx->o.layout == CMP_TILED;
+  const int64_t plane = ctx->npix;
+  for (int32_t k0 = 0, k = 0; k0 < n; k0 += d, ++k) {
+    const int slot = k % nb;
+    const int cnt = std::min<int32_t>(d, n - k0);
+    CMP_TRY(hipStreamWaitEvent(ctx->copy_s, ctx->ev_free[slot], 0));
+    // Upload: runs of host rasters that are contiguous and staged contiguously
+    // go as one copy.
+    int j = 0;
+    while (j < cnt) {
+      int r = j + 1;
+      if (ctx->stage_stride == plane)
+        while (r < cnt && maps[k0 + r] == maps[k0 + r - 1] + plane) ++r;
+      CMP_TRY(hipMemcpyAsync(ctx->d_stage[slot] + j * ctx->stage_stride, maps[k0 + j],
+                             (size_t)(plane * (r - j)), hipMemcpyHostToDevice, ctx->copy_s));
+      j = r;
+    }
+    CMP_TRY(hipEventRecord(ctx->ev_copied[slot], ctx->copy_s));
+    CMP_TRY(hipStreamWaitEvent(ctx->comp_s, ctx->ev_copied[slot], 0));
+    if (tiled) {
+      // The receiving buffer is free again once it is repacked (the paper's
+      // decoupled transfer and transform); the tiled copy is only read by the
+      // kernel that follows on the same stream.
+      cmp::Tiling tl{ctx->W, ctx->H, ctx->o.tile_w, ctx->o.tile_h};
+      Timed *t = nullptr;
+      CMP_TRY(timed_begin(ctx, &t));
+      CMP_TRY(cmp::launch_repack_tiled(ctx->d_stage[slot], ctx->stage_stride, ctx->d_tiled[slot],
+                                       ctx->tiled_stride, cnt, tl, ctx->comp_s));
+      CMP_TRY(timed_end(ctx, t));
+      if (ctx->o.debug_poison)
+        CMP_TRY(cmp::launch_fill(ctx->d_stage[slot], 0xA5, ctx->stage_stride * d, ctx->comp_s));
+      CMP_TRY(hipEventRecord(ctx->ev_free[slot], ctx->comp_s));
+      CMP_TRY(composite_pass(ctx, ctx->d_slot_tab[slot], cnt, sub, outs, true));
+    } else {
+      CMP_TRY(composite_pass(ctx, ctx->d_slot_tab[slot], cnt, sub, outs, false));
+      if (ctx->o.debug_poison)
+        CMP_TRY(cmp::launch_fill(ctx->d_stage[slot], 0xA5, ctx->stage_stride * d, ctx->comp_s));
+      CMP_TRY(hipEventRecord(ctx->ev_free[slot], ctx->comp_s));
+    }
+  }
+  CMP_TRY(hipEventRecord(ctx->ev_host_done, ctx->copy_s));
+  CMP_TRY(hipEventSynchronize(ctx->ev_host_done));
+  return CMP_OK;
+}
+
+int check_ids_removable(const cmp_ctx *ctx, const int64_t *ids, int32_t n) {
+  std::unordered_map<int64_t, int64_t> need;
+  for (int32_t i = 0; i < n; ++i) need[ids[i]] += 1;
+  for (auto &kv : need) {
+    auto it = ctx->held.find(kv.first);
+    if (it == ctx->held.end() || (int64_t)it->second.size() < kv.second) return CMP_ENOTMEMBER;
+  }
+  return CMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void composite_default_opts(cmp_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nbuf = 2;
+  o->chunk_depth = 8;
+  o->layout = CMP_LINEAR;
+  o->tile_w = 64;
+  o->tile_h = 64;
+  o->device = 0;
+}
+
+int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_t count_bits,
+                   const cmp_opts *opts) {
+  if (!out) return CMP_EINVAL;
+  *out = nullptr;
+  if (W < 1 || H < 1 || (int64_t)W * H > kMaxPixels) return CMP_EINVAL;
+  if (outputs == 0 || (outputs & ~7u)) return CMP_EINVAL;
+  if ((outputs & CMP_COUNT) && count_bits != 16 && count_bits != 32) return CMP_EINVAL;
+  cmp_opts o;
+  composite_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.nbuf < 1 || o.nbuf > 2) return CMP_EINVAL;
+  if (o.chunk_depth < 1 || o.chunk_depth > cmp::kGroup) return CMP_EINVAL;
+  if (o.layout != CMP_LINEAR && o.layout != CMP_TILED) return CMP_EINVAL;
+  if (o.layout == CMP_TILED) {
+    if (o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64 && o.tile_w != 128) return CMP_EINVAL;
+    if (o.tile_h < 1 || o.tile_h > 256) return CMP_EINVAL;
+    if (W % 16) return CMP_EUNSUPPORTED;
+  }
+  for (int r : o.reserved)
+    if (r) return CMP_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CMP_EDEVICE;
+  if (o.device < 0 || o.device >= ndev) return CMP_EINVAL;
+
+  cmp_ctx *ctx = new (std::nothrow) cmp_ctx();
+  if (!ctx) return CMP_ENOMEM;
+  ctx->dev = o.device;
+  ctx->W = W;
+  ctx->H = H;
+  ctx->npix = (int64_t)W * H;
+  ctx->outs = outputs;
+  ctx->count_bits = (outputs & CMP_COUNT) ? count_bits : 32;
+  ctx->o = o;
+  int rc = CMP_EDEVICE;
+  do {
+    if (hipSetDevice(ctx->dev) != hipSuccess) break;
+    if (o.copy_stream) {
+      ctx->copy_s = (hipStream_t)o.copy_stream;
+    } else {
+      if (hipStreamCreateWithFlags(&ctx->copy_s, hipStreamNonBlocking) != hipSuccess) break;
+      ctx->own_copy = true;
+    }
+    if (o.compute_stream) {
+      ctx->comp_s = (hipStream_t)o.compute_stream;
+    } else {
+      if (hipStreamCreateWithFlags(&ctx->comp_s, hipStreamNonBlocking) != hipSuccess) break;
+      ctx->own_comp = true;
+    }
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i) {
+      ok = hipEventCreateWithFlags(&ctx->ev_copied[i], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&ctx->ev_free[i], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&ctx->ev_tab[i], hipEventDisableTiming) == hipSuccess;
+      // every event starts recorded, so the first wait on it is satisfied
+      ok = ok && hipEventRecord(ctx->ev_free[i], ctx->comp_s) == hipSuccess &&
+           hipEventRecord(ctx->ev_copied[i], ctx->copy_s) == hipSuccess &&
+           hipEventRecord(ctx->ev_tab[i], ctx->comp_s) == hipSuccess;
+    }
+    if (!ok || hipEventCreateWithFlags(&ctx->ev_host_done, hipEventDisableTiming) != hipSuccess) break;
+    rc = CMP_ENOMEM;
+    if (outputs & CMP_COUNT) {
+      if (hipMalloc(&ctx->d_count, ctx->npix * (ctx->count_bits / 8) + 64) != hipSuccess) break;
+    }
+    if (outputs & CMP_SUM) {
+      if (hipMalloc((void **)&ctx->d_sum, ctx->npix * 4 + 64) != hipSuccess) break;
+    }
+    if (outputs & CMP_MAX) {
+      if (hipMalloc((void **)&ctx->d_max, ctx->npix + 64) != hipSuccess) break;
+    }
+    ctx->out.count = ctx->d_count;
+    ctx->out.sum = ctx->d_sum;
+    ctx->out.max = ctx->d_max;
+    ctx->out.count16 = ctx->count_bits == 16;
+    rc = CMP_EDEVICE;
+    if (clear_outputs(ctx) != hipSuccess) break;
+    if (hipStreamSynchronize(ctx->comp_s) != hipSuccess) break;
+    rc = CMP_OK;
+  } while (false);
+  if (rc != CMP_OK) {
+    free_all(ctx);
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return CMP_OK;
+}
+
+int composite_clear(cmp_ctx *ctx) {
+  if (!ctx) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  CMP_TRY(set_device(ctx));
+  // the clear must not overtake uploads still feeding the compute stream
+  CMP_TRY(hipStreamSynchronize(ctx->copy_s));
+  CMP_TRY(clear_outputs(ctx));
+  ctx->members = 0;
+  ctx->host_members = 0;
+  ctx->held.clear();
+  return CMP_OK;
+}
+
+int composite_add(cmp_ctx *ctx, const uint8_t *const *host_maps, const int64_t *ids, int32_t n) {
+  if (!ctx) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  if (n < 0 || (n > 0 && !host_maps)) return CMP_EINVAL;
+  for (int32_t i = 0; i < n; ++i)
+    if (!host_maps[i]) return CMP_EINVAL;
+  if (n == 0) return CMP_OK;
+  if (!fits(ctx, n)) return CMP_ERANGE;
+  CMP_TRY(set_device(ctx));
+  int rc = ensure_staging(ctx);
+  if (rc != CMP_OK) return rc;
+  rc = stream_members(ctx, host_maps, n, false, ctx->outs);
+  if (rc != CMP_OK) {
+    ctx->poisoned = true;
+    return rc == CMP_ENOMEM ? CMP_ENOMEM : CMP_EDEVICE;
+  }
+  ctx->members += n;
+  ctx->host_members += n;
+  for (int32_t i = 0; i < n; ++i) ctx->held[ids ? ids[i] : -1].push_back(nullptr);
+  return CMP_OK;
+}
+
+int composite_add_device(cmp_ctx *ctx, const uint8_t *const *dev_maps, const int64_t *ids,
+                         int32_t n) {
+  if (!ctx) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  if (n < 0 || (n > 0 && !dev_maps)) return CMP_EINVAL;
+  for (int32_t i = 0; i < n; ++i)
+    if (!dev_maps[i]) return CMP_EINVAL;
+  if (n == 0) return CMP_OK;
+  if (!fits(ctx, n)) return CMP_ERANGE;
+  CMP_TRY(set_device(ctx));
+  const uint8_t **d_tab = nullptr;
+  int rc = upload_table(ctx, dev_maps, n, &d_tab);
+  if (rc != CMP_OK) {
+    ctx->poisoned = true;
+    return rc;
+  }
+  CMP_TRY(composite_pass(ctx, d_tab, n, false, ctx->outs, false));
+  ctx->members += n;
+  for (int32_t i = 0; i < n; ++i)
+    ctx->held[ids ? ids[i] : -1].push_back(ctx->o.retain_members ? dev_maps[i] : nullptr);
+  return CMP_OK;
+}
+
+int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *ids, int32_t n,
+                     int32_t maps_on_device) {
+  if (!ctx) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  if (n < 0) return CMP_EINVAL;
+  if (n == 0) return CMP_OK;
+  if (maps_on_device != 0 && maps_on_device != 1) return CMP_EINVAL;
+  if (n > ctx->members) return ids ? CMP_ENOTMEMBER : CMP_EINVAL;
+  std::vector<const uint8_t *> rm(n);
+  if (ids) {
+    int rc = check_ids_removable(ctx, ids, n);
+    if (rc != CMP_OK) return rc;
+  } else {
+    auto it = ctx->held.find(-1);
+    if (it == ctx->held.end() || (int64_t)it->second.size() < n) return CMP_ENOTMEMBER;
+  }
+  if (maps) {
+    for (int32_t i = 0; i < n; ++i) {
+      if (!maps[i]) return CMP_EINVAL;
+      rm[i] = maps[i];
+    }
+  } else {
+    // use the retained device rasters of the ids being removed
+    if (!ids || !ctx->o.retain_members) return CMP_EINVAL;
+    std::unordered_map<int64_t, size_t> used;
+    for (int32_t i = 0; i < n; ++i) {
+      auto &v = ctx->held.at(ids[i]);
+      const uint8_t *p = v[used[ids[i]]++];
+      if (!p) return CMP_EINVAL;  // that copy came from host memory
+      rm[i] = p;
+    }
+    maps_on_device = 1;
+  }
+  const bool need_max = (ctx->outs & CMP_MAX) != 0;
+  if (need_max && (!ctx->o.retain_members || ctx->host_members > 0)) return CMP_EUNSUPPORTED;
+
+  // Registry after the removal (committed only on success).
+  auto held = ctx->held;
+  for (int32_t i = 0; i < n; ++i) {
+    auto &v = held[ids ? ids[i] : -1];
+    // drop the copy with this raster if the registry knows it, else any copy
+    auto it = std::find(v.begin(), v.end(), rm[i]);
+    if (it == v.end()) it = v.begin();
+    v.erase(it);
+  }
+  std::vector<const uint8_t *> keep;
+  if (need_max) {
+    for (auto &kv : held)
+      for (auto *p : kv.second) keep.push_back(p);
+  }
+
+  CMP_TRY(set_device(ctx));
+  const uint32_t sub_outs = ctx->outs & (CMP_COUNT | CMP_SUM);
+  if (sub_outs) {
+    int rc;
+    if (maps_on_device) {
+      const uint8_t **d_tab = nullptr;
+      rc = upload_table(ctx, rm.data(), n, &d_tab);
+      if (rc == CMP_OK && composite_pass(ctx, d_tab, n, true, sub_outs, false) != hipSuccess)
+        rc = CMP_EDEVICE;
+    } else {
+      rc = ensure_staging(ctx);
+      if (rc != CMP_OK) return rc;
+      rc = stream_members(ctx, rm.data(), n, true, sub_outs);
+    }
+    if (rc != CMP_OK) {
+      ctx->poisoned = true;
+      return rc;
+    }
+  }
+  if (need_max) {
+    // max has no inverse: rebuild it from the members that remain
+    CMP_TRY(cmp::launch_fill(ctx->d_max, 0, ctx->npix, ctx->comp_s));
+    for (size_t k0 = 0; k0 < keep.size(); k0 += 65536) {
+      const int cnt = (int)std::min<size_t>(65536, keep.size() - k0);
+      const uint8_t **d_tab = nullptr;
+      int rc = upload_table(ctx, keep.data() + k0, cnt, &d_tab);
+      if (rc != CMP_OK) {
+        ctx->poisoned = true;
+        return rc;
+      }
+      CMP_TRY(composite_pass(ctx, d_tab, cnt, false, CMP_MAX, false));
+    }
+  }
+  for (auto it = held.begin(); it != held.end();) {
+    if (it->second.empty()) it = held.erase(it);
+    else ++it;
+  }
+  ctx->held.swap(held);
+  ctx->members -= n;
+  return CMP_OK;
+}
+
+int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0, int32_t w, int32_t h,
+                   void *dst, int64_t dst_pitch_bytes, int32_t dst_on_device) {
+  if (!ctx) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  if (which != CMP_COUNT && which != CMP_SUM && which != CMP_MAX) return CMP_EINVAL;
+  if (!(ctx->outs & which)) return CMP_EINVAL;
+  if (x0 < 0 || y0 < 0 || w < 0 || h < 0 || (int64_t)x0 + w > ctx->W || (int64_t)y0 + h > ctx->H)
+    return CMP_EINVAL;
+  if (dst_on_device != 0 && dst_on_device != 1) return CMP_EINVAL;
+  const int eb = elem_bytes(ctx, which);
+  if (w == 0 || h == 0) return CMP_OK;
+  if (!dst || dst_pitch_bytes < (int64_t)w * eb) return CMP_EINVAL;
+  const void *src = which == CMP_COUNT ? ctx->d_count
+                    : which == CMP_SUM ? (const void *)ctx->d_sum
+                                       : (const void *)ctx->d_max;
+  CMP_TRY(set_device(ctx));
+  CMP_TRY(hipStreamSynchronize(ctx->copy_s));
+  if (dst_on_device) {
+    CMP_TRY(cmp::launch_pack_window(src, eb, ctx->W, x0, y0, w, h, dst, dst_pitch_bytes, ctx->comp_s));
+  } else {
+    const uint8_t *s8 = static_cast<const uint8_t *>(src) + ((int64_t)y0 * ctx->W + x0) * eb;
+    CMP_TRY(hipMemcpy2DAsync(dst, (size_t)dst_pitch_bytes, s8, (size_t)ctx->W * eb, (size_t)w * eb,
+                             (size_t)h, hipMemcpyDeviceToHost, ctx->comp_s));
+  }
+  CMP_TRY(hipStreamSynchronize(ctx->comp_s));
+  return CMP_OK;
+}
+
+int composite_sync(cmp_ctx *ctx) {
+  if (!ctx) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  CMP_TRY(set_device(ctx));
+  CMP_TRY(hipStreamSynchronize(ctx->copy_s));
+  CMP_TRY(hipStreamSynchronize(ctx->comp_s));
+  CMP_TRY(harvest_timing(ctx));
+  return CMP_OK;
+}
+
+int composite_members(const cmp_ctx *ctx, int64_t *n_out) {
+  if (!ctx || !n_out) return CMP_EINVAL;
+  *n_out = ctx->members;
+  return CMP_OK;
+}
+
+int composite_device_buffer(cmp_ctx *ctx, uint32_t which, void **dev_ptr) {
+  if (!ctx || !dev_ptr) return CMP_EINVAL;
+  if (which != CMP_COUNT && which != CMP_SUM && which != CMP_MAX) return CMP_EINVAL;
+  if (!(ctx->outs & which)) return CMP_EINVAL;
+  *dev_ptr = which == CMP_COUNT ? ctx->d_count
+             : which == CMP_SUM ? (void *)ctx->d_sum
+                                : (void *)ctx->d_max;
+  return CMP_OK;
+}
+
+int composite_kernel_stats(cmp_ctx *ctx, int64_t *launches, double *total_ms, int32_t reset) {
+  if (!ctx || !launches || !total_ms) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  CMP_TRY(set_device(ctx));
+  CMP_TRY(harvest_timing(ctx));
+  *launches = ctx->timed_launches;
+  *total_ms = ctx->timed_ms;
+  if (reset) {
+    ctx->timed_launches = 0;
+    ctx->timed_ms = 0.0;
+  }
+  return CMP_OK;
+}
+
+const char *composite_strerror(int status) {
+  switch (status) {
+    case CMP_OK: return "ok";
+    case CMP_EINVAL: return "invalid argument";
+    case CMP_ENOMEM: return "out of memory";
+    case CMP_ERANGE: return "composite value could overflow its stored width";
+    case CMP_ENOTMEMBER: return "not a member of the working set";
+    case CMP_EUNSUPPORTED: return "unsupported in this configuration";
+    case CMP_EDEVICE: return "GPU unavailable or HIP failure";
+    case CMP_EBUSY: return "busy";
+    case CMP_ETIMEDOUT: return "timed out";
+    default: return "unknown status";
+  }
+}
+
+void composite_free(cmp_ctx *ctx) {
+  if (!ctx) return;
+  free_all(ctx);
+  delete ctx;
+}
+
+}  // extern "C"

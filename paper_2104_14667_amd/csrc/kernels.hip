@@ -1,0 +1,405 @@
+// Compositing kernels for gfx950 (CDNA4).
+//
+// The accumulation step of the paper (Section 4, Figures 2 and 3) folds each
+// input raster into the running composite.  Here one thread owns 16 adjacent
+// pixels and walks all members of the launch: per member it issues one 16-byte
+// load (a 64-lane wave reads 1 KiB of contiguous HBM), splits the 4 dwords
+// into 16-bit lanes with v_perm_b32 (bytes 0,2 and bytes 1,3 of each dword),
+// and updates packed 16-bit accumulators: count with min(x, 1), sum with x,
+// max with a packed max.  That is 10 VALU operations per dword for all three
+// outputs, about half of what the VALU can issue per dword at HBM rate, so
+// the kernel stays bound by memory.  After a group of at most 256 members the
+// lanes are widened to 32 bits, and at the end the composite is updated in
+// place once (read-modify-write), not ping-ponged: HIP buffers may be read and
+// written by one kernel, which is what forced the paper's image kernels to use
+// two accumulators.  No matrix cores: nothing here is a contraction.
+
+#include "kernels.h"
+
+namespace cmp {
+namespace {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t lanes_lo(uint32_t w) {  // bytes 0,2 -> u16 lanes
+  return __builtin_amdgcn_perm(0u, w, 0x0c020c00u);
+}
+__device__ __forceinline__ uint32_t lanes_hi(uint32_t w) {  // bytes 1,3 -> u16 lanes
+  return __builtin_amdgcn_perm(0u, w, 0x0c030c01u);
+}
+__device__ __forceinline__ u16x2 as16(uint32_t a) { return __builtin_bit_cast(u16x2, a); }
+__device__ __forceinline__ uint32_t as32(u16x2 a) { return __builtin_bit_cast(uint32_t, a); }
+// min(lane, 1) on both 16-bit lanes.  Written as the instruction itself:
+// the compiler otherwise rewrites min(x, 1) as (x != 0) and splits the lanes
+// into compares and selects, three times the work.
+__device__ __forceinline__ uint32_t pmin1(uint32_t a) {
+  uint32_t r;
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(a), "s"(0x00010001u));
+  return r;
+}
+__device__ __forceinline__ uint32_t pmax(uint32_t a, uint32_t b) {
+  return as32(__builtin_elementwise_max(as16(a), as16(b)));
+}
+__device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) { return as32(as16(a) + as16(b)); }
+__device__ __forceinline__ uint32_t psub(uint32_t a, uint32_t b) { return as32(as16(a) - as16(b)); }
+// Bytewise max of two dwords.
+__device__ __forceinline__ uint32_t bmax(uint32_t a, uint32_t b) {
+  const uint32_t l = pmax(lanes_lo(a), lanes_lo(b));
+  const uint32_t h = pmax(lanes_hi(a), lanes_hi(b));
+  return __builtin_amdgcn_perm(h, l, 0x06020400u);
+}
+
+typedef const __attribute__((address_space(1))) uint8_t gbyte;
+
+// 16 bytes from global memory at base + off, any alignment: one
+// global_load_dwordx4 with the base in SGPRs and a 32-bit VGPR offset.
+__device__ __forceinline__ uint4 ld16(const uint8_t *base, uint32_t off) {
+  uint4 v;
+  __builtin_memcpy(&v, (gbyte *)base + off, 16);
+  return v;
+}
+
+// Packed accumulators of 16 pixels.  Lane pair k*2 holds pixels 4k and 4k+2,
+// lane pair k*2+1 holds pixels 4k+1 and 4k+3 (low half first).
+template <uint32_t OUTS>
+struct Acc {
+  uint32_t c[8], s[8], m[8];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = s[k] = m[k] = 0u;
+  }
+  __device__ __forceinline__ void fold(const uint4 x) {
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t lo = lanes_lo(w[k]), hi = lanes_hi(w[k]);
+      if constexpr (OUTS & kCount) {
+        c[2 * k] += pmin1(lo);
+        c[2 * k + 1] += pmin1(hi);
+      }
+      if constexpr (OUTS & kSum) {
+        s[2 * k] += lo;
+        s[2 * k + 1] += hi;
+      }
+      if constexpr (OUTS & kMax) {
+        m[2 * k] = pmax(m[2 * k], lo);
+        m[2 * k + 1] = pmax(m[2 * k + 1], hi);
+      }
+    }
+  }
+};
+
+// Value of pixel j (0..15) held in packed lanes a[8].
+__device__ __forceinline__ uint32_t lane_px(const uint32_t *a, int j) {
+  const int k = j >> 2, r = j & 3;
+  const uint32_t d = a[2 * k + (r & 1)];
+  return (r & 2) ? (d >> 16) : (d & 0xffffu);
+}
+
+template <int UNROLL, uint32_t OUTS>
+__device__ __forceinline__ void fold_members(const uint8_t *const *__restrict__ tab,
+                                             int i0, int i1, uint32_t off, Acc<OUTS> &a) {
+  int i = i0;
+  for (; i + UNROLL <= i1; i += UNROLL) {
+    uint4 x[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) x[u] = ld16(tab[i + u], off);
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) a.fold(x[u]);
+  }
+  for (; i < i1; ++i) a.fold(ld16(tab[i], off));
+}
+
+// Read-modify-write of 16 composite pixels starting at pixel index p.
+template <uint32_t OUTS, bool SUB, bool C16>
+__device__ __forceinline__ void update16(const uint32_t *cnt, const uint32_t *sm,
+                                         const uint32_t *mx8, uint32_t p,
+                                         void *__restrict__ count, uint32_t *__restrict__ sum,
+                                         uint8_t *__restrict__ mx) {
+  if constexpr (OUTS & kCount) {
+    if constexpr (C16) {
+      uint4 *dst = reinterpret_cast<uint4 *>(static_cast<uint16_t *>(count) + p);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        uint4 o = dst[q];
+        uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t nw = cnt[8 * q + 2 * k] | (cnt[8 * q + 2 * k + 1] << 16);
+          ow[k] = SUB ? psub(ow[k], nw) : padd(ow[k], nw);
+        }
+        dst[q] = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+      }
+    } else {
+      uint4 *dst = reinterpret_cast<uint4 *>(static_cast<uint32_t *>(count) + p);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint4 o = dst[q];
+        if (SUB) {
+          o.x -= cnt[4 * q]; o.y -= cnt[4 * q + 1]; o.z -= cnt[4 * q + 2]; o.w -= cnt[4 * q + 3];
+        } else {
+          o.x += cnt[4 * q]; o.y += cnt[4 * q + 1]; o.z += cnt[4 * q + 2]; o.w += cnt[4 * q + 3];
+        }
+        dst[q] = o;
+      }
+    }
+  }
+  if constexpr (OUTS & kSum) {
+    uint4 *dst = reinterpret_cast<uint4 *>(sum + p);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint4 o = dst[q];
+      if (SUB) {
+        o.x -= sm[4 * q]; o.y -= sm[4 * q + 1]; o.z -= sm[4 * q + 2]; o.w -= sm[4 * q + 3];
+      } else {
+        o.x += sm[4 * q]; o.y += sm[4 * q + 1]; o.z += sm[4 * q + 2]; o.w += sm[4 * q + 3];
+      }
+      dst[q] = o;
+    }
+  }
+  if constexpr ((OUTS & kMax) && !SUB) {
+    uint4 *dst = reinterpret_cast<uint4 *>(mx + p);
+    uint4 o = *dst;
+    o.x = bmax(o.x, mx8[0]); o.y = bmax(o.y, mx8[1]); o.z = bmax(o.z, mx8[2]); o.w = bmax(o.w, mx8[3]);
+    *dst = o;
+  }
+}
+
+// Output position of 16-pixel vector v: linear (identity) or tiled.
+// Pixel indices fit 32 bits: the library refuses rasters of 2^32 pixels or more.
+struct LinearMap {
+  __device__ __forceinline__ bool pixel(uint32_t v, uint32_t &p) const {
+    p = v * 16u;
+    return true;
+  }
+};
+struct TiledMap {
+  uint32_t W, H, tw, th, ntx;
+  __device__ __forceinline__ bool pixel(uint32_t v, uint32_t &p) const {
+    const uint32_t vpr = tw >> 4;                 // vectors per tile row
+    const uint32_t per_tile = vpr * th;
+    const uint32_t tile = v / per_tile;
+    const uint32_t in = v - tile * per_tile;
+    const uint32_t r = in / vpr, c = in - r * vpr;
+    const uint32_t ty = tile / ntx, tx = tile - ty * ntx;
+    const uint32_t y = ty * th + r, x = tx * tw + 16u * c;
+    p = y * W + x;
+    return y < H && x < W;
+  }
+};
+
+template <uint32_t OUTS, bool SUB, bool C16, bool MULTI, class Map>
+__global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restrict__ tab,
+                                                   int n, uint32_t nvec, Map map,
+                                                   void *__restrict__ count,
+                                                   uint32_t *__restrict__ sum,
+                                                   uint8_t *__restrict__ mx) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec) return;
+  uint32_t p;
+  if (!map.pixel(v, p)) return;
+  const uint32_t off = v * 16u;
+  constexpr int UNROLL = (OUTS == kCount) ? 8 : 4;
+
+  Acc<OUTS> a;
+  a.zero();
+  uint32_t cnt[16], sm[16], mx8[4];
+  if constexpr (MULTI) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) cnt[j] = sm[j] = 0u;
+    for (int g0 = 0; g0 < n; g0 += kGroup) {
+      const int g1 = min(n, g0 + kGroup);
+      fold_members<UNROLL>(tab, g0, g1, off, a);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if constexpr (OUTS & kCount) cnt[j] += lane_px(a.c, j);
+        if constexpr (OUTS & kSum) sm[j] += lane_px(a.s, j);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a.c[k] = a.s[k] = 0u;
+    }
+  } else {
+    fold_members<UNROLL>(tab, 0, n, off, a);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      cnt[j] = lane_px(a.c, j);
+      sm[j] = lane_px(a.s, j);
+    }
+  }
+  if constexpr (OUTS & kMax) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mx8[k] = __builtin_amdgcn_perm(a.m[2 * k + 1], a.m[2 * k], 0x06020400u);
+  }
+  update16<OUTS, SUB, C16>(cnt, sm, mx8, p, count, sum, mx);
+}
+
+// Pixels [p0, npix) that do not fill a 16-pixel vector: one thread per pixel.
+template <uint32_t OUTS, bool SUB, bool C16>
+__global__ __launch_bounds__(64) void k_composite_tail(const uint8_t *const *__restrict__ tab,
+                                                       int n, int64_t p0, int64_t npix,
+                                                       void *__restrict__ count,
+                                                       uint32_t *__restrict__ sum,
+                                                       uint8_t *__restrict__ mx) {
+  const int64_t p = p0 + threadIdx.x;
+  if (p >= npix) return;
+  uint32_t c = 0, s = 0, m = 0;
+  for (int i = 0; i < n; ++i) {
+    const uint32_t x = tab[i][p];
+    c += x != 0u;
+    s += x;
+    m = x > m ? x : m;
+  }
+  if constexpr (OUTS & kCount) {
+    if constexpr (C16) {
+      uint16_t *d = static_cast<uint16_t *>(count) + p;
+      *d = (uint16_t)(SUB ? *d - c : *d + c);
+    } else {
+      uint32_t *d = static_cast<uint32_t *>(count) + p;
+      *d = SUB ? *d - c : *d + c;
+    }
+  }
+  if constexpr (OUTS & kSum) sum[p] = SUB ? sum[p] - s : sum[p] + s;
+  if constexpr ((OUTS & kMax) && !SUB) mx[p] = (uint8_t)(m > mx[p] ? m : mx[p]);
+}
+
+template <uint32_t OUTS, bool SUB, bool C16, class Map>
+hipError_t go(const uint8_t *const *tab, int n, int64_t nvec, const Map &map,
+              const Outputs &o, hipStream_t s) {
+  if (nvec <= 0) return hipSuccess;
+  if (nvec >= (int64_t(1) << 28)) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)((nvec + 255) / 256);
+  if (n > kGroup)
+    k_composite<OUTS, SUB, C16, true, Map><<<blocks, 256, 0, s>>>(tab, n, (uint32_t)nvec, map, o.count, o.sum, o.max);
+  else
+    k_composite<OUTS, SUB, C16, false, Map><<<blocks, 256, 0, s>>>(tab, n, (uint32_t)nvec, map, o.count, o.sum, o.max);
+  return hipGetLastError();
+}
+
+template <uint32_t OUTS, bool SUB, bool C16>
+hipError_t go_tail(const uint8_t *const *tab, int n, int64_t p0, int64_t npix,
+                   const Outputs &o, hipStream_t s) {
+  if (npix <= p0) return hipSuccess;
+  k_composite_tail<OUTS, SUB, C16><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum, o.max);
+  return hipGetLastError();
+}
+
+template <uint32_t O, bool S, bool C>
+hipError_t run_linear(const uint8_t *const *tab, int n, int64_t npix, const Outputs &o,
+                      hipStream_t s) {
+  const int64_t nvec = npix / 16;
+  hipError_t e = go<O, S, C>(tab, n, nvec, LinearMap{}, o, s);
+  if (e != hipSuccess) return e;
+  return go_tail<O, S, C>(tab, n, nvec * 16, npix, o, s);
+}
+
+template <uint32_t O, bool S, bool C>
+hipError_t run_tiled(const uint8_t *const *tab, int n, int64_t nvec, const TiledMap &map,
+                     const Outputs &o, hipStream_t s) {
+  return go<O, S, C>(tab, n, nvec, map, o, s);
+}
+
+// Runtime (outs, sub, count16) -> template instance of FN<O, S, C>(ARGS).
+#define CMP_DISPATCH(FN, outs, sub, c16, ...)                                   \
+  do {                                                                          \
+    switch (outs) {                                                             \
+      CMP_DISPATCH_CASE(FN, 1, sub, c16, __VA_ARGS__)                           \
+      CMP_DISPATCH_CASE(FN, 2, sub, c16, __VA_ARGS__)                           \
+      CMP_DISPATCH_CASE(FN, 3, sub, c16, __VA_ARGS__)                           \
+      CMP_DISPATCH_CASE(FN, 4, sub, c16, __VA_ARGS__)                           \
+      CMP_DISPATCH_CASE(FN, 5, sub, c16, __VA_ARGS__)                           \
+      CMP_DISPATCH_CASE(FN, 6, sub, c16, __VA_ARGS__)                           \
+      CMP_DISPATCH_CASE(FN, 7, sub, c16, __VA_ARGS__)                           \
+      default:                                                                  \
+        return hipErrorInvalidValue;                                            \
+    }                                                                           \
+  } while (0)
+#define CMP_DISPATCH_CASE(FN, O, sub, c16, ...)                                 \
+  case O:                                                                       \
+    if (sub)                                                                    \
+      return c16 ? FN<O, true, true>(__VA_ARGS__) : FN<O, true, false>(__VA_ARGS__); \
+    return c16 ? FN<O, false, true>(__VA_ARGS__) : FN<O, false, false>(__VA_ARGS__);
+
+__global__ __launch_bounds__(256) void k_repack(const uint8_t *__restrict__ src, int64_t src_stride,
+                                                uint8_t *__restrict__ dst, int64_t dst_stride,
+                                                uint32_t nvec, TiledMap map) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec) return;
+  const int64_t i = blockIdx.y;
+  uint32_t p;
+  uint4 x = make_uint4(0u, 0u, 0u, 0u);
+  if (map.pixel(v, p)) x = ld16(src + i * src_stride, p);
+  *reinterpret_cast<uint4 *>(dst + i * dst_stride + (int64_t)v * 16) = x;
+}
+
+__global__ __launch_bounds__(256) void k_fill(uint8_t *__restrict__ p, uint32_t word,
+                                              int64_t nvec, int64_t bytes) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nvec) reinterpret_cast<uint4 *>(p)[v] = make_uint4(word, word, word, word);
+  if (v == 0)
+    for (int64_t b = nvec * 16; b < bytes; ++b) p[b] = (uint8_t)word;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pack(const T *__restrict__ src, int32_t W, int32_t x0,
+                                              int32_t y0, int32_t w, int32_t h,
+                                              uint8_t *__restrict__ dst, int64_t dst_pitch) {
+  const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t y = blockIdx.y;
+  if (x >= w || y >= h) return;
+  reinterpret_cast<T *>(dst + (int64_t)y * dst_pitch)[x] = src[(int64_t)(y0 + y) * W + x0 + x];
+}
+
+}  // namespace
+
+hipError_t launch_composite_linear(const uint8_t *const *d_tab, int n, int64_t npix,
+                                   const Outputs &o, uint32_t outs, bool sub, hipStream_t s) {
+  if (n <= 0 || npix <= 0) return hipSuccess;
+  CMP_DISPATCH(run_linear, outs, sub, o.count16, d_tab, n, npix, o, s);
+}
+
+hipError_t launch_composite_tiled(const uint8_t *const *d_tab, int n, const Tiling &t,
+                                  const Outputs &o, uint32_t outs, bool sub, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (t.W % 16 || t.tw % 16) return hipErrorInvalidValue;
+  const TiledMap map{(uint32_t)t.W, (uint32_t)t.H, (uint32_t)t.tw, (uint32_t)t.th, (uint32_t)t.ntx()};
+  const int64_t nvec = t.plane() / 16;
+  CMP_DISPATCH(run_tiled, outs, sub, o.count16, d_tab, n, nvec, map, o, s);
+}
+
+hipError_t launch_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
+                               int64_t dst_stride, int n, const Tiling &t, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (t.W % 16 || t.tw % 16 || n > 65535) return hipErrorInvalidValue;
+  const TiledMap map{(uint32_t)t.W, (uint32_t)t.H, (uint32_t)t.tw, (uint32_t)t.th, (uint32_t)t.ntx()};
+  const int64_t nvec = t.plane() / 16;
+  if (nvec >= (int64_t(1) << 28)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((nvec + 255) / 256), (unsigned)n);
+  k_repack<<<grid, 256, 0, s>>>(src, src_stride, dst, dst_stride, (uint32_t)nvec, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void *p, uint8_t value, int64_t bytes, hipStream_t s) {
+  if (bytes <= 0) return hipSuccess;
+  const uint32_t word = 0x01010101u * value;
+  const int64_t nvec = bytes / 16;
+  const int64_t blocks = nvec > 0 ? (nvec + 255) / 256 : 1;
+  k_fill<<<(unsigned)blocks, 256, 0, s>>>(static_cast<uint8_t *>(p), word, nvec, bytes);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_window(const void *src, int elem, int32_t W, int32_t x0, int32_t y0,
+                              int32_t w, int32_t h, void *dst, int64_t dst_pitch,
+                              hipStream_t s) {
+  if (w <= 0 || h <= 0) return hipSuccess;
+  dim3 grid((unsigned)((w + 255) / 256), (unsigned)h);
+  uint8_t *d = static_cast<uint8_t *>(dst);
+  switch (elem) {
+    case 1: k_pack<uint8_t><<<grid, 256, 0, s>>>(static_cast<const uint8_t *>(src), W, x0, y0, w, h, d, dst_pitch); break;
+    case 2: k_pack<uint16_t><<<grid, 256, 0, s>>>(static_cast<const uint16_t *>(src), W, x0, y0, w, h, d, dst_pitch); break;
+    case 4: k_pack<uint32_t><<<grid, 256, 0, s>>>(static_cast<const uint32_t *>(src), W, x0, y0, w, h, d, dst_pitch); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cmp

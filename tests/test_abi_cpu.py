@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports what include/composite.h declares (CPU).
+
+No compute calls: this box has no GPU."""
+
+import ctypes as C
+
+import pytest
+import torch
+
+from paper_2104_14667_amd import composite as cb
+
+
+def test_header_declares_the_boundary():
+    names = cb.header_functions()
+    for must in ("composite_init", "composite_add", "composite_add_device",
+                 "composite_remove", "composite_read", "composite_free"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(cb.LIB_PATH)
+    missing = [n for n in cb.header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding wraps every one of them under the same name
+    for n in cb.header_functions():
+        assert hasattr(cb, n) or n in cb._SIGS, n
+
+
+def test_strerror_is_total():
+    for s in range(-10, 2):
+        assert isinstance(cb.composite_strerror(s), str) and cb.composite_strerror(s)
+    assert cb.composite_strerror(cb.CMP_ERANGE).startswith("composite value")
+
+
+def test_default_opts():
+    o = cb.composite_default_opts()
+    assert (o.nbuf, o.chunk_depth, o.layout, o.tile_w, o.tile_h) == (2, 8, cb.CMP_LINEAR, 64, 64)
+    assert o.copy_stream is None and o.compute_stream is None
+    assert C.sizeof(cb.cmp_opts) == 72
+
+
+def test_argument_checks_before_any_device_call():
+    h = C.c_void_p()
+    assert cb.lib.composite_init(None, 4, 4, 1, 32, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_init(C.byref(h), 0, 4, 1, 32, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_init(C.byref(h), 4, 4, 0, 32, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_init(C.byref(h), 4, 4, 8, 32, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_init(C.byref(h), 4, 4, 1, 8, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_init(C.byref(h), 1 << 20, 1 << 12, 1, 32, None) == cb.CMP_EINVAL
+    o = cb.composite_default_opts()
+    o.nbuf = 3
+    assert cb.lib.composite_init(C.byref(h), 4, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
+    o = cb.composite_default_opts()
+    o.layout = cb.CMP_TILED
+    assert cb.lib.composite_init(C.byref(h), 24, 4, 1, 32, C.byref(o)) == cb.CMP_EUNSUPPORTED
+    o = cb.composite_default_opts()
+    o.reserved[2] = 1
+    assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
+    for fn in ("composite_clear", "composite_sync"):
+        assert getattr(cb.lib, fn)(None) == cb.CMP_EINVAL
+    cb.lib.composite_free(None)   # NULL-safe
+
+
+@pytest.mark.skipif(torch.cuda.device_count() > 0, reason="a GPU is present")
+def test_init_without_gpu_reports_edevice():
+    h = C.c_void_p()
+    assert cb.lib.composite_init(C.byref(h), 16, 16, 1, 32, None) == cb.CMP_EDEVICE
+    assert h.value is None
