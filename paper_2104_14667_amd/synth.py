@@ -126,7 +126,7 @@ def sha256(a: np.ndarray) -> str:
 # sizes it is specified at; ``scaled`` returns the same recipe at other sizes
 # for tests that must finish on the CPU.
 
-@dataclass
+@dataclass(frozen=True)
 class Ensemble:
     """N members of W x H from one shared elevation field."""
     name: str
