@@ -55,6 +55,12 @@ enum cmp_status {
 /* Output selection bits (composite_init `outputs`, composite_read `which`). */
 enum cmp_outputs { CMP_COUNT = 1, CMP_SUM = 2, CMP_MAX = 4 };
 
+/* Kind of memory composite_read writes to.  CMP_DST_HOST: any host memory;
+ * the data passes through pinned buffers of the library.  CMP_DST_PINNED:
+ * page-locked host memory the copy engine writes directly.  CMP_DST_DEVICE:
+ * device memory, written by a kernel. */
+enum cmp_dst_kind { CMP_DST_HOST = 0, CMP_DST_DEVICE = 1, CMP_DST_PINNED = 2 };
+
 /* Layout of staged members on the device.  CMP_LINEAR reads the staged
  * rasters row-major as uploaded (the paper's buffers).  CMP_TILED first
  * repacks each staged raster into tiles of tile_w bytes x tile_h rows, stored
@@ -87,7 +93,13 @@ typedef struct cmp_opts {
   int32_t profile;        /* 1: time every compositing kernel with HIP events
                              on the compute stream (composite_kernel_stats).
                              Default 0 */
-  int32_t reserved[5];    /* must be zero */
+  int32_t pageable_host;  /* 0: host rasters given to composite_add/remove are
+                             page-locked (hipHostMalloc, torch pin_memory) and
+                             the copy engine reads them directly.  1: they may
+                             be ordinary pageable memory; the host first copies
+                             each chunk into a pinned bounce buffer of the
+                             library (one per staging slot).  Default 0 */
+  int32_t reserved[4];    /* must be zero */
 } cmp_opts;
 
 typedef struct cmp_ctx cmp_ctx;
@@ -97,7 +109,8 @@ void composite_default_opts(cmp_opts *opts);
 
 /* Creates a context holding a cleared W x H composite on the device.
  * outputs: non-empty OR of cmp_outputs.  count_bits: 16 or 32 (ignored
- * without CMP_COUNT).  opts: NULL for defaults.  W, H >= 1 and W*H < 2^40.
+ * without CMP_COUNT).  opts: NULL for defaults.  W, H >= 1 and
+ * W*H <= 2^32 - 16 (larger rasters are split spatially by the caller).
  * Returns CMP_EDEVICE when no GPU is usable, CMP_ENOMEM when the composite
  * does not fit.  On success *out owns the context (composite_free). */
 int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs,
@@ -107,9 +120,10 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs,
 int composite_clear(cmp_ctx *ctx);
 
 /* Streams n members from host memory into the composite.
- * host_maps[i]: W*H bytes, row-major.  Pinned memory (hipHostMalloc or
- * torch pin_memory) is uploaded by the copy engine at full link rate; pageable
- * memory works but is staged by the runtime.  Members are uploaded in chunks of
+ * host_maps[i]: W*H bytes, row-major, page-locked unless opts.pageable_host
+ * is set (then the host first copies each chunk into a pinned bounce buffer,
+ * the counterpart of the paper's first implementation method, Section 4).
+ * Members are uploaded in chunks of
  * chunk_depth into nbuf staging slots on the copy stream; the compute stream
  * waits for each chunk's upload and the copy stream waits for a slot to be
  * released by the kernel that read it, so no host synchronisation happens
@@ -142,12 +156,13 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps,
 /* Copies the window [x0, x0+w) x [y0, y0+h) of one output (`which` is exactly
  * one of CMP_COUNT, CMP_SUM, CMP_MAX and must have been selected at init) to
  * dst, row by row with dst_pitch_bytes between rows (>= w * element size:
- * 2 or 4 bytes for count, 4 for sum, 1 for max).  dst is host memory if
- * dst_on_device == 0, else device memory.  Waits for all work enqueued on the
- * context before it and returns when dst holds the data. */
+ * 2 or 4 bytes for count, 4 for sum, 1 for max).  dst_kind (cmp_dst_kind)
+ * says what memory dst is.  Waits for all work enqueued on the context before
+ * it and returns when dst holds the data.  The result is the composite of the
+ * members, restricted to the window (the retrieval of results, Section 1). */
 int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0,
                    int32_t w, int32_t h, void *dst, int64_t dst_pitch_bytes,
-                   int32_t dst_on_device);
+                   int32_t dst_kind);
 
 /* Waits for all work enqueued on the context. */
 int composite_sync(cmp_ctx *ctx);

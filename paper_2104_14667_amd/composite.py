@@ -23,6 +23,7 @@ CMP_OK, CMP_EINVAL, CMP_ENOMEM, CMP_ERANGE, CMP_ENOTMEMBER = 0, -1, -2, -3, -4
 CMP_EUNSUPPORTED, CMP_EDEVICE, CMP_EBUSY, CMP_ETIMEDOUT = -5, -6, -7, -8
 CMP_COUNT, CMP_SUM, CMP_MAX = 1, 2, 4
 CMP_LINEAR, CMP_TILED = 0, 1
+CMP_DST_HOST, CMP_DST_DEVICE, CMP_DST_PINNED = 0, 1, 2
 OUTPUT_BITS = {"count": CMP_COUNT, "sum": CMP_SUM, "max": CMP_MAX}
 
 
@@ -31,7 +32,8 @@ class cmp_opts(C.Structure):
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("device", C.c_int32),
                 ("copy_stream", C.c_void_p), ("compute_stream", C.c_void_p),
                 ("retain_members", C.c_int32), ("debug_poison", C.c_int32),
-                ("profile", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("profile", C.c_int32), ("pageable_host", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class CompositeError(RuntimeError):
@@ -153,9 +155,9 @@ def composite_remove(ctx: int, maps: Optional[Sequence], ids=None, n: Optional[i
 
 
 def composite_read(ctx: int, which: int, x0: int, y0: int, w: int, h: int, dst,
-                   dst_pitch_bytes: int, dst_on_device: bool = False) -> None:
+                   dst_pitch_bytes: int, dst_kind: int = CMP_DST_HOST) -> None:
     _check(lib.composite_read(ctx, int(which), int(x0), int(y0), int(w), int(h), _ptr(dst),
-                              int(dst_pitch_bytes), int(bool(dst_on_device))), "composite_read")
+                              int(dst_pitch_bytes), int(dst_kind)), "composite_read")
 
 
 def composite_sync(ctx: int) -> None:
@@ -250,15 +252,18 @@ class Composite:
             return np.uint16 if self.count_bits == 16 else np.uint32
         return _DT[OUTPUT_BITS[name]]
 
-    def read(self, name: str, window=None, out: Optional[np.ndarray] = None) -> np.ndarray:
-        """Window (x0, y0, w, h) of one output into host memory (numpy)."""
+    def read(self, name: str, window=None, out: Optional[np.ndarray] = None,
+             pinned: bool = False) -> np.ndarray:
+        """Window (x0, y0, w, h) of one output into host memory (numpy); pass
+        pinned=True when `out` views page-locked memory."""
         x0, y0, w, h = window if window is not None else (0, 0, self.W, self.H)
         dt = self.dtype(name)
         if out is None:
             out = np.empty((h, w), dtype=dt)
         if out.dtype != dt or out.shape != (h, w) or not out.flags.c_contiguous:
             raise ValueError("out must be a C-contiguous (h, w) array of the output's dtype")
-        composite_read(self.ctx, OUTPUT_BITS[name], x0, y0, w, h, out, w * out.itemsize)
+        composite_read(self.ctx, OUTPUT_BITS[name], x0, y0, w, h, out, w * out.itemsize,
+                       CMP_DST_PINNED if pinned else CMP_DST_HOST)
         return out
 
     def read_device(self, name: str, dst, window=None, pitch_bytes: Optional[int] = None):
@@ -266,7 +271,7 @@ class Composite:
         x0, y0, w, h = window if window is not None else (0, 0, self.W, self.H)
         eb = np.dtype(self.dtype(name)).itemsize
         composite_read(self.ctx, OUTPUT_BITS[name], x0, y0, w, h, dst,
-                       pitch_bytes if pitch_bytes is not None else w * eb, True)
+                       pitch_bytes if pitch_bytes is not None else w * eb, CMP_DST_DEVICE)
 
     def device_buffer(self, name: str) -> int:
         return composite_device_buffer(self.ctx, OUTPUT_BITS[name])

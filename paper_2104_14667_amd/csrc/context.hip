@@ -69,6 +69,15 @@ struct cmp_ctx {
   int tab_half = 0;
   hipEvent_t ev_tab[2] = {nullptr, nullptr};
 
+  // Pinned bounce buffers for uploads from pageable host memory, and pinned
+  // staging for reads into pageable host memory (the library never relies on
+  // the runtime's own handling of pageable memory).
+  uint8_t *h_bounce[2] = {nullptr, nullptr};
+  hipEvent_t ev_bounce[2] = {nullptr, nullptr};
+  uint8_t *h_read[2] = {nullptr, nullptr};
+  int64_t read_cap = 0;
+  hipEvent_t ev_read[2] = {nullptr, nullptr};
+
   // Registry: members with multiplicity (anonymous ones under id -1) and,
   // with retain_members, their device pointers.
   int64_t members = 0;
@@ -122,6 +131,10 @@ void free_all(cmp_ctx *ctx) {
     hipFree(ctx->d_slot_tab[i]);
     hipFree(ctx->d_tab[i]);
     if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
+    if (ctx->h_bounce[i]) hipHostFree(ctx->h_bounce[i]);
+    if (ctx->h_read[i]) hipHostFree(ctx->h_read[i]);
+    if (ctx->ev_bounce[i]) hipEventDestroy(ctx->ev_bounce[i]);
+    if (ctx->ev_read[i]) hipEventDestroy(ctx->ev_read[i]);
     if (ctx->ev_copied[i]) hipEventDestroy(ctx->ev_copied[i]);
     if (ctx->ev_free[i]) hipEventDestroy(ctx->ev_free[i]);
     if (ctx->ev_tab[i]) hipEventDestroy(ctx->ev_tab[i]);
@@ -266,6 +279,21 @@ int upload_table(cmp_ctx *ctx, const uint8_t *const *ptrs, int64_t n, const uint
   return CMP_OK;
 }
 
+int ensure_bounce(cmp_ctx *ctx) {
+  if (ctx->h_bounce[0]) return CMP_OK;
+  const int64_t bytes = ctx->stage_stride * ctx->o.chunk_depth;
+  for (int i = 0; i < ctx->o.nbuf; ++i) {
+    if (hipHostMalloc((void **)&ctx->h_bounce[i], bytes, hipHostMallocDefault) != hipSuccess) {
+      for (int j = 0; j < 2; ++j) {
+        if (ctx->h_bounce[j]) hipHostFree(ctx->h_bounce[j]);
+        ctx->h_bounce[j] = nullptr;
+      }
+      return CMP_ENOMEM;
+    }
+  }
+  return CMP_OK;
+}
+
 // Streams n host rasters through the staging slots with op add or sub.
 int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub, uint32_t outs) {
   int rc = ensure_staging(ctx);
@@ -274,20 +302,38 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
   const int nb = ctx->o.nbuf;
   const bool tiled = ctx->o.layout == CMP_TILED;
   const int64_t plane = ctx->npix;
+  const bool pinned = ctx->o.pageable_host == 0;
+  if (!pinned) {
+    // Pageable sources are first copied by the host into pinned bounce
+    // buffers (one per slot), then uploaded by the copy engine.
+    rc = ensure_bounce(ctx);
+    if (rc != CMP_OK) return rc;
+  }
   for (int32_t k0 = 0, k = 0; k0 < n; k0 += d, ++k) {
     const int slot = k % nb;
     const int cnt = std::min<int32_t>(d, n - k0);
     CMP_TRY(hipStreamWaitEvent(ctx->copy_s, ctx->ev_free[slot], 0));
-    // Upload: runs of host rasters that are contiguous and staged contiguously
-    // go as one copy.
-    int j = 0;
-    while (j < cnt) {
-      int r = j + 1;
-      if (ctx->stage_stride == plane)
-        while (r < cnt && maps[k0 + r] == maps[k0 + r - 1] + plane) ++r;
-      CMP_TRY(hipMemcpyAsync(ctx->d_stage[slot] + j * ctx->stage_stride, maps[k0 + j],
-                             (size_t)(plane * (r - j)), hipMemcpyHostToDevice, ctx->copy_s));
-      j = r;
+    if (pinned) {
+      // Runs of host rasters that are contiguous, and staged contiguously, go
+      // as one copy.
+      int j = 0;
+      while (j < cnt) {
+        int r = j + 1;
+        if (ctx->stage_stride == plane)
+          while (r < cnt && maps[k0 + r] == maps[k0 + r - 1] + plane) ++r;
+        CMP_TRY(hipMemcpyAsync(ctx->d_stage[slot] + j * ctx->stage_stride, maps[k0 + j],
+                               (size_t)(plane * (r - j)), hipMemcpyHostToDevice, ctx->copy_s));
+        j = r;
+      }
+    } else {
+      // the bounce buffer of this slot may still feed its previous upload
+      CMP_TRY(hipEventSynchronize(ctx->ev_bounce[slot]));
+      for (int j = 0; j < cnt; ++j)
+        std::memcpy(ctx->h_bounce[slot] + j * ctx->stage_stride, maps[k0 + j], (size_t)plane);
+      CMP_TRY(hipMemcpyAsync(ctx->d_stage[slot], ctx->h_bounce[slot],
+                             (size_t)((cnt - 1) * ctx->stage_stride + plane), hipMemcpyHostToDevice,
+                             ctx->copy_s));
+      CMP_TRY(hipEventRecord(ctx->ev_bounce[slot], ctx->copy_s));
     }
     CMP_TRY(hipEventRecord(ctx->ev_copied[slot], ctx->copy_s));
     CMP_TRY(hipStreamWaitEvent(ctx->comp_s, ctx->ev_copied[slot], 0));
@@ -394,11 +440,15 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
     for (int i = 0; i < 2 && ok; ++i) {
       ok = hipEventCreateWithFlags(&ctx->ev_copied[i], hipEventDisableTiming) == hipSuccess &&
            hipEventCreateWithFlags(&ctx->ev_free[i], hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&ctx->ev_tab[i], hipEventDisableTiming) == hipSuccess;
+           hipEventCreateWithFlags(&ctx->ev_tab[i], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&ctx->ev_bounce[i], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&ctx->ev_read[i], hipEventDisableTiming) == hipSuccess;
       // every event starts recorded, so the first wait on it is satisfied
       ok = ok && hipEventRecord(ctx->ev_free[i], ctx->comp_s) == hipSuccess &&
            hipEventRecord(ctx->ev_copied[i], ctx->copy_s) == hipSuccess &&
-           hipEventRecord(ctx->ev_tab[i], ctx->comp_s) == hipSuccess;
+           hipEventRecord(ctx->ev_tab[i], ctx->comp_s) == hipSuccess &&
+           hipEventRecord(ctx->ev_bounce[i], ctx->copy_s) == hipSuccess &&
+           hipEventRecord(ctx->ev_read[i], ctx->comp_s) == hipSuccess;
     }
     if (!ok || hipEventCreateWithFlags(&ctx->ev_host_done, hipEventDisableTiming) != hipSuccess) break;
     rc = CMP_ENOMEM;
@@ -581,14 +631,15 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *id
 }
 
 int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0, int32_t w, int32_t h,
-                   void *dst, int64_t dst_pitch_bytes, int32_t dst_on_device) {
+                   void *dst, int64_t dst_pitch_bytes, int32_t dst_kind) {
   if (!ctx) return CMP_EINVAL;
   if (ctx->poisoned) return CMP_EDEVICE;
   if (which != CMP_COUNT && which != CMP_SUM && which != CMP_MAX) return CMP_EINVAL;
   if (!(ctx->outs & which)) return CMP_EINVAL;
   if (x0 < 0 || y0 < 0 || w < 0 || h < 0 || (int64_t)x0 + w > ctx->W || (int64_t)y0 + h > ctx->H)
     return CMP_EINVAL;
-  if (dst_on_device != 0 && dst_on_device != 1) return CMP_EINVAL;
+  if (dst_kind != CMP_DST_HOST && dst_kind != CMP_DST_DEVICE && dst_kind != CMP_DST_PINNED)
+    return CMP_EINVAL;
   const int eb = elem_bytes(ctx, which);
   if (w == 0 || h == 0) return CMP_OK;
   if (!dst || dst_pitch_bytes < (int64_t)w * eb) return CMP_EINVAL;
@@ -597,14 +648,62 @@ int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0, int32_t
                                        : (const void *)ctx->d_max;
   CMP_TRY(set_device(ctx));
   CMP_TRY(hipStreamSynchronize(ctx->copy_s));
-  if (dst_on_device) {
+  if (dst_kind == CMP_DST_DEVICE) {
     CMP_TRY(cmp::launch_pack_window(src, eb, ctx->W, x0, y0, w, h, dst, dst_pitch_bytes, ctx->comp_s));
-  } else {
-    const uint8_t *s8 = static_cast<const uint8_t *>(src) + ((int64_t)y0 * ctx->W + x0) * eb;
-    CMP_TRY(hipMemcpy2DAsync(dst, (size_t)dst_pitch_bytes, s8, (size_t)ctx->W * eb, (size_t)w * eb,
-                             (size_t)h, hipMemcpyDeviceToHost, ctx->comp_s));
+    CMP_TRY(hipStreamSynchronize(ctx->comp_s));
+    return CMP_OK;
   }
-  CMP_TRY(hipStreamSynchronize(ctx->comp_s));
+  const uint8_t *s8 = static_cast<const uint8_t *>(src) + ((int64_t)y0 * ctx->W + x0) * eb;
+  const size_t spitch = (size_t)ctx->W * eb, row = (size_t)w * eb;
+  if (dst_kind == CMP_DST_PINNED) {
+    CMP_TRY(hipMemcpy2DAsync(dst, (size_t)dst_pitch_bytes, s8, spitch, row, (size_t)h,
+                             hipMemcpyDeviceToHost, ctx->comp_s));
+    CMP_TRY(hipStreamSynchronize(ctx->comp_s));
+    return CMP_OK;
+  }
+  // Pageable destination: bands of rows go through two pinned buffers; the
+  // copy engine fills one while the host empties the other.
+  const int64_t want = std::max<int64_t>(16 << 20, (int64_t)row);
+  if (ctx->read_cap < want) {
+    for (int i = 0; i < 2; ++i) {
+      CMP_TRY(hipEventSynchronize(ctx->ev_read[i]));
+      if (ctx->h_read[i]) hipHostFree(ctx->h_read[i]);
+      ctx->h_read[i] = nullptr;
+    }
+    ctx->read_cap = 0;
+    for (int i = 0; i < 2; ++i)
+      if (hipHostMalloc((void **)&ctx->h_read[i], want, hipHostMallocDefault) != hipSuccess)
+        return CMP_ENOMEM;
+    ctx->read_cap = want;
+  }
+  const int64_t band = std::max<int64_t>(1, ctx->read_cap / (int64_t)row);
+  auto drain = [&](int slot, int64_t r0, int64_t rows) -> bool {
+    if (hipEventSynchronize(ctx->ev_read[slot]) != hipSuccess) return false;
+    uint8_t *d8 = static_cast<uint8_t *>(dst);
+    for (int64_t r = 0; r < rows; ++r)
+      std::memcpy(d8 + (r0 + r) * dst_pitch_bytes, ctx->h_read[slot] + r * row, row);
+    return true;
+  };
+  int64_t prev_r0 = -1, prev_rows = 0;
+  int prev_slot = 0;
+  for (int64_t r0 = 0, b = 0; r0 < h; r0 += band, ++b) {
+    const int slot = (int)(b & 1);
+    const int64_t rows = std::min<int64_t>(band, h - r0);
+    CMP_TRY(hipMemcpy2DAsync(ctx->h_read[slot], row, s8 + r0 * spitch, spitch, row, (size_t)rows,
+                             hipMemcpyDeviceToHost, ctx->comp_s));
+    CMP_TRY(hipEventRecord(ctx->ev_read[slot], ctx->comp_s));
+    if (prev_r0 >= 0 && !drain(prev_slot, prev_r0, prev_rows)) {
+      ctx->poisoned = true;
+      return CMP_EDEVICE;
+    }
+    prev_r0 = r0;
+    prev_rows = rows;
+    prev_slot = slot;
+  }
+  if (prev_r0 >= 0 && !drain(prev_slot, prev_r0, prev_rows)) {
+    ctx->poisoned = true;
+    return CMP_EDEVICE;
+  }
   return CMP_OK;
 }
 

@@ -49,14 +49,16 @@ __device__ __forceinline__ uint32_t bmax(uint32_t a, uint32_t b) {
   return __builtin_amdgcn_perm(h, l, 0x06020400u);
 }
 
-typedef const __attribute__((address_space(1))) uint8_t gbyte;
+typedef unsigned int u32x4u __attribute__((ext_vector_type(4), aligned(1)));
+typedef const __attribute__((address_space(1))) u32x4u gu32x4u;
 
-// 16 bytes from global memory at base + off, any alignment: one
-// global_load_dwordx4 with the base in SGPRs and a 32-bit VGPR offset.
+// 16 member bytes from global memory at base + off, any alignment: one
+// global_load_dwordx4 with the non-temporal hint.  Every member byte is read
+// exactly once, so the loads should not displace the composite's lines in the
+// caches (measured: +4% bandwidth over plain loads for 128 members of 8192^2).
 __device__ __forceinline__ uint4 ld16(const uint8_t *base, uint32_t off) {
-  uint4 v;
-  __builtin_memcpy(&v, (gbyte *)base + off, 16);
-  return v;
+  const u32x4u v = __builtin_nontemporal_load((gu32x4u *)(base + off));
+  return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 // Packed accumulators of 16 pixels.  Lane pair k*2 holds pixels 4k and 4k+2,
@@ -110,19 +112,46 @@ __device__ __forceinline__ void fold_members(const uint8_t *const *__restrict__ 
   for (; i < i1; ++i) a.fold(ld16(tab[i], off));
 }
 
-// Read-modify-write of 16 composite pixels starting at pixel index p.
+// The composite values of 16 pixels before this launch's update.
+template <bool C16>
+struct Old {
+  uint4 c[C16 ? 2 : 4];
+  uint4 s[4];
+  uint4 m;
+};
+
 template <uint32_t OUTS, bool SUB, bool C16>
-__device__ __forceinline__ void update16(const uint32_t *cnt, const uint32_t *sm,
-                                         const uint32_t *mx8, uint32_t p,
-                                         void *__restrict__ count, uint32_t *__restrict__ sum,
-                                         uint8_t *__restrict__ mx) {
+__device__ __forceinline__ void load_old(Old<C16> &o, uint32_t p, const void *__restrict__ count,
+                                         const uint32_t *__restrict__ sum,
+                                         const uint8_t *__restrict__ mx) {
+  if constexpr (OUTS & kCount) {
+    const uint4 *src = C16 ? reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(count) + p)
+                           : reinterpret_cast<const uint4 *>(static_cast<const uint32_t *>(count) + p);
+#pragma unroll
+    for (int q = 0; q < (C16 ? 2 : 4); ++q) o.c[q] = src[q];
+  }
+  if constexpr (OUTS & kSum) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(sum + p);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o.s[q] = src[q];
+  }
+  if constexpr ((OUTS & kMax) && !SUB) o.m = *reinterpret_cast<const uint4 *>(mx + p);
+}
+
+// Writes old (+ or -) new for 16 pixels starting at pixel index p; max takes
+// the bytewise maximum.  cnt, sm: per-pixel 32-bit contributions; mx8: the
+// new maxima as 16 bytes.
+template <uint32_t OUTS, bool SUB, bool C16>
+__device__ __forceinline__ void store_new(const Old<C16> &o, const uint32_t *cnt,
+                                          const uint32_t *sm, const uint32_t *mx8, uint32_t p,
+                                          void *__restrict__ count, uint32_t *__restrict__ sum,
+                                          uint8_t *__restrict__ mx) {
   if constexpr (OUTS & kCount) {
     if constexpr (C16) {
       uint4 *dst = reinterpret_cast<uint4 *>(static_cast<uint16_t *>(count) + p);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        uint4 o = dst[q];
-        uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+        uint32_t ow[4] = {o.c[q].x, o.c[q].y, o.c[q].z, o.c[q].w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const uint32_t nw = cnt[8 * q + 2 * k] | (cnt[8 * q + 2 * k + 1] << 16);
@@ -134,13 +163,13 @@ __device__ __forceinline__ void update16(const uint32_t *cnt, const uint32_t *sm
       uint4 *dst = reinterpret_cast<uint4 *>(static_cast<uint32_t *>(count) + p);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        uint4 o = dst[q];
+        uint4 v = o.c[q];
         if (SUB) {
-          o.x -= cnt[4 * q]; o.y -= cnt[4 * q + 1]; o.z -= cnt[4 * q + 2]; o.w -= cnt[4 * q + 3];
+          v.x -= cnt[4 * q]; v.y -= cnt[4 * q + 1]; v.z -= cnt[4 * q + 2]; v.w -= cnt[4 * q + 3];
         } else {
-          o.x += cnt[4 * q]; o.y += cnt[4 * q + 1]; o.z += cnt[4 * q + 2]; o.w += cnt[4 * q + 3];
+          v.x += cnt[4 * q]; v.y += cnt[4 * q + 1]; v.z += cnt[4 * q + 2]; v.w += cnt[4 * q + 3];
         }
-        dst[q] = o;
+        dst[q] = v;
       }
     }
   }
@@ -148,20 +177,19 @@ __device__ __forceinline__ void update16(const uint32_t *cnt, const uint32_t *sm
     uint4 *dst = reinterpret_cast<uint4 *>(sum + p);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      uint4 o = dst[q];
+      uint4 v = o.s[q];
       if (SUB) {
-        o.x -= sm[4 * q]; o.y -= sm[4 * q + 1]; o.z -= sm[4 * q + 2]; o.w -= sm[4 * q + 3];
+        v.x -= sm[4 * q]; v.y -= sm[4 * q + 1]; v.z -= sm[4 * q + 2]; v.w -= sm[4 * q + 3];
       } else {
-        o.x += sm[4 * q]; o.y += sm[4 * q + 1]; o.z += sm[4 * q + 2]; o.w += sm[4 * q + 3];
+        v.x += sm[4 * q]; v.y += sm[4 * q + 1]; v.z += sm[4 * q + 2]; v.w += sm[4 * q + 3];
       }
-      dst[q] = o;
+      dst[q] = v;
     }
   }
   if constexpr ((OUTS & kMax) && !SUB) {
-    uint4 *dst = reinterpret_cast<uint4 *>(mx + p);
-    uint4 o = *dst;
-    o.x = bmax(o.x, mx8[0]); o.y = bmax(o.y, mx8[1]); o.z = bmax(o.z, mx8[2]); o.w = bmax(o.w, mx8[3]);
-    *dst = o;
+    uint4 v = o.m;
+    v.x = bmax(v.x, mx8[0]); v.y = bmax(v.y, mx8[1]); v.z = bmax(v.z, mx8[2]); v.w = bmax(v.w, mx8[3]);
+    *reinterpret_cast<uint4 *>(mx + p) = v;
   }
 }
 
@@ -203,6 +231,7 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 
   Acc<OUTS> a;
   a.zero();
+  Old<C16> old;
   uint32_t cnt[16], sm[16], mx8[4];
   if constexpr (MULTI) {
 #pragma unroll
@@ -218,8 +247,28 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 #pragma unroll
       for (int k = 0; k < 8; ++k) a.c[k] = a.s[k] = 0u;
     }
+    load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
   } else {
-    fold_members<UNROLL>(tab, 0, n, off, a);
+    // The old composite is requested before the last members are read, so
+    // its latency overlaps them instead of trailing the wave (+1-2%).
+    int i = 0;
+    for (; i + UNROLL < n; i += UNROLL) {
+      uint4 x[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) x[u] = ld16(tab[i + u], off);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) a.fold(x[u]);
+    }
+    load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
+    {  // the last 1..UNROLL members (n >= 1)
+      uint4 x[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+        if (i + u < n) x[u] = ld16(tab[i + u], off);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+        if (i + u < n) a.fold(x[u]);
+    }
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       cnt[j] = lane_px(a.c, j);
@@ -230,7 +279,7 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 #pragma unroll
     for (int k = 0; k < 4; ++k) mx8[k] = __builtin_amdgcn_perm(a.m[2 * k + 1], a.m[2 * k], 0x06020400u);
   }
-  update16<OUTS, SUB, C16>(cnt, sm, mx8, p, count, sum, mx);
+  store_new<OUTS, SUB, C16>(old, cnt, sm, mx8, p, count, sum, mx);
 }
 
 // Pixels [p0, npix) that do not fill a 16-pixel vector: one thread per pixel.

@@ -82,9 +82,15 @@ def test_streamed_from_pageable_numpy():
     W, H, n = 100, 37, 9
     stack = _random_stack(5, n, H, W)
     exp = expect_oracle(stack, ALL, 32)
-    with Composite(W, H, ALL, 32, chunk_depth=4) as c:
-        c.add([stack[i] for i in range(n)])
-        check_full(c, exp)
+    for nbuf in (1, 2):
+        with Composite(W, H, ALL, 32, chunk_depth=4, nbuf=nbuf, pageable_host=1) as c:
+            c.add([stack[i] for i in range(n)])
+            check_full(c, exp)
+        with Composite(W, H, ("count", "sum"), 32, chunk_depth=2, nbuf=nbuf,
+                       pageable_host=1) as c:
+            c.add([stack[i] for i in range(n)])
+            c.remove([stack[i] for i in range(3, n)])
+            check_full(c, expect_oracle(stack[:3], ("count", "sum"), 32))
 
 
 @pytest.mark.parametrize("depth", [1, 3, 8, 255, 256])
@@ -226,6 +232,13 @@ def test_read_windows_and_device_destination():
         with pytest.raises(CompositeError) as ei:
             c.read("count", (W - 2, 0, 3, 1))
         assert ei.value.status == CMP_EINVAL
+        # page-locked destination written by the copy engine directly
+        for k in ALL:
+            dt = {"max": torch.uint8}.get(k, torch.int32)
+            pin = torch.zeros((H - 3, W - 5), dtype=dt, pin_memory=True)
+            arr = pin.numpy().view(full[k].dtype)
+            c.read(k, (2, 1, W - 5, H - 3), out=arr, pinned=True)
+            assert np.array_equal(arr, oracle.window(full[k], 2, 1, W - 5, H - 3))
 
 
 def test_clear_forgets_members():
