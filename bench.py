@@ -183,6 +183,68 @@ def run_streamed(torch, ens, e, reps, variants):
     return res
 
 
+def run_batched(torch, reps):
+    """Batched crop requests: pool of 2048 masks of 2048x2048, 64 requests;
+    one autotuned persistent launch (graph replay) against 64 plain launches."""
+    from paper_2104_14667_amd import synth
+    from paper_2104_14667_amd.composite import (CMP_BATCH_PER_REQUEST, CMP_BATCH_PERSISTENT,
+                                                Pool, make_tune)
+    from paper_2104_14667_amd.tune import autotune
+    wl = synth.BATCHED
+    e = wl.elevation()
+    lv = wl.levels()
+    et = torch.from_numpy(e).to("cuda:0")
+    plane = wl.H * wl.W
+    buf = torch.empty(wl.pool * plane + 64, dtype=torch.uint8, device="cuda:0")
+    for i, L in enumerate(lv):
+        synth.member_torch(et, int(L), "mask", out=buf[i * plane:(i + 1) * plane].view(wl.H, wl.W))
+    reqs = wl.requests()
+    for r in reqs:
+        r["out"] = torch.empty((r["h"], r["w"]), dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    pxm = sum(len(r["ids"]) * r["w"] * r["h"] for r in reqs)
+    out = {"workload": "batched: pool 2048 x 2048x2048 masks, 64 requests, N in [4,512], "
+                       "square crops of side [512,2048] -> u32 count",
+           "px_members": pxm}
+    with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
+        best = autotune(pool, reqs, reps=2)
+        out["autotune"] = {k: best[k] for k in ("tile_vecs", "blocks_per_cu", "seconds")}
+        variants = {
+            "persistent_graph": make_tune(CMP_BATCH_PERSISTENT, best["tile_vecs"],
+                                          best["blocks_per_cu"], 1),
+            "persistent_no_graph": make_tune(CMP_BATCH_PERSISTENT, best["tile_vecs"],
+                                             best["blocks_per_cu"], 0),
+            "per_request_launches": make_tune(CMP_BATCH_PER_REQUEST),
+        }
+        for name, tune in variants.items():
+            dev_ms, wall_ms = [], []
+            for _ in range(reps + 1):
+                t0 = time.perf_counter()
+                pool.run(reqs, tune)
+                wall_ms.append((time.perf_counter() - t0) * 1e3)
+                dev_ms.append(pool.last()[0])
+            dev_ms, wall_ms = dev_ms[1:], wall_ms[1:]
+            d = float(np.median(dev_ms))
+            out[name] = {"device_ms": round(d, 4), "wall_ms": round(float(np.median(wall_ms)), 4),
+                         "gpx_member_per_s": round(pxm / (d * 1e-3) / 1e9, 1)}
+        # the last run's outputs against the closed form of each request
+        exact = True
+        for r in reqs:
+            got = r["out"].cpu().numpy().view(np.uint32)
+            ec = e[r["y0"]:r["y0"] + r["h"], r["x0"]:r["x0"] + r["w"]]
+            lvs = np.sort(lv[r["ids"]])
+            exp = len(lvs) - np.searchsorted(lvs, ec, side="right")
+            exact = exact and bool(np.array_equal(got, exp))
+        out["exact"] = exact
+        p = out["persistent_graph"]["device_ms"]
+        out["speedup_vs_per_request"] = round(out["per_request_launches"]["device_ms"] / p, 3)
+        out["hbm_GBps_persistent"] = round((pxm + 4 * sum(r["w"] * r["h"] for r in reqs))
+                                           / (p * 1e-3) / 1e9, 1)
+    del buf, reqs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(ens, e, seconds):
     """The oracle as it stands, single-threaded numpy, on bands of rows of the
     same workload until about `seconds` of CPU work; scaled to px-members/s."""
@@ -215,6 +277,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--stream-reps", type=int, default=3)
     ap.add_argument("--no-streamed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy of 1 GiB (torch.neg on int32) "
@@ -292,6 +355,9 @@ def main():
             "workload": "depth N=128 x 8192x8192 from pinned host, chunk 8, PCIe-inclusive",
             **run_streamed(torch, ens, e, max(1, args.stream_reps - 1), {
                 "dual_buffer_linear": dict(nbuf=2, chunk_depth=8)})}
+    if not args.no_batched:
+        log("batched", synth.BATCHED.name)
+        out["batched"] = run_batched(torch, args.stream_reps + 2)
     log("cpu baseline")
     out["cpu_baseline"] = cpu_baseline(ens, e, args.cpu_seconds)
     out["host"] = {"cpu": platform.processor() or platform.machine(),

@@ -182,6 +182,71 @@ int composite_device_buffer(cmp_ctx *ctx, uint32_t which, void **dev_ptr);
 int composite_kernel_stats(cmp_ctx *ctx, int64_t *launches, double *total_ms,
                            int32_t reset);
 
+/* ------------------------------------------------------------------------
+ * Batched requests against a device-resident pool of rasters.
+ *
+ * A request asks for the member count composite of a subset of the pool,
+ * restricted to a crop window: the paper's compositing of a chosen set of
+ * surfaces (Figure 1) applied to a spatial segment (Section 1, spatial
+ * subdivision).  Many requests of uneven set sizes and windows are served by
+ * one persistent launch whose workgroups pull (request, band of rows) work
+ * items from a queue in device memory.
+ */
+typedef struct cmp_pool cmp_pool;
+
+/* Wraps `count` rasters of W x H bytes already in device memory at
+ * dev_base + i * stride_bytes (row-major, pitch W).  pool_bytes is the size
+ * of the allocation that starts at dev_base; it must extend at least 16
+ * bytes past the end of the last raster (the kernels read whole 16-byte
+ * vectors and may touch up to 15 bytes past a window's right edge).  The
+ * caller keeps the memory alive until composite_pool_free.  The pool owns a
+ * compute stream (default priority) and its descriptor buffers. */
+int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count, int32_t W,
+                          int32_t H, int64_t stride_bytes, int64_t pool_bytes, int32_t device);
+
+/* Waits for the pool's stream, then releases what the pool owns (not the
+ * rasters).  NULL is ignored. */
+void composite_pool_free(cmp_pool *pool);
+
+typedef struct cmp_request {
+  const int32_t *ids;     /* host array of n pool indices (repeats count twice) */
+  int32_t n;              /* 0 .. 65535 */
+  int32_t x0, y0, w, h;   /* crop window inside W x H, w, h >= 1 */
+  uint32_t *dev_count;    /* device memory: h rows of w uint32 counts */
+  int64_t out_pitch;      /* elements between output rows, >= w */
+} cmp_request;
+
+enum cmp_batch_mode { CMP_BATCH_PERSISTENT = 0, CMP_BATCH_PER_REQUEST = 1 };
+
+typedef struct cmp_tune {
+  int32_t mode;           /* cmp_batch_mode.  PER_REQUEST launches one plain
+                             kernel per request, in order (the baseline) */
+  int32_t tile_vecs;      /* persistent mode: 16-pixel vectors per work item
+                             (a band of whole crop rows), 64 .. 65536 */
+  int32_t blocks_per_cu;  /* persistent mode: workgroups of 256 per compute
+                             unit, 1 .. 16 */
+  int32_t use_graph;      /* persistent mode: 1 replays a captured hipGraph of
+                             [queue reset, persistent kernel]; captured once
+                             per grid size and reused */
+  int32_t reserved[4];    /* must be zero */
+} cmp_tune;
+
+/* Fills *t with the defaults (persistent, tile_vecs 1024, blocks_per_cu 8,
+ * use_graph 1).  NULL is ignored. */
+void composite_default_tune(cmp_tune *t);
+
+/* Runs nreq requests and returns when every output is written.  Every
+ * request is validated first (ids < pool count, window inside the raster,
+ * dev_count non-NULL, out_pitch >= w); nothing is launched on error.
+ * tune: NULL for the defaults. */
+int composite_batch_run(cmp_pool *pool, const cmp_request *reqs, int32_t nreq,
+                        const cmp_tune *tune);
+
+/* Device time in milliseconds of the last composite_batch_run, measured with
+ * HIP events around its launches on the pool's stream (descriptor upload
+ * excluded), and the number of work items it ran. */
+int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items);
+
 /* Static description of a status code; never NULL. */
 const char *composite_strerror(int status);
 

@@ -36,6 +36,20 @@ class cmp_opts(C.Structure):
                 ("reserved", C.c_int32 * 4)]
 
 
+class cmp_request(C.Structure):
+    _fields_ = [("ids", C.POINTER(C.c_int32)), ("n", C.c_int32), ("x0", C.c_int32),
+                ("y0", C.c_int32), ("w", C.c_int32), ("h", C.c_int32),
+                ("dev_count", C.c_void_p), ("out_pitch", C.c_int64)]
+
+
+class cmp_tune(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("tile_vecs", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("use_graph", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+CMP_BATCH_PERSISTENT, CMP_BATCH_PER_REQUEST = 0, 1
+
+
 class CompositeError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -65,6 +79,11 @@ _SIGS = {
     "composite_members": (C.c_int, [_vp, _P(_i64)]),
     "composite_device_buffer": (C.c_int, [_vp, _u32, _P(_vp)]),
     "composite_kernel_stats": (C.c_int, [_vp, _P(_i64), _P(C.c_double), _i32]),
+    "composite_pool_create": (C.c_int, [_P(_vp), _vp, _i64, _i32, _i32, _i64, _i64, _i32]),
+    "composite_pool_free": (None, [_vp]),
+    "composite_default_tune": (None, [_P(cmp_tune)]),
+    "composite_batch_run": (C.c_int, [_vp, _P(cmp_request), _i32, _P(cmp_tune)]),
+    "composite_batch_last": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
     "composite_strerror": (C.c_char_p, [C.c_int]),
     "composite_free": (None, [_vp]),
 }
@@ -275,3 +294,94 @@ class Composite:
 
     def device_buffer(self, name: str) -> int:
         return composite_device_buffer(self.ctx, OUTPUT_BITS[name])
+
+
+# ---------------------------------------------------------------- batched pool
+
+def composite_default_tune() -> cmp_tune:
+    t = cmp_tune()
+    lib.composite_default_tune(C.byref(t))
+    return t
+
+
+def composite_pool_create(dev_base, count: int, W: int, H: int, stride_bytes: int,
+                          pool_bytes: int, device: int = 0) -> int:
+    h = C.c_void_p()
+    _check(lib.composite_pool_create(C.byref(h), _ptr(dev_base), int(count), int(W), int(H),
+                                     int(stride_bytes), int(pool_bytes), int(device)),
+           "composite_pool_create")
+    return h.value
+
+
+def composite_pool_free(pool: int) -> None:
+    lib.composite_pool_free(pool)
+
+
+def make_requests(requests) -> tuple:
+    """ctypes array of cmp_request from dicts with ids, x0, y0, w, h, out (a
+    device tensor or address) and optional pitch (elements).  Returns the array
+    and the id buffers it points into (keep both alive)."""
+    arr = (cmp_request * len(requests))()
+    keep = []
+    for i, r in enumerate(requests):
+        ids = np.ascontiguousarray(np.asarray(r["ids"], dtype=np.int32))
+        keep.append(ids)
+        arr[i].ids = ids.ctypes.data_as(C.POINTER(C.c_int32)) if ids.size else None
+        arr[i].n = ids.size
+        arr[i].x0, arr[i].y0, arr[i].w, arr[i].h = int(r["x0"]), int(r["y0"]), int(r["w"]), int(r["h"])
+        arr[i].dev_count = _ptr(r["out"])
+        arr[i].out_pitch = int(r.get("pitch", r["w"]))
+    return arr, keep
+
+
+def composite_batch_run(pool: int, requests, tune: Optional[cmp_tune] = None) -> None:
+    arr, keep = make_requests(requests)
+    _check(lib.composite_batch_run(pool, arr, len(requests),
+                                   C.byref(tune) if tune is not None else None),
+           "composite_batch_run")
+    del keep
+
+
+def composite_batch_last(pool: int):
+    ms = C.c_double()
+    items = C.c_int64()
+    _check(lib.composite_batch_last(pool, C.byref(ms), C.byref(items)), "composite_batch_last")
+    return ms.value, items.value
+
+
+def make_tune(mode=CMP_BATCH_PERSISTENT, tile_vecs=1024, blocks_per_cu=8, use_graph=1) -> cmp_tune:
+    t = composite_default_tune()
+    t.mode, t.tile_vecs, t.blocks_per_cu, t.use_graph = mode, tile_vecs, blocks_per_cu, use_graph
+    return t
+
+
+class Pool:
+    """Device-resident pool of rasters for batched crop requests."""
+
+    def __init__(self, dev_base, count: int, W: int, H: int, stride_bytes: int,
+                 pool_bytes: int, device: int = 0):
+        self.count, self.W, self.H = int(count), int(W), int(H)
+        self.handle = composite_pool_create(dev_base, count, W, H, stride_bytes, pool_bytes, device)
+
+    def run(self, requests, tune: Optional[cmp_tune] = None) -> None:
+        composite_batch_run(self.handle, requests, tune)
+
+    def last(self):
+        return composite_batch_last(self.handle)
+
+    def close(self):
+        if self.handle:
+            composite_pool_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,66 @@
+"""Autotuner of the batched persistent launch.
+
+Sweeps the work-item size (16-pixel vectors per item) and the persistent
+occupancy (workgroups per compute unit) on the actual batch, timing each
+candidate with the library's own event timing, and keeps the fastest.  Results
+are cached per shape class (arch, raster size, request count, typical window
+side and set size, each bucketed to a power of two) in memory and, when a path
+is given, in a JSON file."""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Dict, Optional, Sequence
+
+from .composite import CMP_BATCH_PERSISTENT, Pool, make_tune
+
+TILE_VECS = (256, 512, 1024, 2048, 4096, 8192)
+BLOCKS_PER_CU = (2, 4, 8, 12, 16)
+
+_cache: Dict[str, dict] = {}
+
+
+def _bucket(x: float) -> int:
+    return 1 << max(0, int(round(math.log2(max(1.0, x)))))
+
+
+def shape_key(pool: Pool, requests: Sequence[dict], arch: str = "gfx950") -> str:
+    nreq = len(requests)
+    side = sum((r["w"] * r["h"]) ** 0.5 for r in requests) / max(1, nreq)
+    n = sum(len(r["ids"]) for r in requests) / max(1, nreq)
+    return f"{arch}/W{pool.W}xH{pool.H}/req{_bucket(nreq)}/side{_bucket(side)}/n{_bucket(n)}"
+
+
+def autotune(pool: Pool, requests: Sequence[dict], reps: int = 3,
+             cache_path: Optional[str] = None, use_graph: int = 1) -> dict:
+    """Returns {'tile_vecs', 'blocks_per_cu', 'ms', 'key', 'seconds', 'cached'}."""
+    key = shape_key(pool, requests)
+    if cache_path and os.path.exists(cache_path) and not _cache:
+        try:
+            _cache.update(json.load(open(cache_path)))
+        except (OSError, ValueError):
+            pass
+    if key in _cache:
+        return dict(_cache[key], key=key, cached=True, seconds=0.0)
+    t0 = time.perf_counter()
+    best = None
+    for tv in TILE_VECS:
+        for bpc in BLOCKS_PER_CU:
+            tune = make_tune(CMP_BATCH_PERSISTENT, tv, bpc, use_graph)
+            ms = []
+            for _ in range(reps):
+                pool.run(requests, tune)
+                ms.append(pool.last()[0])
+            m = min(ms)
+            if best is None or m < best["ms"]:
+                best = {"tile_vecs": tv, "blocks_per_cu": bpc, "ms": m}
+    _cache[key] = best
+    if cache_path:
+        try:
+            json.dump(_cache, open(cache_path, "w"), indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return dict(best, key=key, cached=False, seconds=time.perf_counter() - t0)

@@ -66,3 +66,22 @@ def test_init_without_gpu_reports_edevice():
     h = C.c_void_p()
     assert cb.lib.composite_init(C.byref(h), 16, 16, 1, 32, None) == cb.CMP_EDEVICE
     assert h.value is None
+
+
+def test_pool_and_batch_argument_checks():
+    h = C.c_void_p()
+    assert cb.lib.composite_pool_create(None, 1, 1, 4, 4, 16, 32, 0) == cb.CMP_EINVAL
+    assert cb.lib.composite_pool_create(C.byref(h), None, 1, 4, 4, 16, 32, 0) == cb.CMP_EINVAL
+    assert cb.lib.composite_pool_create(C.byref(h), 4096, 2, 4, 4, 16, 40, 0) == cb.CMP_EINVAL
+    assert cb.lib.composite_pool_create(C.byref(h), 4096, 2, 4, 4, 8, 64, 0) == cb.CMP_EINVAL
+    assert cb.lib.composite_batch_run(None, None, 0, None) == cb.CMP_EINVAL
+    t = cb.composite_default_tune()
+    assert (t.mode, t.tile_vecs, t.blocks_per_cu, t.use_graph) == (0, 1024, 8, 1)
+    assert C.sizeof(cb.cmp_request) == 48 and C.sizeof(cb.cmp_tune) == 32
+    cb.lib.composite_pool_free(None)
+
+
+@pytest.mark.skipif(torch.cuda.device_count() > 0, reason="a GPU is present")
+def test_pool_without_gpu_reports_edevice():
+    h = C.c_void_p()
+    assert cb.lib.composite_pool_create(C.byref(h), 4096, 2, 4, 4, 16, 64, 0) == cb.CMP_EDEVICE

@@ -1,0 +1,158 @@
+"""Batched crop requests against a device pool, through the C ABI (GPU).
+
+Every output is compared with the oracle's batched composite (small pools,
+every pixel) or with the closed form per request plus sampled pixels of the
+oracle (the full pool of 2048 maps of 2048x2048).  Tolerance zero."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2104_14667_amd import synth
+from paper_2104_14667_amd.composite import (CMP_BATCH_PER_REQUEST, CMP_BATCH_PERSISTENT,
+                                            CMP_EINVAL, CompositeError, Pool, make_tune)
+from paper_2104_14667_amd.tune import autotune
+
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _pool_tensor(stack: np.ndarray):
+    """Contiguous device copy with 64 bytes of slack after the last raster."""
+    P, H, W = stack.shape
+    buf = torch.zeros(P * H * W + 64, dtype=torch.uint8, device="cuda")
+    buf[: P * H * W].copy_(torch.from_numpy(stack.reshape(-1)))
+    torch.cuda.synchronize()
+    return buf
+
+
+def _outs(reqs, pad=0):
+    for r in reqs:
+        r["out"] = torch.full((r["h"], r["w"] + pad), -1, dtype=torch.int32, device="cuda")
+        r["pitch"] = r["w"] + pad
+    torch.cuda.synchronize()
+
+
+def _got(r):
+    return r["out"][:, : r["w"]].cpu().numpy().view(np.uint32).astype(np.int64)
+
+
+TUNES = [make_tune(CMP_BATCH_PERSISTENT, 64, 1, 0), make_tune(CMP_BATCH_PERSISTENT, 1024, 8, 1),
+         make_tune(CMP_BATCH_PERSISTENT, 256, 3, 1), make_tune(CMP_BATCH_PER_REQUEST)]
+
+
+def _small_case(seed):
+    rng = np.random.default_rng(seed)
+    P, H, W = 37, 45, 77
+    stack = synth.random_members(seed, P, H, W)
+    reqs = [dict(ids=[], x0=0, y0=0, w=W, h=H),                       # empty set
+            dict(ids=[3], x0=W - 1, y0=H - 1, w=1, h=1),               # last pixel
+            dict(ids=[5, 5, 5], x0=1, y0=2, w=17, h=3),                 # repeats
+            dict(ids=list(range(P)), x0=0, y0=0, w=W, h=H)]             # everything
+    for _ in range(12):
+        w = int(rng.integers(1, W + 1))
+        h = int(rng.integers(1, H + 1))
+        n = int(rng.integers(0, 300))
+        reqs.append(dict(ids=rng.integers(0, P, n).tolist(), x0=int(rng.integers(0, W - w + 1)),
+                         y0=int(rng.integers(0, H - h + 1)), w=w, h=h))
+    return stack, reqs
+
+
+@pytest.mark.parametrize("ti", range(len(TUNES)))
+def test_small_pool_all_tunes(ti):
+    stack, reqs = _small_case(ti + 1)
+    P, H, W = stack.shape
+    exp = oracle.batch(stack, reqs)
+    buf = _pool_tensor(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        for pad in (0, 5):
+            _outs(reqs, pad)
+            pool.run(reqs, TUNES[ti])
+            for k, (r, e) in enumerate(zip(reqs, exp)):
+                assert np.array_equal(_got(r), e), f"request {k}"
+            # a second run of the same pool and tune (graph replay) is identical
+            _outs(reqs, pad)
+            pool.run(reqs, TUNES[ti])
+            for k, (r, e) in enumerate(zip(reqs, exp)):
+                assert np.array_equal(_got(r), e), f"replay, request {k}"
+
+
+def test_varying_batches_reuse_one_graph():
+    stack, reqs = _small_case(9)
+    P, H, W = stack.shape
+    buf = _pool_tensor(stack)
+    tune = make_tune(CMP_BATCH_PERSISTENT, 128, 2, 1)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        for k in range(1, len(reqs) + 1, 3):
+            sub = [dict(r) for r in reqs[:k]]
+            _outs(sub)
+            pool.run(sub, tune)
+            for r, e in zip(sub, oracle.batch(stack, sub)):
+                assert np.array_equal(_got(r), e)
+            torch.cuda.synchronize()          # eager work between replays
+
+
+def test_invalid_requests_launch_nothing():
+    stack, reqs = _small_case(4)
+    P, H, W = stack.shape
+    buf = _pool_tensor(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        good = [dict(reqs[2])]
+        bads = [dict(good[0], ids=[P]), dict(good[0], ids=[-1]), dict(good[0], x0=W - 3, w=4),
+                dict(good[0], h=0)]
+        for bad in bads:
+            batch = [dict(good[0]), bad]
+            _outs(batch)
+            with pytest.raises(CompositeError) as ei:
+                pool.run(batch)
+            assert ei.value.status == CMP_EINVAL
+            assert (batch[0]["out"] == -1).all()      # nothing ran
+        bad = dict(good[0])
+        _outs([bad])
+        bad["pitch"] = bad["w"] - 1
+        with pytest.raises(CompositeError):
+            pool.run([bad])
+    with pytest.raises(CompositeError):
+        Pool(buf, P, W, H, H * W, P * H * W)          # no slack after the last raster
+
+
+def _closed_form_counts(levels_sorted, e_crop):
+    # count of levels L > e, for members e < L of one shared elevation field
+    return len(levels_sorted) - np.searchsorted(levels_sorted, e_crop, side="right")
+
+
+def test_full_batched_pool_2048():
+    wl = synth.BATCHED
+    say("full batched", wl.name)
+    e = wl.elevation()
+    lv = wl.levels()
+    et = torch.from_numpy(e).cuda()
+    plane = wl.H * wl.W
+    buf = torch.empty(wl.pool * plane + 64, dtype=torch.uint8, device="cuda")
+    for i, L in enumerate(lv):
+        synth.member_torch(et, int(L), "mask", out=buf[i * plane:(i + 1) * plane].view(wl.H, wl.W))
+    torch.cuda.synchronize()
+    reqs = wl.requests()
+    rng = np.random.default_rng(0)
+    _outs(reqs)
+    with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
+        best = autotune(pool, reqs[:16], reps=1)
+        say("autotuned", best)
+        for tune in (make_tune(CMP_BATCH_PERSISTENT, best["tile_vecs"], best["blocks_per_cu"], 1),
+                     make_tune(CMP_BATCH_PER_REQUEST)):
+            _outs(reqs)
+            pool.run(reqs, tune)
+            for k, r in enumerate(reqs):
+                got = _got(r)
+                ec = e[r["y0"]:r["y0"] + r["h"], r["x0"]:r["x0"] + r["w"]]
+                exp = _closed_form_counts(np.sort(lv[r["ids"]]), ec)
+                assert np.array_equal(got, exp), f"request {k} vs closed form"
+                # sampled pixels against the oracle, members rebuilt on the host
+                ys = rng.integers(0, r["h"], 16)
+                xs = rng.integers(0, r["w"], 16)
+                es = ec[ys, xs]
+                o = oracle.accumulate([synth.mask(es, int(lv[i])) for i in r["ids"]],
+                                      shape=es.shape, outputs=("count",))["count"]
+                assert np.array_equal(got[ys, xs], o), f"request {k} vs oracle samples"
