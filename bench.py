@@ -245,6 +245,62 @@ def run_batched(torch, reps):
     return out
 
 
+def run_served(torch, duration_s, spill_duration_s):
+    """Served sessions: open-loop Poisson arrivals at 2000 req/s over 256
+    sessions of 4096x4096 u32 count, pool of 1024 depth maps; each request adds
+    or removes 1-32 members and reads a 1024x1024 viewport.  Continuous
+    batching against unbatched FIFO serving on the same GPU."""
+    from paper_2104_14667_amd import synth
+    from paper_2104_14667_amd.composite import Pool, Server
+    wl = synth.SERVED
+    e = wl.elevation()
+    lv = wl.levels()
+    et = torch.from_numpy(e).to("cuda:0")
+    plane = wl.H * wl.W
+    buf = torch.empty(wl.pool * plane + 64, dtype=torch.uint8, device="cuda:0")
+    for i, L in enumerate(lv):
+        synth.member_torch(et, int(L), "depth", out=buf[i * plane:(i + 1) * plane].view(wl.H, wl.W))
+    torch.cuda.synchronize()
+    n = int(wl.rate * duration_s)
+    sched = wl.schedule(n)
+    ring = [torch.empty((wl.view, wl.view), dtype=torch.int32, pin_memory=True) for _ in range(128)]
+    out = {"workload": "served: 256 sessions x 4096x4096 u32 count, pool 1024 depth maps, "
+                       "Poisson 2000 req/s, add/remove 1-32 members (60/40), 1024x1024 viewport",
+           "requests": n, "offered_rps": wl.rate}
+
+    def one(name, sched, **opts):
+        with Server(pool, **opts) as srv:
+            sids = [srv.open() for _ in range(wl.sessions)]
+            t0 = time.perf_counter()
+            lat = srv.replay(sched, sids, ring, wl.view)
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        lat_ms = lat / 1e6
+        pxm = sum(len(r["ids"]) for r in sched) * plane
+        out[name] = {"p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                     "mean_ms": round(float(lat_ms.mean()), 3),
+                     "completed_rps": round(len(sched) / wall, 1),
+                     "steps": st["steps"], "mean_step": round(st["requests"] / max(1, st["steps"]), 2),
+                     "max_step": st["max_step"], "spills": st["spills"], "restores": st["restores"],
+                     "device_ms_per_request": round(st["device_ms"] / max(1, st["requests"]), 4),
+                     "gpx_member_per_s": round(pxm / wall / 1e9, 1)}
+
+    with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
+        one("continuous_batching", sched, max_batch=64, overlap=1,
+            hbm_budget_bytes=wl.sessions * plane * 4)
+        one("unbatched_fifo", sched, max_batch=1, overlap=0,
+            hbm_budget_bytes=wl.sessions * plane * 4)
+        if spill_duration_s > 0:
+            m = int(wl.rate * spill_duration_s)
+            out["spill_requests"] = m
+            one("continuous_batching_budget_half", sched[:m], max_batch=64, overlap=1,
+                hbm_budget_bytes=wl.sessions // 2 * plane * 4)
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(ens, e, seconds):
     """The oracle as it stands, single-threaded numpy, on bands of rows of the
     same workload until about `seconds` of CPU work; scaled to px-members/s."""
@@ -278,6 +334,10 @@ def main():
     ap.add_argument("--stream-reps", type=int, default=3)
     ap.add_argument("--no-streamed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=20.0,
+                    help="length of the open-loop served schedule (0 skips it)")
+    ap.add_argument("--spill-seconds", type=float, default=1.0,
+                    help="length of the served run with half the sessions' HBM budget")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy of 1 GiB (torch.neg on int32) "
@@ -358,6 +418,9 @@ def main():
     if not args.no_batched:
         log("batched", synth.BATCHED.name)
         out["batched"] = run_batched(torch, args.stream_reps + 2)
+    if args.served_seconds > 0:
+        log("served", synth.SERVED.name)
+        out["served"] = run_served(torch, args.served_seconds, args.spill_seconds)
     log("cpu baseline")
     out["cpu_baseline"] = cpu_baseline(ens, e, args.cpu_seconds)
     out["host"] = {"cpu": platform.processor() or platform.machine(),

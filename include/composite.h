@@ -247,6 +247,107 @@ int composite_batch_run(cmp_pool *pool, const cmp_request *reqs, int32_t nreq,
  * excluded), and the number of work items it ran. */
 int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items);
 
+/* ------------------------------------------------------------------------
+ * Served sessions: interactive add/remove against per-session composites.
+ *
+ * Each session is one user's working set (Figure 1: surfaces are added and
+ * removed in real time, and the composite follows) over the rasters of a
+ * pool, with its own device-resident uint32 count composite of the pool's
+ * W x H.  A request adds or removes pool members and asks for a viewport of
+ * the updated composite.  One server thread batches continuously: every step
+ * takes the oldest queued request of each session (at most max_batch), runs
+ * one launch that updates all their composites and writes their viewports to
+ * device staging, and queues the copies of the viewports to host memory on a
+ * second stream, so the next step's launch overlaps them.  Requests of one
+ * session are applied in submission order; sessions interleave.  Session
+ * composites live in a device slab of hbm_budget_bytes; when a request needs
+ * a session that is not resident and the slab is full, the least recently
+ * used session that is not part of the step is spilled to pinned host memory
+ * (and restored when it is next needed).
+ */
+typedef struct cmp_server cmp_server;
+
+enum cmp_op { CMP_OP_ADD = 0, CMP_OP_REMOVE = 1 };
+
+typedef struct cmp_server_opts {
+  int64_t hbm_budget_bytes; /* device bytes for resident session composites;
+                               at least one composite (W*H*4).  Default 16 GiB */
+  int32_t max_sessions;     /* open sessions at most.  Default 1024 */
+  int32_t max_batch;        /* requests per step, 1 .. 4096; 1 = unbatched FIFO.
+                               Default 64 */
+  int32_t max_view_pixels;  /* largest viewport w*h accepted.  Default 2^20 */
+  int32_t tile_vecs;        /* 16-pixel vectors per work item.  Default 1024 */
+  int32_t blocks_per_cu;    /* persistent workgroups per compute unit.  Default 8 */
+  int32_t overlap;          /* 1: a step may launch while the previous step's
+                               viewports are still being copied out; 0: each
+                               step completes before the next starts.
+                               Default 1 */
+  int32_t reserved[6];      /* must be zero */
+} cmp_server_opts;
+
+void composite_default_server_opts(cmp_server_opts *opts);
+
+/* Creates a server over the rasters of `pool` (W must be a multiple of 16;
+ * the pool must outlive the server).  Allocates the composite slab and the
+ * staging buffers up front; the serving loop allocates only a session's
+ * pinned spill buffer, on its first spill. */
+int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_opts *opts);
+
+/* Finishes every submitted request, stops the server and frees it.  NULL is
+ * ignored. */
+void composite_server_free(cmp_server *srv);
+
+/* Opens a session with an empty working set (all-zero composite).
+ * CMP_ENOMEM when max_sessions are open. */
+int composite_session_open(cmp_server *srv, int64_t *sid_out);
+
+/* Closes a session; CMP_EBUSY while it has unfinished requests. */
+int composite_session_close(cmp_server *srv, int64_t sid);
+
+/* Queues one request: op (cmp_op) of n pool ids, then the viewport
+ * (vx0, vy0, vw, vh) of the session's count composite copied to dst (host
+ * memory allocated page-locked, vh rows of vw uint32 with dst_pitch elements
+ * between rows).  The request is validated against the session's working set
+ * as it will be after all its earlier requests: removing an id it will not
+ * hold gives CMP_ENOTMEMBER.  Thread-safe; returns without waiting.  *ticket
+ * identifies the request to composite_session_wait.  dst must stay valid and
+ * untouched until the request completes. */
+int composite_session_submit(cmp_server *srv, int64_t sid, int32_t op, const int32_t *ids,
+                             int32_t n, int32_t vx0, int32_t vy0, int32_t vw, int32_t vh,
+                             uint32_t *dst, int64_t dst_pitch, uint64_t *ticket);
+
+/* Waits until the request is complete (its viewport is in dst) or timeout_us
+ * passes (CMP_ETIMEDOUT; negative waits forever).  Optionally returns the
+ * submit and completion times (CLOCK_MONOTONIC nanoseconds). */
+int composite_session_wait(cmp_server *srv, uint64_t ticket, int64_t timeout_us,
+                           int64_t *t_submit_ns, int64_t *t_done_ns);
+
+typedef struct cmp_server_stats {
+  int64_t requests, steps, max_step, spills, restores, resident_slots;
+  double device_ms;          /* summed device time of the update launches */
+} cmp_server_stats;
+
+int composite_server_stats(cmp_server *srv, cmp_server_stats *st);
+
+/* One request of an open-loop replay: t_ns is its arrival time after the
+ * replay starts; its ids are ids[ids_off .. ids_off + n). */
+typedef struct cmp_replay_req {
+  int64_t t_ns;
+  int64_t sid;
+  int64_t ids_off;
+  int32_t op, n;
+  int32_t vx0, vy0, vw, vh;
+} cmp_replay_req;
+
+/* Submits the requests at their arrival times from the calling thread (an
+ * open-loop Poisson schedule does not wait for completions), then waits for
+ * all of them.  Request i copies its viewport to dst_ring[i % ring] (pinned
+ * host buffers of at least vh * dst_pitch uint32).  latency_ns[i] = completion
+ * time - scheduled arrival time.  Returns the first failing status. */
+int composite_server_replay(cmp_server *srv, const cmp_replay_req *reqs, int64_t nreq,
+                            const int32_t *ids, uint32_t *const *dst_ring, int32_t ring,
+                            int64_t dst_pitch, int64_t *latency_ns);
+
 /* Static description of a status code; never NULL. */
 const char *composite_strerror(int status);
 

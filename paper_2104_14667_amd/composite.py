@@ -48,6 +48,26 @@ class cmp_tune(C.Structure):
 
 
 CMP_BATCH_PERSISTENT, CMP_BATCH_PER_REQUEST = 0, 1
+CMP_OP_ADD, CMP_OP_REMOVE = 0, 1
+
+
+class cmp_server_opts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_sessions", C.c_int32),
+                ("max_batch", C.c_int32), ("max_view_pixels", C.c_int32),
+                ("tile_vecs", C.c_int32), ("blocks_per_cu", C.c_int32), ("overlap", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+class cmp_server_stats(C.Structure):
+    _fields_ = [("requests", C.c_int64), ("steps", C.c_int64), ("max_step", C.c_int64),
+                ("spills", C.c_int64), ("restores", C.c_int64), ("resident_slots", C.c_int64),
+                ("device_ms", C.c_double)]
+
+
+class cmp_replay_req(C.Structure):
+    _fields_ = [("t_ns", C.c_int64), ("sid", C.c_int64), ("ids_off", C.c_int64),
+                ("op", C.c_int32), ("n", C.c_int32), ("vx0", C.c_int32), ("vy0", C.c_int32),
+                ("vw", C.c_int32), ("vh", C.c_int32)]
 
 
 class CompositeError(RuntimeError):
@@ -84,6 +104,17 @@ _SIGS = {
     "composite_default_tune": (None, [_P(cmp_tune)]),
     "composite_batch_run": (C.c_int, [_vp, _P(cmp_request), _i32, _P(cmp_tune)]),
     "composite_batch_last": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
+    "composite_default_server_opts": (None, [_P(cmp_server_opts)]),
+    "composite_server_create": (C.c_int, [_P(_vp), _vp, _P(cmp_server_opts)]),
+    "composite_server_free": (None, [_vp]),
+    "composite_session_open": (C.c_int, [_vp, _P(_i64)]),
+    "composite_session_close": (C.c_int, [_vp, _i64]),
+    "composite_session_submit": (C.c_int, [_vp, _i64, _i32, _P(_i32), _i32, _i32, _i32, _i32,
+                                           _i32, _vp, _i64, _P(C.c_uint64)]),
+    "composite_session_wait": (C.c_int, [_vp, C.c_uint64, _i64, _P(_i64), _P(_i64)]),
+    "composite_server_stats": (C.c_int, [_vp, _P(cmp_server_stats)]),
+    "composite_server_replay": (C.c_int, [_vp, _P(cmp_replay_req), _i64, _P(_i32), _P(_vp),
+                                          _i32, _i64, _P(_i64)]),
     "composite_strerror": (C.c_char_p, [C.c_int]),
     "composite_free": (None, [_vp]),
 }
@@ -372,6 +403,105 @@ class Pool:
     def close(self):
         if self.handle:
             composite_pool_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- served sessions
+
+def composite_default_server_opts() -> cmp_server_opts:
+    o = cmp_server_opts()
+    lib.composite_default_server_opts(C.byref(o))
+    return o
+
+
+class Server:
+    """Continuous-batching server of add/remove/viewport requests over a pool."""
+
+    def __init__(self, pool: Pool, **opts):
+        o = composite_default_server_opts()
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.opts = o
+        self.pool = pool
+        h = C.c_void_p()
+        _check(lib.composite_server_create(C.byref(h), pool.handle, C.byref(o)),
+               "composite_server_create")
+        self.handle = h.value
+
+    def open(self) -> int:
+        sid = C.c_int64()
+        _check(lib.composite_session_open(self.handle, C.byref(sid)), "composite_session_open")
+        return sid.value
+
+    def close_session(self, sid: int) -> None:
+        _check(lib.composite_session_close(self.handle, int(sid)), "composite_session_close")
+
+    def submit(self, sid: int, op: int, ids, viewport, dst, pitch: Optional[int] = None) -> int:
+        """dst: page-locked host memory (a pinned torch tensor or its address)."""
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int32))
+        vx0, vy0, vw, vh = viewport
+        t = C.c_uint64()
+        _check(lib.composite_session_submit(
+            self.handle, int(sid), int(op),
+            ids.ctypes.data_as(C.POINTER(C.c_int32)) if ids.size else None, int(ids.size),
+            int(vx0), int(vy0), int(vw), int(vh), _ptr(dst),
+            int(pitch if pitch is not None else vw), C.byref(t)), "composite_session_submit")
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        ts, td = C.c_int64(), C.c_int64()
+        _check(lib.composite_session_wait(self.handle, C.c_uint64(ticket), int(timeout_us),
+                                          C.byref(ts), C.byref(td)), "composite_session_wait")
+        return ts.value, td.value
+
+    def stats(self) -> dict:
+        st = cmp_server_stats()
+        _check(lib.composite_server_stats(self.handle, C.byref(st)), "composite_server_stats")
+        return {k: getattr(st, k) for k, _ in cmp_server_stats._fields_}
+
+    def replay(self, schedule, sid_of, dst_ring, pitch: int) -> np.ndarray:
+        """Open-loop replay of requests (dicts t, sid, op, ids, vx0, vy0, vw, vh,
+        as made by synth.ServeWorkload.schedule); sid_of maps the schedule's
+        session index to a server session id.  Returns latency in ns per
+        request (completion time minus scheduled arrival)."""
+        n = len(schedule)
+        reqs = (cmp_replay_req * n)()
+        ids_all = []
+        off = 0
+        for i, r in enumerate(schedule):
+            q = reqs[i]
+            q.t_ns = int(round(r["t"] * 1e9))
+            q.sid = int(sid_of[r["sid"]])
+            q.op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
+            q.n = len(r["ids"])
+            q.ids_off = off
+            q.vx0, q.vy0, q.vw, q.vh = int(r["vx0"]), int(r["vy0"]), int(r["vw"]), int(r["vh"])
+            ids_all.append(np.asarray(r["ids"], dtype=np.int32))
+            off += q.n
+        ids = np.ascontiguousarray(np.concatenate(ids_all) if ids_all else np.zeros(1, np.int32))
+        ring = (C.c_void_p * len(dst_ring))(*[_ptr(d) for d in dst_ring])
+        lat = np.zeros(n, dtype=np.int64)
+        rc = lib.composite_server_replay(self.handle, reqs, n, ids.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         ring, len(dst_ring), int(pitch),
+                                         lat.ctypes.data_as(C.POINTER(C.c_int64)))
+        _check(rc, "composite_server_replay")
+        return lat
+
+    def close(self):
+        if self.handle:
+            lib.composite_server_free(self.handle)
             self.handle = None
 
     def __enter__(self):

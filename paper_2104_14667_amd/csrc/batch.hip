@@ -20,7 +20,8 @@
 #include <vector>
 
 #include "../../include/composite.h"
-#include "kernels.h"
+#include "lanes.h"
+#include "pool.h"
 
 namespace {
 
@@ -43,36 +44,6 @@ struct Header {
 };
 static_assert(sizeof(Header) == 64, "arena header is 64 bytes");
 
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4u __attribute__((ext_vector_type(4), aligned(1)));
-typedef const __attribute__((address_space(1))) u32x4u gu32x4u;
-
-__device__ __forceinline__ uint4 ldv(const uint8_t *base, uint32_t off) {
-  const u32x4u v = __builtin_nontemporal_load((gu32x4u *)(base + off));
-  return make_uint4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ uint32_t pmin1(uint32_t a) {
-  uint32_t r;
-  asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(a), "s"(0x00010001u));
-  return r;
-}
-// count of nonzero bytes of x into packed 16-bit lanes c[8] (pixel order as
-// in the main compositing kernel: lanes of dword k hold pixels 4k,4k+2 and
-// 4k+1,4k+3)
-__device__ __forceinline__ void fold_count(const uint4 x, uint32_t *c) {
-  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    c[2 * k] += pmin1(__builtin_amdgcn_perm(0u, w[k], 0x0c020c00u));
-    c[2 * k + 1] += pmin1(__builtin_amdgcn_perm(0u, w[k], 0x0c030c01u));
-  }
-}
-__device__ __forceinline__ uint32_t lane_px(const uint32_t *a, int j) {
-  const int k = j >> 2, r = j & 3;
-  const uint32_t d = a[2 * k + (r & 1)];
-  return (r & 2) ? (d >> 16) : (d & 0xffffu);
-}
-
 // Counts of one 16-pixel vector of a request: pixels (y, x .. x+15) of the
 // pool rasters ids[0..n), written to out[0..valid).
 __device__ __forceinline__ void crop_vector(const uint8_t *__restrict__ base, int64_t stride,
@@ -84,18 +55,19 @@ __device__ __forceinline__ void crop_vector(const uint8_t *__restrict__ base, in
   for (int j = 0; j < 16; ++j) cnt[j] = 0u;
   for (int g0 = 0; g0 < n; g0 += cmp::kGroup) {
     const int g1 = min(n, g0 + cmp::kGroup);
-    uint32_t c[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    cmp::Acc<cmp::kCount> a;
+    a.zero();
     int i = g0;
     for (; i + U <= g1; i += U) {
       uint4 x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = ldv(base + (int64_t)ids[i + u] * stride, off);
+      for (int u = 0; u < U; ++u) x[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
 #pragma unroll
-      for (int u = 0; u < U; ++u) fold_count(x[u], c);
+      for (int u = 0; u < U; ++u) a.fold(x[u]);
     }
-    for (; i < g1; ++i) fold_count(ldv(base + (int64_t)ids[i] * stride, off), c);
+    for (; i < g1; ++i) a.fold(cmp::ld16(base + (int64_t)ids[i] * stride, off));
 #pragma unroll
-    for (int j = 0; j < 16; ++j) cnt[j] += lane_px(c, j);
+    for (int j = 0; j < 16; ++j) cnt[j] += cmp::lane_px(a.c, j);
   }
   if (valid == 16) {
 #pragma unroll
@@ -153,22 +125,7 @@ int64_t align64(int64_t x) { return (x + 63) / 64 * 64; }
 
 }  // namespace
 
-struct cmp_pool {
-  int dev = 0;
-  const uint8_t *base = nullptr;
-  int64_t count = 0, stride = 0, bytes = 0;
-  int32_t W = 0, H = 0;
-  int cus = 0;
-  bool poisoned = false;
-  hipStream_t s = nullptr;
-  char *d_arena = nullptr, *h_arena = nullptr;
-  int64_t arena_cap = 0;
-  uint32_t *d_queue = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  double last_ms = 0.0;
-  int64_t last_items = 0;
-  std::map<int, hipGraphExec_t> graphs;  // by grid size; they capture d_arena
-};
+
 
 namespace {
 

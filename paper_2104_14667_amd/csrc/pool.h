@@ -1,0 +1,24 @@
+// The pool of device-resident rasters behind composite_pool_* (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+
+struct cmp_pool {
+  int dev = 0;
+  const uint8_t *base = nullptr;
+  int64_t count = 0, stride = 0, bytes = 0;
+  int32_t W = 0, H = 0;
+  int cus = 0;
+  bool poisoned = false;
+  hipStream_t s = nullptr;
+  char *d_arena = nullptr, *h_arena = nullptr;
+  int64_t arena_cap = 0;
+  uint32_t *d_queue = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
+  int64_t last_items = 0;
+  std::map<int, hipGraphExec_t> graphs;  // by grid size; they capture d_arena
+};

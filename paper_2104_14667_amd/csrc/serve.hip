@@ -1,0 +1,699 @@
+// Served sessions (composite_server_*, composite_session_*): continuous
+// batching of interactive add/remove requests against per-session
+// device-resident count composites.
+//
+// Threads:
+//   submitters (any)  validate a request against the session's projected
+//                     working set and append it to the queue;
+//   worker            forms a step from the queue (the oldest request of each
+//                     session, at most max_batch), makes the step's sessions
+//                     resident, uploads the step's descriptors and launches
+//                     one update kernel on the compute stream; the copy
+//                     stream then moves the viewports to host memory;
+//   completer         waits for each step's copies in order and completes its
+//                     requests (timestamps, waiters).
+// At most two steps are in flight; their descriptors, staging and events
+// alternate between two halves.  With overlap = 0 the worker waits for each
+// step to complete before forming the next (the unbatched FIFO baseline uses
+// max_batch = 1 and overlap = 0).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/composite.h"
+#include "lanes.h"
+#include "pool.h"
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct SReq {
+  uint32_t *comp;     // session composite (device)
+  uint32_t *stage;    // viewport staging (device), vh rows of vw
+  int32_t sub, ids_off, n;
+  int32_t vx0, vy0, vw, vh;
+  int32_t pad;
+};
+struct SItem {
+  int32_t req, row0, nrows, pad;
+};
+struct SHeader {
+  int32_t nitems, nreq;
+  int64_t reqs_off, items_off, ids_off;
+  int64_t pad[4];
+};
+static_assert(sizeof(SHeader) == 64, "arena header is 64 bytes");
+
+// One work item: rows [row0, row0 + nrows) of a session composite.  Each thread
+// updates 16 pixels (count +/- the nonzero members) and copies the pixels that
+// fall in the request's viewport to staging.
+__global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base, int64_t stride,
+                                               int32_t W, const char *__restrict__ arena,
+                                               uint32_t *__restrict__ queue) {
+  const SHeader *hd = reinterpret_cast<const SHeader *>(arena);
+  const int nitems = hd->nitems;
+  const SReq *reqs = reinterpret_cast<const SReq *>(arena + hd->reqs_off);
+  const SItem *items = reinterpret_cast<const SItem *>(arena + hd->items_off);
+  const int32_t *ids_all = reinterpret_cast<const int32_t *>(arena + hd->ids_off);
+  const int nvr = W >> 4;
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= nitems) break;  // the queue counter only grows: every wave exits
+    const SItem I = items[it];
+    const SReq R = reqs[I.req];
+    const int32_t *ids = ids_all + R.ids_off;
+    const int total = I.nrows * nvr;
+    for (int v = threadIdx.x; v < total; v += blockDim.x) {
+      const int row = v / nvr, j = v - row * nvr;
+      const int y = I.row0 + row, x = 16 * j;
+      const uint32_t off = (uint32_t)y * (uint32_t)W + (uint32_t)x;
+      uint32_t cnt[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) cnt[k] = 0u;
+      for (int g0 = 0; g0 < R.n; g0 += cmp::kGroup) {
+        const int g1 = min(R.n, g0 + cmp::kGroup);
+        cmp::Acc<cmp::kCount> a;
+        a.zero();
+        int i = g0;
+        for (; i + 4 <= g1; i += 4) {
+          uint4 xs[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a.fold(xs[u]);
+        }
+        for (; i < g1; ++i) a.fold(cmp::ld16(base + (int64_t)ids[i] * stride, off));
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cnt[k] += cmp::lane_px(a.c, k);
+      }
+      uint4 *c = reinterpret_cast<uint4 *>(R.comp + off);
+      uint32_t nv[16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint4 o = c[q];
+        if (R.sub) {
+          o.x -= cnt[4 * q]; o.y -= cnt[4 * q + 1]; o.z -= cnt[4 * q + 2]; o.w -= cnt[4 * q + 3];
+        } else {
+          o.x += cnt[4 * q]; o.y += cnt[4 * q + 1]; o.z += cnt[4 * q + 2]; o.w += cnt[4 * q + 3];
+        }
+        c[q] = o;
+        nv[4 * q] = o.x; nv[4 * q + 1] = o.y; nv[4 * q + 2] = o.z; nv[4 * q + 3] = o.w;
+      }
+      if (y >= R.vy0 && y < R.vy0 + R.vh && x + 16 > R.vx0 && x < R.vx0 + R.vw) {
+        const int64_t row_base = (int64_t)(y - R.vy0) * R.vw;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (x + k >= R.vx0 && x + k < R.vx0 + R.vw) R.stage[row_base + (x + k - R.vx0)] = nv[k];
+      }
+    }
+  }
+}
+
+struct Request {
+  uint64_t ticket;
+  int64_t sid;
+  int32_t op;
+  std::vector<int32_t> ids;
+  int32_t vx0, vy0, vw, vh;
+  uint32_t *dst;
+  int64_t pitch;
+  int64_t t_submit;
+};
+
+struct Session {
+  bool open = false;
+  int slot = -1;            // resident slot or -1
+  bool has_data = false;    // false: all zero (new); true: data in slot or spill
+  uint32_t *spill = nullptr;  // pinned host copy while not resident
+  std::unordered_map<int32_t, int64_t> projected;  // working set after queued requests
+  int64_t inflight = 0;     // requests submitted and not completed
+  uint64_t last_use = 0;
+};
+
+struct Done {
+  int64_t t_submit, t_done;
+};
+
+struct Step {
+  std::vector<uint64_t> tickets;
+  std::vector<int64_t> sids;
+  int half;
+  uint64_t index;
+};
+
+}  // namespace
+
+struct cmp_server {
+  cmp_pool *pool = nullptr;
+  cmp_server_opts o{};
+  int dev = 0;
+  int32_t W = 0, H = 0;
+  int64_t comp_bytes = 0;
+  hipStream_t comp = nullptr, copy = nullptr;
+  uint32_t *slab = nullptr;
+  std::vector<int64_t> slot_owner;  // session id per slot, or -1
+  uint32_t *d_queue = nullptr;
+  // per half: descriptor arena (pinned + device), viewport staging, events
+  char *h_arena[2] = {nullptr, nullptr};
+  char *d_arena[2] = {nullptr, nullptr};
+  int64_t arena_cap = 0;
+  uint32_t *stage[2] = {nullptr, nullptr};
+  hipEvent_t ev_k0[2] = {nullptr, nullptr}, ev_k1[2] = {nullptr, nullptr};
+  hipEvent_t ev_copied[2] = {nullptr, nullptr};
+
+  std::mutex mu;
+  std::condition_variable cv_queue, cv_done, cv_steps;
+  std::deque<Request> queue;
+  std::unordered_map<int64_t, Session> sessions;
+  int64_t next_sid = 1;
+  int64_t open_sessions = 0;
+  uint64_t next_ticket = 1;
+  std::unordered_map<uint64_t, Done> done;
+  std::unordered_set<uint64_t> pending;
+  std::deque<Step> steps;        // launched, not completed (for the completer)
+  uint64_t steps_launched = 0, steps_completed = 0;
+  uint64_t use_clock = 0;
+  bool stop = false;
+  bool worker_done = false;
+  int failed = CMP_OK;           // sticky device failure
+  cmp_server_stats st{};
+  std::thread worker, completer;
+};
+
+namespace {
+
+void fail(cmp_server *s, int rc) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->failed == CMP_OK) s->failed = rc;
+  s->cv_done.notify_all();
+  s->cv_steps.notify_all();
+}
+
+// Makes `sid` resident.  Called by the worker with the server lock held.
+hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
+                         const std::unordered_set<int64_t> &in_step) {
+  if (ss.slot >= 0) return hipSuccess;
+  int slot = -1;
+  for (size_t i = 0; i < s->slot_owner.size(); ++i)
+    if (s->slot_owner[i] < 0) {
+      slot = (int)i;
+      break;
+    }
+  if (slot < 0) {
+    // spill the least recently used resident session outside this step
+    int64_t victim = -1;
+    uint64_t oldest = UINT64_MAX;
+    for (size_t i = 0; i < s->slot_owner.size(); ++i) {
+      const int64_t v = s->slot_owner[i];
+      if (in_step.count(v)) continue;
+      const uint64_t lu = s->sessions[v].last_use;
+      if (lu < oldest) {
+        oldest = lu;
+        victim = v;
+        slot = (int)i;
+      }
+    }
+    if (victim < 0) return hipErrorOutOfMemory;  // cannot happen: slots >= max_batch
+    Session &vs = s->sessions[victim];
+    if (!vs.spill) {
+      hipError_t e = hipHostMalloc((void **)&vs.spill, s->comp_bytes, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+    }
+    // ordered after every kernel that wrote the slot (same stream)
+    hipError_t e = hipMemcpyAsync(vs.spill, s->slab + (int64_t)slot * (s->comp_bytes / 4),
+                                  s->comp_bytes, hipMemcpyDeviceToHost, s->comp);
+    if (e != hipSuccess) return e;
+    vs.slot = -1;
+    s->slot_owner[slot] = -1;
+    s->st.spills += 1;
+  }
+  uint32_t *dst = s->slab + (int64_t)slot * (s->comp_bytes / 4);
+  hipError_t e;
+  if (ss.has_data && ss.spill) {
+    e = hipMemcpyAsync(dst, ss.spill, s->comp_bytes, hipMemcpyHostToDevice, s->comp);
+    s->st.restores += 1;
+  } else {
+    e = cmp::launch_fill(dst, 0, s->comp_bytes, s->comp);
+  }
+  if (e != hipSuccess) return e;
+  ss.slot = slot;
+  ss.has_data = true;
+  s->slot_owner[slot] = sid;
+  return hipSuccess;
+}
+
+void worker_body(cmp_server *s);
+
+void worker_loop(cmp_server *s) {
+  hipSetDevice(s->dev);
+  worker_body(s);
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->worker_done = true;
+  s->cv_steps.notify_all();
+  s->cv_done.notify_all();
+}
+
+void worker_body(cmp_server *s) {
+  const int64_t view_stride = s->o.max_view_pixels;  // uint32 per staging slot
+  for (;;) {
+    std::vector<Request> step;
+    uint64_t index;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_queue.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      if (s->queue.empty() && s->stop) return;
+      if (s->failed != CMP_OK) return;
+      index = s->steps_launched;
+      // both halves busy, or (no overlap) the previous step still running
+      const uint64_t need = s->o.overlap ? (index >= 2 ? index - 1 : 0) : index;
+      s->cv_steps.wait(lk, [&] { return s->steps_completed >= need || s->failed != CMP_OK; });
+      if (s->failed != CMP_OK) return;
+      std::unordered_set<int64_t> taken;
+      for (auto it = s->queue.begin(); it != s->queue.end() && (int)step.size() < s->o.max_batch;) {
+        if (taken.insert(it->sid).second) {
+          step.push_back(std::move(*it));
+          it = s->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    const int half = (int)(index & 1);
+    std::unordered_set<int64_t> in_step;
+    for (auto &r : step) in_step.insert(r.sid);
+    // residency and descriptors (slots are touched by this thread only)
+    std::vector<SReq> rd(step.size());
+    std::vector<SItem> items;
+    int64_t nids = 0;
+    hipError_t e = hipSuccess;
+    // Residency changes hold the lock: sessions may be opened and closed
+    // concurrently, and a close releases the slot of an idle session.
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (auto &r : step) s->sessions[r.sid].last_use = ++s->use_clock;
+    for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
+      Request &r = step[k];
+      Session *ss = &s->sessions[r.sid];
+      e = make_resident(s, *ss, r.sid, in_step);
+      SReq &d = rd[k];
+      d.comp = s->slab + (int64_t)ss->slot * (s->comp_bytes / 4);
+      d.stage = s->stage[half] + (int64_t)k * view_stride;
+      d.sub = r.op == CMP_OP_REMOVE;
+      d.ids_off = (int32_t)nids;
+      d.n = (int32_t)r.ids.size();
+      d.vx0 = r.vx0;
+      d.vy0 = r.vy0;
+      d.vw = r.vw;
+      d.vh = r.vh;
+      d.pad = 0;
+      nids += d.n;
+      const int nvr = s->W / 16;
+      const int rows = std::max(1, s->o.tile_vecs / nvr);
+      for (int r0 = 0; r0 < s->H; r0 += rows) items.push_back(SItem{(int32_t)k, r0, std::min(rows, s->H - r0), 0});
+    }
+    lk.unlock();
+    if (e != hipSuccess) {
+      fail(s, CMP_EDEVICE);
+      return;
+    }
+    SHeader hd{};
+    hd.nitems = (int32_t)items.size();
+    hd.nreq = (int32_t)step.size();
+    hd.reqs_off = 64;
+    hd.items_off = (hd.reqs_off + (int64_t)sizeof(SReq) * rd.size() + 63) / 64 * 64;
+    hd.ids_off = (hd.items_off + (int64_t)sizeof(SItem) * items.size() + 63) / 64 * 64;
+    const int64_t bytes = hd.ids_off + 4 * nids;
+    if (bytes > s->arena_cap) {
+      fail(s, CMP_ENOMEM);
+      return;
+    }
+    char *h = s->h_arena[half];
+    std::memcpy(h, &hd, sizeof(hd));
+    std::memcpy(h + hd.reqs_off, rd.data(), sizeof(SReq) * rd.size());
+    std::memcpy(h + hd.items_off, items.data(), sizeof(SItem) * items.size());
+    for (size_t k = 0; k < step.size(); ++k)
+      if (!step[k].ids.empty())
+        std::memcpy(h + hd.ids_off + 4 * (int64_t)rd[k].ids_off, step[k].ids.data(), 4 * step[k].ids.size());
+    const int grid = s->pool->cus * s->o.blocks_per_cu;
+    e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
+    if (e == hipSuccess) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
+    if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);
+    if (e == hipSuccess) {
+      k_serve<<<grid, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half],
+                                          s->d_queue);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(s->ev_k1[half], s->comp);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->copy, s->ev_k1[half], 0);
+    for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
+      const Request &r = step[k];
+      e = hipMemcpy2DAsync(r.dst, (size_t)r.pitch * 4, rd[k].stage, (size_t)r.vw * 4,
+                           (size_t)r.vw * 4, (size_t)r.vh, hipMemcpyDeviceToHost, s->copy);
+    }
+    if (e == hipSuccess) e = hipEventRecord(s->ev_copied[half], s->copy);
+    if (e != hipSuccess) {
+      fail(s, CMP_EDEVICE);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      Step st;
+      st.half = half;
+      st.index = index;
+      for (auto &r : step) {
+        st.tickets.push_back(r.ticket);
+        st.sids.push_back(r.sid);
+      }
+      s->steps.push_back(std::move(st));
+      s->steps_launched += 1;
+      s->st.steps += 1;
+      s->st.max_step = std::max<int64_t>(s->st.max_step, (int64_t)step.size());
+    }
+    s->cv_steps.notify_all();
+  }
+}
+
+void completer_loop(cmp_server *s) {
+  hipSetDevice(s->dev);
+  for (;;) {
+    Step st;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_steps.wait(lk, [&] { return !s->steps.empty() || s->worker_done || s->failed != CMP_OK; });
+      if (s->steps.empty()) {
+        if (s->worker_done || s->failed != CMP_OK) return;
+        continue;
+      }
+      st = s->steps.front();
+    }
+    const hipError_t e = hipEventSynchronize(s->ev_copied[st.half]);
+    const int64_t t = now_ns();
+    float ms = 0.f;
+    const hipError_t e2 = e == hipSuccess ? hipEventElapsedTime(&ms, s->ev_k0[st.half], s->ev_k1[st.half]) : e;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->steps.pop_front();
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (s->failed == CMP_OK) s->failed = CMP_EDEVICE;
+    }
+    s->st.device_ms += ms;
+    for (size_t k = 0; k < st.tickets.size(); ++k) {
+      auto it = s->done.find(st.tickets[k]);
+      if (it != s->done.end()) it->second.t_done = t;
+      s->pending.erase(st.tickets[k]);
+      s->sessions[st.sids[k]].inflight -= 1;
+      s->st.requests += 1;
+    }
+    s->steps_completed += 1;
+    s->cv_done.notify_all();
+    s->cv_steps.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void composite_default_server_opts(cmp_server_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->hbm_budget_bytes = int64_t(16) << 30;
+  o->max_sessions = 1024;
+  o->max_batch = 64;
+  o->max_view_pixels = 1 << 20;
+  o->tile_vecs = 1024;
+  o->blocks_per_cu = 8;
+  o->overlap = 1;
+}
+
+int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_opts *opts) {
+  if (!out) return CMP_EINVAL;
+  *out = nullptr;
+  if (!pool) return CMP_EINVAL;
+  cmp_server_opts o;
+  composite_default_server_opts(&o);
+  if (opts) o = *opts;
+  for (int r : o.reserved)
+    if (r) return CMP_EINVAL;
+  if (pool->W % 16) return CMP_EUNSUPPORTED;
+  const int64_t comp_bytes = (int64_t)pool->W * pool->H * 4;
+  if (o.max_batch < 1 || o.max_batch > 4096 || o.max_sessions < 1 || o.max_view_pixels < 1 ||
+      o.tile_vecs < 64 || o.tile_vecs > 65536 || o.blocks_per_cu < 1 || o.blocks_per_cu > 16 ||
+      (o.overlap != 0 && o.overlap != 1))
+    return CMP_EINVAL;
+  // a step must fit in the slab: at least max_batch resident composites
+  if (o.hbm_budget_bytes / comp_bytes < o.max_batch) return CMP_EINVAL;
+  cmp_server *s = new (std::nothrow) cmp_server();
+  if (!s) return CMP_ENOMEM;
+  s->pool = pool;
+  s->o = o;
+  s->dev = pool->dev;
+  s->W = pool->W;
+  s->H = pool->H;
+  s->comp_bytes = comp_bytes;
+  const int64_t nslots = std::min<int64_t>(o.hbm_budget_bytes / comp_bytes, o.max_sessions);
+  int rc = CMP_EDEVICE;
+  do {
+    if (hipSetDevice(s->dev) != hipSuccess) break;
+    if (hipStreamCreateWithFlags(&s->comp, hipStreamNonBlocking) != hipSuccess) break;
+    if (hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess) break;
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i)
+      ok = hipEventCreate(&s->ev_k0[i]) == hipSuccess && hipEventCreate(&s->ev_k1[i]) == hipSuccess &&
+           hipEventCreateWithFlags(&s->ev_copied[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) break;
+    rc = CMP_ENOMEM;
+    if (hipMalloc((void **)&s->slab, nslots * comp_bytes) != hipSuccess) break;
+    s->slot_owner.assign(nslots, -1);
+    if (hipMalloc((void **)&s->d_queue, 64) != hipSuccess) break;
+    const int64_t nvr = s->W / 16;
+    const int64_t rows = std::max<int64_t>(1, o.tile_vecs / nvr);
+    const int64_t items = (int64_t)o.max_batch * ((s->H + rows - 1) / rows);
+    // ids per request are capped at 65535 by submit
+    s->arena_cap = 64 + 64 + (int64_t)sizeof(SReq) * o.max_batch + 64 + (int64_t)sizeof(SItem) * items +
+                   4 * (int64_t)o.max_batch * 65535;
+    for (int i = 0; i < 2 && rc == CMP_ENOMEM; ++i) {
+      if (hipHostMalloc((void **)&s->h_arena[i], s->arena_cap, hipHostMallocDefault) != hipSuccess ||
+          hipMalloc((void **)&s->d_arena[i], s->arena_cap) != hipSuccess ||
+          hipMalloc((void **)&s->stage[i], (int64_t)o.max_batch * o.max_view_pixels * 4) != hipSuccess) {
+        rc = -100;  // marker: allocation failed
+      }
+    }
+    if (rc == -100) {
+      rc = CMP_ENOMEM;
+      break;
+    }
+    s->st.resident_slots = nslots;
+    rc = CMP_OK;
+  } while (false);
+  if (rc != CMP_OK) {
+    composite_server_free(s);
+    return rc;
+  }
+  s->worker = std::thread(worker_loop, s);
+  s->completer = std::thread(completer_loop, s);
+  *out = s;
+  return CMP_OK;
+}
+
+void composite_server_free(cmp_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_queue.notify_all();
+  s->cv_steps.notify_all();
+  // the worker drains the queue and exits; the completer then drains the
+  // launched steps and exits
+  if (s->worker.joinable()) s->worker.join();
+  else s->worker_done = true;
+  s->cv_steps.notify_all();
+  if (s->completer.joinable()) s->completer.join();
+  hipSetDevice(s->dev);
+  if (s->comp) hipStreamSynchronize(s->comp);
+  if (s->copy) hipStreamSynchronize(s->copy);
+  for (auto &kv : s->sessions)
+    if (kv.second.spill) hipHostFree(kv.second.spill);
+  hipFree(s->slab);
+  hipFree(s->d_queue);
+  for (int i = 0; i < 2; ++i) {
+    if (s->h_arena[i]) hipHostFree(s->h_arena[i]);
+    hipFree(s->d_arena[i]);
+    hipFree(s->stage[i]);
+    if (s->ev_k0[i]) hipEventDestroy(s->ev_k0[i]);
+    if (s->ev_k1[i]) hipEventDestroy(s->ev_k1[i]);
+    if (s->ev_copied[i]) hipEventDestroy(s->ev_copied[i]);
+  }
+  if (s->comp) hipStreamDestroy(s->comp);
+  if (s->copy) hipStreamDestroy(s->copy);
+  delete s;
+}
+
+int composite_session_open(cmp_server *s, int64_t *sid_out) {
+  if (!s || !sid_out) return CMP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->failed != CMP_OK) return s->failed;
+  if (s->open_sessions >= s->o.max_sessions) return CMP_ENOMEM;
+  const int64_t sid = s->next_sid++;
+  Session &ss = s->sessions[sid];
+  ss.open = true;
+  s->open_sessions += 1;
+  *sid_out = sid;
+  return CMP_OK;
+}
+
+int composite_session_close(cmp_server *s, int64_t sid) {
+  if (!s) return CMP_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->sessions.find(sid);
+  if (it == s->sessions.end() || !it->second.open) return CMP_EINVAL;
+  if (it->second.inflight > 0) return CMP_EBUSY;
+  // the slot is released; the worker never touches it again for this id
+  if (it->second.slot >= 0) s->slot_owner[it->second.slot] = -1;
+  uint32_t *spill = it->second.spill;
+  s->sessions.erase(it);
+  s->open_sessions -= 1;
+  lk.unlock();
+  if (spill) {
+    // a spill copy into it may still be queued on the compute stream
+    hipSetDevice(s->dev);
+    hipStreamSynchronize(s->comp);
+    hipHostFree(spill);
+  }
+  return CMP_OK;
+}
+
+int composite_session_submit(cmp_server *s, int64_t sid, int32_t op, const int32_t *ids, int32_t n,
+                             int32_t vx0, int32_t vy0, int32_t vw, int32_t vh, uint32_t *dst,
+                             int64_t dst_pitch, uint64_t *ticket) {
+  if (!s || !ticket) return CMP_EINVAL;
+  if (op != CMP_OP_ADD && op != CMP_OP_REMOVE) return CMP_EINVAL;
+  if (n < 0 || n > 65535 || (n > 0 && !ids)) return CMP_EINVAL;
+  if (vw < 1 || vh < 1 || vx0 < 0 || vy0 < 0 || (int64_t)vx0 + vw > s->W || (int64_t)vy0 + vh > s->H)
+    return CMP_EINVAL;
+  if ((int64_t)vw * vh > s->o.max_view_pixels || !dst || dst_pitch < vw) return CMP_EINVAL;
+  for (int32_t i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= s->pool->count) return CMP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->failed != CMP_OK) return s->failed;
+  if (s->stop) return CMP_EINVAL;
+  auto it = s->sessions.find(sid);
+  if (it == s->sessions.end() || !it->second.open) return CMP_EINVAL;
+  Session &ss = it->second;
+  if (op == CMP_OP_REMOVE) {
+    std::unordered_map<int32_t, int64_t> need;
+    for (int32_t i = 0; i < n; ++i) need[ids[i]] += 1;
+    for (auto &kv : need) {
+      auto h = ss.projected.find(kv.first);
+      if (h == ss.projected.end() || h->second < kv.second) return CMP_ENOTMEMBER;
+    }
+    for (auto &kv : need)
+      if ((ss.projected[kv.first] -= kv.second) == 0) ss.projected.erase(kv.first);
+  } else {
+    for (int32_t i = 0; i < n; ++i) ss.projected[ids[i]] += 1;
+  }
+  Request r;
+  r.ticket = s->next_ticket++;
+  r.sid = sid;
+  r.op = op;
+  r.ids.assign(ids, ids + n);
+  r.vx0 = vx0;
+  r.vy0 = vy0;
+  r.vw = vw;
+  r.vh = vh;
+  r.dst = dst;
+  r.pitch = dst_pitch;
+  r.t_submit = now_ns();
+  ss.inflight += 1;
+  s->done[r.ticket] = Done{r.t_submit, 0};
+  s->pending.insert(r.ticket);
+  *ticket = r.ticket;
+  s->queue.push_back(std::move(r));
+  s->cv_queue.notify_one();
+  return CMP_OK;
+}
+
+int composite_session_wait(cmp_server *s, uint64_t ticket, int64_t timeout_us, int64_t *t_submit_ns,
+                           int64_t *t_done_ns) {
+  if (!s) return CMP_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->done.find(ticket);
+  if (it == s->done.end()) return CMP_EINVAL;
+  auto ready = [&] { return !s->pending.count(ticket) || s->failed != CMP_OK; };
+  if (timeout_us < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return CMP_ETIMEDOUT;
+  }
+  if (s->pending.count(ticket)) return s->failed;
+  if (t_submit_ns) *t_submit_ns = it->second.t_submit;
+  if (t_done_ns) *t_done_ns = it->second.t_done;
+  return CMP_OK;
+}
+
+int composite_server_stats(cmp_server *s, cmp_server_stats *st) {
+  if (!s || !st) return CMP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *st = s->st;
+  return CMP_OK;
+}
+
+int composite_server_replay(cmp_server *s, const cmp_replay_req *reqs, int64_t nreq, const int32_t *ids,
+                            uint32_t *const *dst_ring, int32_t ring, int64_t dst_pitch,
+                            int64_t *latency_ns) {
+  if (!s || nreq < 0 || (nreq > 0 && (!reqs || !dst_ring || ring < 1 || !latency_ns))) return CMP_EINVAL;
+  std::vector<uint64_t> tickets(nreq, 0);
+  std::vector<int64_t> arrival(nreq, 0);
+  const int64_t t0 = now_ns();
+  int rc = CMP_OK;
+  for (int64_t i = 0; i < nreq; ++i) {
+    const cmp_replay_req &q = reqs[i];
+    const int64_t target = t0 + q.t_ns;
+    for (;;) {
+      const int64_t d = target - now_ns();
+      if (d <= 0) break;
+      if (d > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(d - 100000));
+      else std::this_thread::yield();
+    }
+    arrival[i] = target;
+    rc = composite_session_submit(s, q.sid, q.op, q.n ? ids + q.ids_off : nullptr, q.n, q.vx0, q.vy0,
+                                  q.vw, q.vh, dst_ring[i % ring], dst_pitch, &tickets[i]);
+    if (rc != CMP_OK) break;
+  }
+  const int64_t submitted = rc == CMP_OK ? nreq : std::count_if(tickets.begin(), tickets.end(),
+                                                                [](uint64_t t) { return t != 0; });
+  for (int64_t i = 0; i < submitted; ++i) {
+    int64_t ts = 0, td = 0;
+    const int w = composite_session_wait(s, tickets[i], -1, &ts, &td);
+    if (w != CMP_OK) {
+      if (rc == CMP_OK) rc = w;
+      latency_ns[i] = -1;
+      continue;
+    }
+    latency_ns[i] = td - arrival[i];
+  }
+  for (int64_t i = submitted; i < nreq; ++i) latency_ns[i] = -1;
+  return rc;
+}
+
+}  // extern "C"
