@@ -348,6 +348,28 @@ int composite_server_replay(cmp_server *srv, const cmp_replay_req *reqs, int64_t
                             const int32_t *ids, uint32_t *const *dst_ring, int32_t ring,
                             int64_t dst_pitch, int64_t *latency_ns);
 
+/* Histogram of overlap classes (Figure 1, lower-left panel: the frequency of
+ * each overlap class of the composite): bins[k] = number of pixels whose count
+ * is exactly k, for k = 0 .. nbins - 1, and *overflow = number of pixels with
+ * count >= nbins.  Needs CMP_COUNT.  bins: host array of nbins int64;
+ * 1 <= nbins <= 2^24.  Waits for work enqueued before it. */
+int composite_histogram(cmp_ctx *ctx, int64_t *bins, int32_t nbins, int64_t *overflow);
+
+/* Repacks n row-major W x H rasters (device memory, src + i * src_stride) into
+ * the tiled layout of CMP_TILED (tiles of tile_w bytes x tile_h rows, stored
+ * tile after tile; padding bytes of edge tiles are zero) at dst + i *
+ * dst_stride (device memory, at least composite_tiled_bytes each): the
+ * counterpart of the paper's buffer-to-image transform (Section 4; its rate
+ * over image dimensions is the experiment of Section 5.2).  Enqueued on
+ * `stream` (a hipStream_t, or NULL for the null stream); returns without
+ * waiting.  W must be a multiple of 16. */
+int composite_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
+                           int64_t dst_stride, int32_t n, int32_t W, int32_t H,
+                           int32_t tile_w, int32_t tile_h, void *stream);
+
+/* Bytes of one raster in the tiled layout (edge tiles padded). */
+int64_t composite_tiled_bytes(int32_t W, int32_t H, int32_t tile_w, int32_t tile_h);
+
 /* Static description of a status code; never NULL. */
 const char *composite_strerror(int status);
 

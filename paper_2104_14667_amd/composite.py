@@ -115,6 +115,9 @@ _SIGS = {
     "composite_server_stats": (C.c_int, [_vp, _P(cmp_server_stats)]),
     "composite_server_replay": (C.c_int, [_vp, _P(cmp_replay_req), _i64, _P(_i32), _P(_vp),
                                           _i32, _i64, _P(_i64)]),
+    "composite_histogram": (C.c_int, [_vp, _P(_i64), _i32, _P(_i64)]),
+    "composite_repack_tiled": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _i32, _i32, _vp]),
+    "composite_tiled_bytes": (C.c_int64, [_i32, _i32, _i32, _i32]),
     "composite_strerror": (C.c_char_p, [C.c_int]),
     "composite_free": (None, [_vp]),
 }
@@ -234,6 +237,26 @@ def composite_kernel_stats(ctx: int, reset: bool = False):
     return n.value, ms.value
 
 
+def composite_histogram(ctx: int, nbins: int):
+    bins = np.zeros(int(nbins), dtype=np.int64)
+    over = C.c_int64()
+    _check(lib.composite_histogram(ctx, bins.ctypes.data_as(C.POINTER(C.c_int64)), int(nbins),
+                                   C.byref(over)), "composite_histogram")
+    return bins, over.value
+
+
+def composite_tiled_bytes(W: int, H: int, tile_w: int, tile_h: int) -> int:
+    return int(lib.composite_tiled_bytes(int(W), int(H), int(tile_w), int(tile_h)))
+
+
+def composite_repack_tiled(src, src_stride: int, dst, dst_stride: int, n: int, W: int, H: int,
+                           tile_w: int, tile_h: int, stream=None) -> None:
+    st = None if stream is None else (stream if isinstance(stream, int) else int(stream.cuda_stream))
+    _check(lib.composite_repack_tiled(_ptr(src), int(src_stride), _ptr(dst), int(dst_stride),
+                                      int(n), int(W), int(H), int(tile_w), int(tile_h), st),
+           "composite_repack_tiled")
+
+
 def composite_free(ctx: int) -> None:
     lib.composite_free(ctx)
 
@@ -325,6 +348,10 @@ class Composite:
 
     def device_buffer(self, name: str) -> int:
         return composite_device_buffer(self.ctx, OUTPUT_BITS[name])
+
+    def histogram(self, nbins: int):
+        """(bins[nbins] of overlap classes, pixels with count >= nbins)."""
+        return composite_histogram(self.ctx, nbins)
 
 
 # ---------------------------------------------------------------- batched pool

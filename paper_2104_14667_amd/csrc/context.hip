@@ -84,6 +84,10 @@ struct cmp_ctx {
   int64_t host_members = 0;  // members that came through composite_add
   std::unordered_map<int64_t, std::vector<const uint8_t *>> held;
 
+  // Histogram counters (grown on demand).
+  unsigned long long *d_hist = nullptr;
+  int64_t hist_cap = 0;
+
   // Profiling of compositing kernels.
   std::vector<Timed> timed;
   size_t timed_used = 0;
@@ -140,6 +144,7 @@ void free_all(cmp_ctx *ctx) {
     if (ctx->ev_tab[i]) hipEventDestroy(ctx->ev_tab[i]);
   }
   if (ctx->ev_host_done) hipEventDestroy(ctx->ev_host_done);
+  hipFree(ctx->d_hist);
   for (auto &t : ctx->timed) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
@@ -744,6 +749,64 @@ int composite_kernel_stats(cmp_ctx *ctx, int64_t *launches, double *total_ms, in
     ctx->timed_launches = 0;
     ctx->timed_ms = 0.0;
   }
+  return CMP_OK;
+}
+
+int composite_histogram(cmp_ctx *ctx, int64_t *bins, int32_t nbins, int64_t *overflow) {
+  if (!ctx || !bins || !overflow) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  if (!(ctx->outs & CMP_COUNT) || nbins < 1 || nbins > (1 << 24)) return CMP_EINVAL;
+  CMP_TRY(set_device(ctx));
+  CMP_TRY(hipStreamSynchronize(ctx->copy_s));
+  if (ctx->hist_cap < nbins + 1) {
+    CMP_TRY(hipStreamSynchronize(ctx->comp_s));
+    hipFree(ctx->d_hist);
+    ctx->d_hist = nullptr;
+    ctx->hist_cap = 0;
+    if (hipMalloc((void **)&ctx->d_hist, sizeof(unsigned long long) * (nbins + 1)) != hipSuccess)
+      return CMP_ENOMEM;
+    ctx->hist_cap = nbins + 1;
+  }
+  unsigned long long *d_bins = ctx->d_hist;
+  int cus = 256;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->dev);
+  if (e == hipSuccess) e = cmp::launch_fill(d_bins, 0, sizeof(unsigned long long) * (nbins + 1), ctx->comp_s);
+  if (e == hipSuccess)
+    e = cmp::launch_histogram(ctx->d_count, ctx->count_bits == 16, ctx->npix, nbins, d_bins, cus,
+                              ctx->comp_s);
+  std::vector<unsigned long long> h(nbins + 1);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), d_bins, sizeof(unsigned long long) * (nbins + 1),
+                       hipMemcpyDeviceToHost, ctx->comp_s);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->comp_s);
+  if (e != hipSuccess) {
+    ctx->poisoned = true;
+    return CMP_EDEVICE;
+  }
+  for (int32_t k = 0; k < nbins; ++k) bins[k] = (int64_t)h[k];
+  *overflow = (int64_t)h[nbins];
+  return CMP_OK;
+}
+
+int64_t composite_tiled_bytes(int32_t W, int32_t H, int32_t tile_w, int32_t tile_h) {
+  if (W < 1 || H < 1 || tile_w < 1 || tile_h < 1) return -1;
+  cmp::Tiling tl{W, H, tile_w, tile_h};
+  return tl.plane();
+}
+
+int composite_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst, int64_t dst_stride,
+                           int32_t n, int32_t W, int32_t H, int32_t tile_w, int32_t tile_h,
+                           void *stream) {
+  if (!src || !dst || n < 0 || n > 65535 || W < 1 || H < 1) return CMP_EINVAL;
+  if (tile_w != 16 && tile_w != 32 && tile_w != 64 && tile_w != 128) return CMP_EINVAL;
+  if (tile_h < 1 || tile_h > 256) return CMP_EINVAL;
+  if (W % 16) return CMP_EUNSUPPORTED;
+  const int64_t plane = (int64_t)W * H;
+  cmp::Tiling tl{W, H, tile_w, tile_h};
+  if (plane > (int64_t(1) << 32) - 16 || src_stride < plane || dst_stride < tl.plane()) return CMP_EINVAL;
+  if (n == 0) return CMP_OK;
+  if (cmp::launch_repack_tiled(src, src_stride, dst, dst_stride, n, tl, (hipStream_t)stream) != hipSuccess)
+    return CMP_EDEVICE;
   return CMP_OK;
 }
 

@@ -56,4 +56,11 @@ hipError_t launch_pack_window(const void *src, int elem, int32_t W, int32_t x0,
                               int32_t y0, int32_t w, int32_t h, void *dst,
                               int64_t dst_pitch, hipStream_t s);
 
+// Histogram of a count array (uint16 or uint32, npix values) into nbins
+// uint64 device counters (zeroed by the caller) plus one overflow counter at
+// bins[nbins].  Bins live in LDS per workgroup when nbins <= kLdsBins.
+constexpr int kLdsBins = 8192;
+hipError_t launch_histogram(const void *count, bool count16, int64_t npix, int32_t nbins,
+                            unsigned long long *bins, int cus, hipStream_t s);
+
 }  // namespace cmp

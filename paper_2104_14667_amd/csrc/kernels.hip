@@ -16,6 +16,8 @@
 
 #include "lanes.h"
 
+#include <algorithm>
+
 namespace cmp {
 namespace {
 
@@ -305,7 +307,71 @@ __global__ __launch_bounds__(256) void k_pack(const T *__restrict__ src, int32_t
   reinterpret_cast<T *>(dst + (int64_t)y * dst_pitch)[x] = src[(int64_t)(y0 + y) * W + x0 + x];
 }
 
+// One workgroup walks vectors of 8 counts with a grid stride and counts them
+// into bins privatized in LDS (or straight into global memory for large bin
+// counts); LDS bins are flushed once per workgroup.
+template <bool C16, bool LDS>
+__global__ __launch_bounds__(256) void k_histogram(const void *__restrict__ count, uint32_t npix,
+                                                   int32_t nbins,
+                                                   unsigned long long *__restrict__ bins) {
+  extern __shared__ uint32_t sh[];
+  if constexpr (LDS) {
+    for (int b = threadIdx.x; b <= nbins; b += blockDim.x) sh[b] = 0u;
+    __syncthreads();
+  }
+  auto put = [&](uint32_t c) {
+    const int b = c < (uint32_t)nbins ? (int)c : nbins;
+    if constexpr (LDS) atomicAdd(&sh[b], 1u);
+    else atomicAdd(&bins[b], 1ull);
+  };
+  const uint32_t nv = npix / 8;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    if constexpr (C16) {
+      const uint4 x = reinterpret_cast<const uint4 *>(count)[v];
+      const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        put(w[k] & 0xffffu);
+        put(w[k] >> 16);
+      }
+    } else {
+      const uint4 *p = reinterpret_cast<const uint4 *>(count) + 2 * (size_t)v;
+      const uint4 a = p[0], b = p[1];
+      put(a.x); put(a.y); put(a.z); put(a.w);
+      put(b.x); put(b.y); put(b.z); put(b.w);
+    }
+  }
+  // the last npix % 8 values
+  if (blockIdx.x == 0 && threadIdx.x < npix - nv * 8) {
+    const uint32_t i = nv * 8 + threadIdx.x;
+    put(C16 ? static_cast<const uint16_t *>(count)[i] : static_cast<const uint32_t *>(count)[i]);
+  }
+  if constexpr (LDS) {
+    __syncthreads();
+    for (int b = threadIdx.x; b <= nbins; b += blockDim.x)
+      if (sh[b]) atomicAdd(&bins[b], (unsigned long long)sh[b]);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_histogram(const void *count, bool count16, int64_t npix, int32_t nbins,
+                            unsigned long long *bins, int cus, hipStream_t s) {
+  if (npix <= 0) return hipSuccess;
+  if (npix >= (int64_t(1) << 32) || nbins < 1) return hipErrorInvalidValue;
+  const bool lds = nbins <= kLdsBins;
+  const int64_t nv = npix / 8;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nv + 255) / 256, (int64_t)cus * 4));
+  const size_t shm = lds ? sizeof(uint32_t) * (nbins + 1) : 0;
+  if (count16) {
+    if (lds) k_histogram<true, true><<<grid, 256, shm, s>>>(count, (uint32_t)npix, nbins, bins);
+    else k_histogram<true, false><<<grid, 256, 0, s>>>(count, (uint32_t)npix, nbins, bins);
+  } else {
+    if (lds) k_histogram<false, true><<<grid, 256, shm, s>>>(count, (uint32_t)npix, nbins, bins);
+    else k_histogram<false, false><<<grid, 256, 0, s>>>(count, (uint32_t)npix, nbins, bins);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_composite_linear(const uint8_t *const *d_tab, int n, int64_t npix,
                                    const Outputs &o, uint32_t outs, bool sub, hipStream_t s) {

@@ -85,3 +85,16 @@ def test_pool_and_batch_argument_checks():
 def test_pool_without_gpu_reports_edevice():
     h = C.c_void_p()
     assert cb.lib.composite_pool_create(C.byref(h), 4096, 2, 4, 4, 16, 64, 0) == cb.CMP_EDEVICE
+
+
+def test_tiled_bytes_and_repack_argument_checks():
+    assert cb.composite_tiled_bytes(64, 64, 64, 64) == 4096
+    assert cb.composite_tiled_bytes(65, 1, 64, 64) == 2 * 64 * 64
+    assert cb.composite_tiled_bytes(4096, 9, 128, 4) == 32 * 3 * 128 * 4
+    assert cb.lib.composite_tiled_bytes(0, 1, 16, 1) == -1
+    assert cb.lib.composite_repack_tiled(None, 16, 4096, 16, 1, 16, 1, 16, 1, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_repack_tiled(4096, 16, 8192, 16, 1, 16, 1, 24, 1, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_repack_tiled(4096, 24, 8192, 32, 1, 24, 1, 16, 1, None) == cb.CMP_EUNSUPPORTED
+    assert cb.lib.composite_repack_tiled(4096, 8, 8192, 16, 1, 16, 1, 16, 1, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_repack_tiled(4096, 16, 8192, 16, 0, 16, 1, 16, 1, None) == cb.CMP_OK
+    assert cb.lib.composite_histogram(None, None, 4, None) == cb.CMP_EINVAL
