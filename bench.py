@@ -36,21 +36,29 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_composite_depth8192_n128_resident_hbm_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2104_14667_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2104_14667_amd", "csrc", f)
+               for f in ("kernels.hip", "lanes.h", "kernels.h")]
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources the resident compositing kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch of the resident kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
-    import hashlib
+    summary, or None when the kernel sources changed since it was taken."""
     try:
         kv = {}
         for line in open(TRAFFIC_FILE):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
-                kv[k.strip()] = v.strip()
-        cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if kv.get("kernels_hip_sha256") != cur:
+                kv[k.strip()] = v.split("#")[0].strip()
+        if kv.get("kernel_sources_sha256") != kernel_source_hash():
             return None
         return int(kv["traffic_bytes"])
     except (OSError, KeyError, ValueError):

@@ -362,7 +362,7 @@ int composite_histogram(cmp_ctx *ctx, int64_t *bins, int32_t nbins, int64_t *ove
  * counterpart of the paper's buffer-to-image transform (Section 4; its rate
  * over image dimensions is the experiment of Section 5.2).  Enqueued on
  * `stream` (a hipStream_t, or NULL for the null stream); returns without
- * waiting.  W must be a multiple of 16. */
+ * waiting.  Any W; the streamed CMP_TILED path needs W a multiple of 16. */
 int composite_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
                            int64_t dst_stride, int32_t n, int32_t W, int32_t H,
                            int32_t tile_w, int32_t tile_h, void *stream);

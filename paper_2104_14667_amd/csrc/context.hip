@@ -800,7 +800,6 @@ int composite_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
   if (!src || !dst || n < 0 || n > 65535 || W < 1 || H < 1) return CMP_EINVAL;
   if (tile_w != 16 && tile_w != 32 && tile_w != 64 && tile_w != 128) return CMP_EINVAL;
   if (tile_h < 1 || tile_h > 256) return CMP_EINVAL;
-  if (W % 16) return CMP_EUNSUPPORTED;
   const int64_t plane = (int64_t)W * H;
   cmp::Tiling tl{W, H, tile_w, tile_h};
   if (plane > (int64_t(1) << 32) - 16 || src_stride < plane || dst_stride < tl.plane()) return CMP_EINVAL;

@@ -285,7 +285,19 @@ __global__ __launch_bounds__(256) void k_repack(const uint8_t *__restrict__ src,
   const int64_t i = blockIdx.y;
   uint32_t p;
   uint4 x = make_uint4(0u, 0u, 0u, 0u);
-  if (map.pixel(v, p)) x = ld16(src + i * src_stride, p);
+  if (map.pixel(v, p)) {
+    const uint32_t col = p % map.W;
+    if (col + 16u <= map.W) {
+      x = ld16(src + i * src_stride, p);
+    } else {
+      // the vector crosses the raster's right edge: the bytes past it are
+      // padding (zero) and must not be read
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
+      const uint8_t *row = src + i * src_stride + p;
+      for (uint32_t b = 0; b < map.W - col; ++b) w[b >> 2] |= (uint32_t)row[b] << (8 * (b & 3));
+      x = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
   *reinterpret_cast<uint4 *>(dst + i * dst_stride + (int64_t)v * 16) = x;
 }
 
@@ -391,7 +403,7 @@ hipError_t launch_composite_tiled(const uint8_t *const *d_tab, int n, const Tili
 hipError_t launch_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
                                int64_t dst_stride, int n, const Tiling &t, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (t.W % 16 || t.tw % 16 || n > 65535) return hipErrorInvalidValue;
+  if (t.tw % 16 || n > 65535) return hipErrorInvalidValue;
   const TiledMap map{(uint32_t)t.W, (uint32_t)t.H, (uint32_t)t.tw, (uint32_t)t.th, (uint32_t)t.ntx()};
   const int64_t nvec = t.plane() / 16;
   if (nvec >= (int64_t(1) << 28)) return hipErrorInvalidValue;

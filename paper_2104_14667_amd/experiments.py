@@ -1,0 +1,172 @@
+"""The paper's experiments, re-run on MI355X through the C ABI.
+
+* ``repack-sweep``: rate of the linear-to-tiled transform over a grid of
+  raster dimensions (the buffer-to-image transform test of Section 5.2, whose
+  result is the banded rate map of Figure 15): W and H from `lo` to `hi` in
+  steps of `step`, one raster per measurement, `reps` timed repetitions.
+* ``paper-table``: the dual- and single-buffer streaming runs of Section 5.1
+  at the paper's raster sizes (~2k 1856x2208, ~4k 3712x4416, ~8k 7424x8832)
+  and N = 10, 100, 1000, with the efficiency of Section 6.1 (rate over the
+  rate of a plain host-to-device copy of the same bytes in the same pieces).
+  The paper's host kept a small set of images and sent them again (8 GB of
+  host memory cannot hold 1000 ~8k images); here a ring of 16 distinct pinned
+  rasters is sent round-robin.  Variants: "final" (pinned source, staged
+  copy then transform to tiles, 1 or 2 staging slots, one raster per slot as
+  in the paper), "initial" (pageable source: the host copies every raster
+  into a pinned bounce buffer first, as the runtime did behind the paper's
+  clWriteImage), and this library's default (linear layout, 8 rasters per
+  slot).
+
+Usage: python -m paper_2104_14667_amd.experiments {repack-sweep,paper-table} [--out FILE]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+PAPER_SIZES = {"2k": (1856, 2208), "4k": (3712, 4416), "8k": (7424, 8832)}
+
+
+def repack_sweep(lo: int, hi: int, step: int, reps: int, tile=(64, 64)) -> dict:
+    import torch
+
+    from .composite import composite_repack_tiled, composite_tiled_bytes
+    tw, th = tile
+    maxb = hi * hi
+    src = torch.zeros(maxb + 64, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty(composite_tiled_bytes(hi, hi, tw, th) + 64, dtype=torch.uint8, device="cuda:0")
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    sides = list(range(lo, hi + 1, step))
+    rate = np.zeros((len(sides), len(sides)))
+    t0 = time.perf_counter()
+    for iy, H in enumerate(sides):
+        for ix, W in enumerate(sides):
+            tb = composite_tiled_bytes(W, H, tw, th)
+            composite_repack_tiled(src, W * H, dst, tb, 1, W, H, tw, th, s)   # warm-up
+            ev[0].record(s)
+            for _ in range(reps):
+                composite_repack_tiled(src, W * H, dst, tb, 1, W, H, tw, th, s)
+            ev[1].record(s)
+            ev[1].synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / reps
+            rate[iy, ix] = W * H / (ms * 1e-3) / 1e9
+    return {"lo": lo, "hi": hi, "step": step, "reps": reps, "tile": [tw, th],
+            "seconds": time.perf_counter() - t0, "sides": sides, "rate_GBps": rate.tolist()}
+
+
+def summarize_sweep(res: dict) -> dict:
+    r = np.array(res["rate_GBps"])
+    sides = np.array(res["sides"])
+    out = {"points": int(r.size), "mean": float(r.mean()), "min": float(r.min()),
+           "max": float(r.max()), "p10": float(np.percentile(r, 10)),
+           "p90": float(np.percentile(r, 90))}
+    big = r[np.ix_(sides >= res["hi"] // 4, sides >= res["hi"] // 4)]
+    out["large_mean"] = float(big.mean())
+    out["large_cv"] = float(big.std() / big.mean())
+    # rate against the width's residue modulo powers of two, large rasters only
+    cols = sides >= res["hi"] // 4
+    for m in (256, 512, 1024, 2048):
+        classes = {}
+        for W, c in zip(sides[cols], big.T):
+            classes.setdefault(int(W % m), []).append(float(c.mean()))
+        out[f"by_W_mod_{m}"] = {k: round(float(np.mean(v)), 1) for k, v in sorted(classes.items())}
+    return out
+
+
+def _copy_time(torch, ring, n: int) -> float:
+    """Plain pinned host-to-device copy of n rasters taken round-robin from the
+    ring, one raster per copy, into two alternating device buffers."""
+    plane = ring[0].numel()
+    bufs = [torch.empty(plane, dtype=torch.uint8, device="cuda:0") for _ in range(2)]
+    s = torch.cuda.Stream()
+    best = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s):
+            for i in range(n):
+                bufs[i & 1].copy_(ring[i % len(ring)].view(-1), non_blocking=True)
+        s.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return best
+
+
+def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k")) -> dict:
+    import torch
+
+    from . import synth
+    from .composite import CMP_LINEAR, CMP_TILED, Composite
+    rows = []
+    for name in sizes:
+        W, H = PAPER_SIZES[name]
+        e = synth.elevation(10 + len(name), H, W, 32.0)
+        lv = synth.levels(10, ring_size, 64, 192)
+        pinned = [torch.from_numpy(synth.mask(e, int(L))).pin_memory() for L in lv]
+        pageable = [synth.mask(e, int(L)) for L in lv]
+        variants = {
+            "1b final": dict(nbuf=1, chunk_depth=1, layout=CMP_TILED, src=pinned),
+            "2b final": dict(nbuf=2, chunk_depth=1, layout=CMP_TILED, src=pinned),
+            "1b initial": dict(nbuf=1, chunk_depth=1, layout=CMP_TILED, src=pageable, pageable_host=1),
+            "2b initial": dict(nbuf=2, chunk_depth=1, layout=CMP_TILED, src=pageable, pageable_host=1),
+            "2b linear chunk 8": dict(nbuf=2, chunk_depth=8, layout=CMP_LINEAR, src=pinned),
+        }
+        for N in Ns:
+            copy_s = _copy_time(torch, pinned, N)
+            copy_rate = N * W * H / copy_s / 1e9
+            for vname, kw in variants.items():
+                kw = dict(kw)
+                src = kw.pop("src")
+                maps = [src[i % ring_size] for i in range(N)]
+                times = []
+                with Composite(W, H, ("count",), 32, **kw) as c:
+                    for r in range(3):
+                        c.clear()
+                        c.sync()
+                        t0 = time.perf_counter()
+                        c.add(maps)
+                        c.sync()
+                        if r:
+                            times.append(time.perf_counter() - t0)
+                t = min(times)
+                rate = N * W * H / t / 1e9
+                rows.append({"set": name, "N": N, "alg": vname, "time_us": round(t * 1e6, 1),
+                             "rate_GBps": round(rate, 3), "copy_GBps": round(copy_rate, 3),
+                             "efficiency_pct": round(100 * rate / copy_rate, 2)})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"ring": ring_size, "rows": rows}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("repack-sweep")
+    a.add_argument("--lo", type=int, default=128)
+    a.add_argument("--hi", type=int, default=16384)
+    a.add_argument("--step", type=int, default=128)
+    a.add_argument("--reps", type=int, default=3)
+    a.add_argument("--out", default=None)
+    b = sub.add_parser("paper-table")
+    b.add_argument("--ns", default="10,100,1000")
+    b.add_argument("--sizes", default="2k,4k,8k")
+    b.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    if args.cmd == "repack-sweep":
+        res = repack_sweep(args.lo, args.hi, args.step, args.reps)
+        res["summary"] = summarize_sweep(res)
+        print(json.dumps(res["summary"]))
+    else:
+        res = paper_table(tuple(int(x) for x in args.ns.split(",")),
+                          sizes=tuple(args.sizes.split(",")))
+    if args.out:
+        json.dump(res, open(args.out, "w"))
+
+
+if __name__ == "__main__":
+    main()

@@ -94,7 +94,7 @@ def test_tiled_bytes_and_repack_argument_checks():
     assert cb.lib.composite_tiled_bytes(0, 1, 16, 1) == -1
     assert cb.lib.composite_repack_tiled(None, 16, 4096, 16, 1, 16, 1, 16, 1, None) == cb.CMP_EINVAL
     assert cb.lib.composite_repack_tiled(4096, 16, 8192, 16, 1, 16, 1, 24, 1, None) == cb.CMP_EINVAL
-    assert cb.lib.composite_repack_tiled(4096, 24, 8192, 32, 1, 24, 1, 16, 1, None) == cb.CMP_EUNSUPPORTED
+    assert cb.lib.composite_repack_tiled(4096, 24, 8192, 16, 1, 24, 1, 16, 1, None) == cb.CMP_EINVAL
     assert cb.lib.composite_repack_tiled(4096, 8, 8192, 16, 1, 16, 1, 16, 1, None) == cb.CMP_EINVAL
     assert cb.lib.composite_repack_tiled(4096, 16, 8192, 16, 0, 16, 1, 16, 1, None) == cb.CMP_OK
     assert cb.lib.composite_histogram(None, None, 4, None) == cb.CMP_EINVAL

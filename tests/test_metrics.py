@@ -81,3 +81,22 @@ def test_single_slot_serialises():
     # one slot: copy i+1 waits for processing i, so nothing overlaps
     c, m, p = [2.0] * 6, [0.5] * 6, [1.0] * 6
     assert metrics.simulate_staged(c, m, p, 1) == pytest.approx(6 * 3.5)
+
+
+def test_sweep_summary_on_a_synthetic_map():
+    from paper_2104_14667_amd.experiments import summarize_sweep
+    sides = list(range(128, 1025, 128))
+    rate = [[(100.0 if W % 256 == 0 else 50.0) for W in sides] for H in sides]
+    s = summarize_sweep({"sides": sides, "hi": 1024, "rate_GBps": rate})
+    assert s["points"] == 64 and s["max"] == 100.0 and s["min"] == 50.0
+    assert s["by_W_mod_256"] == {0: 100.0, 128: 50.0}
+
+
+def test_bench_traffic_is_null_when_kernel_sources_change(tmp_path, monkeypatch):
+    import bench
+    f = tmp_path / "t.txt"
+    f.write_text(f"# x\nkernel_sources_sha256 = {bench.kernel_source_hash()}   # c\ntraffic_bytes = 123\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic() == 123
+    f.write_text("kernel_sources_sha256 = 00\ntraffic_bytes = 123\n")
+    assert bench.measured_traffic() is None
