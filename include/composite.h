@@ -218,6 +218,12 @@ typedef struct cmp_request {
 
 enum cmp_batch_mode { CMP_BATCH_PERSISTENT = 0, CMP_BATCH_PER_REQUEST = 1 };
 
+/* Order of the work queue.  COST: largest items first.  ROWS: by the first
+ * raster row an item reads, so that concurrently running items of different
+ * requests read the same rows of the members they share while those rows are
+ * still in the L2 / Infinity Cache. */
+enum cmp_batch_order { CMP_ORDER_COST = 0, CMP_ORDER_ROWS = 1 };
+
 typedef struct cmp_tune {
   int32_t mode;           /* cmp_batch_mode.  PER_REQUEST launches one plain
                              kernel per request, in order (the baseline) */
@@ -227,12 +233,16 @@ typedef struct cmp_tune {
                              unit, 1 .. 16 */
   int32_t use_graph;      /* persistent mode: 1 replays a captured hipGraph of
                              [queue reset, persistent kernel]; captured once
-                             per grid size and reused */
-  int32_t reserved[4];    /* must be zero */
+                             per grid size and load kind, and reused */
+  int32_t order;          /* persistent mode: cmp_batch_order */
+  int32_t stream_loads;   /* 1: member loads carry the non-temporal hint
+                             (nothing is re-read); 0: plain loads, so rows
+                             shared by requests can hit in the caches */
+  int32_t reserved[2];    /* must be zero */
 } cmp_tune;
 
 /* Fills *t with the defaults (persistent, tile_vecs 1024, blocks_per_cu 8,
- * use_graph 1).  NULL is ignored. */
+ * use_graph 1, order ROWS, stream_loads 0).  NULL is ignored. */
 void composite_default_tune(cmp_tune *t);
 
 /* Runs nreq requests and returns when every output is written.  Every

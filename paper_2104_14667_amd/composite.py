@@ -44,7 +44,11 @@ class cmp_request(C.Structure):
 
 class cmp_tune(C.Structure):
     _fields_ = [("mode", C.c_int32), ("tile_vecs", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("use_graph", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("use_graph", C.c_int32), ("order", C.c_int32), ("stream_loads", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+
+
+CMP_ORDER_COST, CMP_ORDER_ROWS = 0, 1
 
 
 CMP_BATCH_PERSISTENT, CMP_BATCH_PER_REQUEST = 0, 1
@@ -407,9 +411,11 @@ def composite_batch_last(pool: int):
     return ms.value, items.value
 
 
-def make_tune(mode=CMP_BATCH_PERSISTENT, tile_vecs=1024, blocks_per_cu=8, use_graph=1) -> cmp_tune:
+def make_tune(mode=CMP_BATCH_PERSISTENT, tile_vecs=1024, blocks_per_cu=8, use_graph=1,
+              order=CMP_ORDER_ROWS, stream_loads=0) -> cmp_tune:
     t = composite_default_tune()
     t.mode, t.tile_vecs, t.blocks_per_cu, t.use_graph = mode, tile_vecs, blocks_per_cu, use_graph
+    t.order, t.stream_loads = order, stream_loads
     return t
 
 

@@ -46,6 +46,7 @@ static_assert(sizeof(Header) == 64, "arena header is 64 bytes");
 
 // Counts of one 16-pixel vector of a request: pixels (y, x .. x+15) of the
 // pool rasters ids[0..n), written to out[0..valid).
+template <bool NT>
 __device__ __forceinline__ void crop_vector(const uint8_t *__restrict__ base, int64_t stride,
                                             const int32_t *__restrict__ ids, int n, uint32_t off,
                                             uint32_t *__restrict__ out, int valid) {
@@ -61,11 +62,11 @@ __device__ __forceinline__ void crop_vector(const uint8_t *__restrict__ base, in
     for (; i + U <= g1; i += U) {
       uint4 x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
+      for (int u = 0; u < U; ++u) x[u] = cmp::ld16_t<NT>(base + (int64_t)ids[i + u] * stride, off);
 #pragma unroll
       for (int u = 0; u < U; ++u) a.fold(x[u]);
     }
-    for (; i < g1; ++i) a.fold(cmp::ld16(base + (int64_t)ids[i] * stride, off));
+    for (; i < g1; ++i) a.fold(cmp::ld16_t<NT>(base + (int64_t)ids[i] * stride, off));
 #pragma unroll
     for (int j = 0; j < 16; ++j) cnt[j] += cmp::lane_px(a.c, j);
   }
@@ -82,6 +83,7 @@ __device__ __forceinline__ void crop_vector(const uint8_t *__restrict__ base, in
   }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(256) void k_batch(const uint8_t *__restrict__ base, int64_t stride,
                                                int32_t W, const char *__restrict__ arena,
                                                uint32_t *__restrict__ queue) {
@@ -105,11 +107,12 @@ __global__ __launch_bounds__(256) void k_batch(const uint8_t *__restrict__ base,
       const int row = v / R.nvr, j = v - row * R.nvr;
       const uint32_t off = (uint32_t)(R.y0 + I.row0 + row) * (uint32_t)W + (uint32_t)(R.x0 + 16 * j);
       uint32_t *out = R.out + (int64_t)(I.row0 + row) * R.pitch + 16 * j;
-      crop_vector(base, stride, ids, R.n, off, out, min(16, R.w - 16 * j));
+      crop_vector<NT>(base, stride, ids, R.n, off, out, min(16, R.w - 16 * j));
     }
   }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(256) void k_crop(const uint8_t *__restrict__ base, int64_t stride,
                                               int32_t W, ReqDesc R,
                                               const int32_t *__restrict__ ids) {
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(256) void k_crop(const uint8_t *__restrict__ base, 
   if (v >= R.h * R.nvr) return;
   const int row = v / R.nvr, j = v - row * R.nvr;
   const uint32_t off = (uint32_t)(R.y0 + row) * (uint32_t)W + (uint32_t)(R.x0 + 16 * j);
-  crop_vector(base, stride, ids, R.n, off, R.out + (int64_t)row * R.pitch + 16 * j,
+  crop_vector<NT>(base, stride, ids, R.n, off, R.out + (int64_t)row * R.pitch + 16 * j,
               min(16, R.w - 16 * j));
 }
 
@@ -158,10 +161,13 @@ int ensure_arena(cmp_pool *p, int64_t bytes) {
   return CMP_OK;
 }
 
-hipError_t launch_persistent(cmp_pool *p, int grid) {
+hipError_t launch_persistent(cmp_pool *p, int grid, bool nt) {
   hipError_t e = cmp::launch_fill(p->d_queue, 0, 4, p->s);
   if (e != hipSuccess) return e;
-  k_batch<<<grid, 256, 0, p->s>>>(p->base, p->stride, p->W, p->d_arena, p->d_queue);
+  if (nt)
+    k_batch<true><<<grid, 256, 0, p->s>>>(p->base, p->stride, p->W, p->d_arena, p->d_queue);
+  else
+    k_batch<false><<<grid, 256, 0, p->s>>>(p->base, p->stride, p->W, p->d_arena, p->d_queue);
   return hipGetLastError();
 }
 
@@ -176,6 +182,8 @@ void composite_default_tune(cmp_tune *t) {
   t->tile_vecs = 1024;
   t->blocks_per_cu = 8;
   t->use_graph = 1;
+  t->order = CMP_ORDER_ROWS;
+  t->stream_loads = 0;
 }
 
 int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count, int32_t W,
@@ -242,8 +250,10 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   if (t.mode != CMP_BATCH_PERSISTENT && t.mode != CMP_BATCH_PER_REQUEST) return CMP_EINVAL;
   if (t.mode == CMP_BATCH_PERSISTENT &&
       (t.tile_vecs < 64 || t.tile_vecs > 65536 || t.blocks_per_cu < 1 || t.blocks_per_cu > 16 ||
-       (t.use_graph != 0 && t.use_graph != 1)))
+       (t.use_graph != 0 && t.use_graph != 1) ||
+       (t.order != CMP_ORDER_COST && t.order != CMP_ORDER_ROWS)))
     return CMP_EINVAL;
+  if (t.stream_loads != 0 && t.stream_loads != 1) return CMP_EINVAL;
   for (int r : t.reserved)
     if (r) return CMP_EINVAL;
   // validate every request before anything is enqueued
@@ -288,13 +298,17 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
       for (int r0 = 0; r0 < q.h; r0 += rows) {
         const int nr = std::min(rows, q.h - r0);
         items.push_back(Item{r, r0, nr, 0});
-        cost.push_back((double)(q.n + 1) * nr * d.nvr);
+        // cost order: largest first; row order: by the first raster row read
+        cost.push_back(t.order == CMP_ORDER_COST ? (double)(q.n + 1) * nr * d.nvr
+                                                 : -(double)(q.y0 + r0));
       }
     }
   }
   if (ids_off > INT32_MAX) return CMP_EINVAL;
   if (t.mode == CMP_BATCH_PERSISTENT) {
-    // costliest items first, so the queue ends with small ones
+    // costliest items first, so the queue ends with small ones; or top to
+    // bottom through the raster, so that concurrent items of different
+    // requests read the same rows of shared members while they are cached
     std::vector<int> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -328,12 +342,13 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   if (t.mode == CMP_BATCH_PERSISTENT) {
     const int grid = p->cus * t.blocks_per_cu;
     if (t.use_graph) {
-      auto it = p->graphs.find(grid);
+      const int key = grid * 2 + t.stream_loads;
+      auto it = p->graphs.find(key);
       if (it == p->graphs.end()) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         POOL_TRY(hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal));
-        const hipError_t le = launch_persistent(p, grid);
+        const hipError_t le = launch_persistent(p, grid, t.stream_loads != 0);
         const hipError_t ce = hipStreamEndCapture(p->s, &g);
         if (le != hipSuccess || ce != hipSuccess) {
           if (g) hipGraphDestroy(g);
@@ -346,18 +361,22 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
           p->poisoned = true;
           return CMP_EDEVICE;
         }
-        it = p->graphs.emplace(grid, ge).first;
+        it = p->graphs.emplace(key, ge).first;
       }
       POOL_TRY(hipGraphLaunch(it->second, p->s));
     } else {
-      POOL_TRY(launch_persistent(p, grid));
+      POOL_TRY(launch_persistent(p, grid, t.stream_loads != 0));
     }
   } else {
     const int32_t *d_ids = reinterpret_cast<const int32_t *>(p->d_arena + hd.ids_off);
     for (int32_t r = 0; r < nreq; ++r) {
       const int64_t nv = (int64_t)rd[r].h * rd[r].nvr;
-      k_crop<<<(unsigned)((nv + 255) / 256), 256, 0, p->s>>>(p->base, p->stride, p->W, rd[r],
-                                                               d_ids + rd[r].ids_off);
+      if (t.stream_loads)
+        k_crop<true><<<(unsigned)((nv + 255) / 256), 256, 0, p->s>>>(p->base, p->stride, p->W, rd[r],
+                                                                     d_ids + rd[r].ids_off);
+      else
+        k_crop<false><<<(unsigned)((nv + 255) / 256), 256, 0, p->s>>>(p->base, p->stride, p->W, rd[r],
+                                                                      d_ids + rd[r].ids_off);
       POOL_TRY(hipGetLastError());
     }
   }

@@ -51,6 +51,17 @@ __device__ __forceinline__ uint4 ld16(const uint8_t *base, uint32_t off) {
   const u32x4u v = __builtin_nontemporal_load((gu32x4u *)(base + off));
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+// The same load without the hint, for bytes other workgroups read again soon
+// (batched requests that share pool members): they may stay in L2/MALL.
+__device__ __forceinline__ uint4 ld16_cached(const uint8_t *base, uint32_t off) {
+  const u32x4u v = *(gu32x4u *)(base + off);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <bool NT>
+__device__ __forceinline__ uint4 ld16_t(const uint8_t *base, uint32_t off) {
+  if constexpr (NT) return ld16(base, off);
+  else return ld16_cached(base, off);
+}
 
 // Packed accumulators of 16 pixels.  Lane pair k*2 holds pixels 4k and 4k+2,
 // lane pair k*2+1 holds pixels 4k+1 and 4k+3 (low half first).

@@ -20,5 +20,5 @@ struct cmp_pool {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   int64_t last_items = 0;
-  std::map<int, hipGraphExec_t> graphs;  // by grid size; they capture d_arena
+  std::map<int, hipGraphExec_t> graphs;  // by grid size and load kind; they capture d_arena
 };

@@ -1,8 +1,11 @@
 """Autotuner of the batched persistent launch.
 
-Sweeps the work-item size (16-pixel vectors per item) and the persistent
-occupancy (workgroups per compute unit) on the actual batch, timing each
-candidate with the library's own event timing, and keeps the fastest.  Results
+Sweeps the work-item size (16-pixel vectors per item), the persistent
+occupancy (workgroups per compute unit), the queue order (largest items first,
+or top to bottom through the raster so that requests sharing members hit in
+the caches) and the load hint (non-temporal or cached) on the actual batch,
+timing each candidate with the library's own event timing, and keeps the
+fastest.  Results
 are cached per shape class (arch, raster size, request count, typical window
 side and set size, each bucketed to a power of two) in memory and, when a path
 is given, in a JSON file."""
@@ -15,10 +18,13 @@ import os
 import time
 from typing import Dict, Optional, Sequence
 
-from .composite import CMP_BATCH_PERSISTENT, Pool, make_tune
+from .composite import (CMP_BATCH_PERSISTENT, CMP_ORDER_COST, CMP_ORDER_ROWS, Pool,
+                        make_tune)
 
-TILE_VECS = (256, 512, 1024, 2048, 4096, 8192)
-BLOCKS_PER_CU = (2, 4, 8, 12, 16)
+TILE_VECS = (64, 128, 256, 512, 1024, 2048, 4096)
+BLOCKS_PER_CU = (1, 2, 4, 8, 16)
+ORDERS = (CMP_ORDER_COST, CMP_ORDER_ROWS)
+STREAM_LOADS = (0, 1)
 
 _cache: Dict[str, dict] = {}
 
@@ -36,7 +42,8 @@ def shape_key(pool: Pool, requests: Sequence[dict], arch: str = "gfx950") -> str
 
 def autotune(pool: Pool, requests: Sequence[dict], reps: int = 3,
              cache_path: Optional[str] = None, use_graph: int = 1) -> dict:
-    """Returns {'tile_vecs', 'blocks_per_cu', 'ms', 'key', 'seconds', 'cached'}."""
+    """Returns {'tile_vecs', 'blocks_per_cu', 'order', 'stream_loads', 'ms', 'key',
+    'seconds', 'cached'}."""
     key = shape_key(pool, requests)
     if cache_path and os.path.exists(cache_path) and not _cache:
         try:
@@ -47,16 +54,19 @@ def autotune(pool: Pool, requests: Sequence[dict], reps: int = 3,
         return dict(_cache[key], key=key, cached=True, seconds=0.0)
     t0 = time.perf_counter()
     best = None
-    for tv in TILE_VECS:
-        for bpc in BLOCKS_PER_CU:
-            tune = make_tune(CMP_BATCH_PERSISTENT, tv, bpc, use_graph)
-            ms = []
-            for _ in range(reps):
-                pool.run(requests, tune)
-                ms.append(pool.last()[0])
-            m = min(ms)
-            if best is None or m < best["ms"]:
-                best = {"tile_vecs": tv, "blocks_per_cu": bpc, "ms": m}
+    for order in ORDERS:
+        for sl in STREAM_LOADS:
+            for tv in TILE_VECS:
+                for bpc in BLOCKS_PER_CU:
+                    tune = make_tune(CMP_BATCH_PERSISTENT, tv, bpc, use_graph, order, sl)
+                    ms = []
+                    for _ in range(reps):
+                        pool.run(requests, tune)
+                        ms.append(pool.last()[0])
+                    m = min(ms)
+                    if best is None or m < best["ms"]:
+                        best = {"tile_vecs": tv, "blocks_per_cu": bpc, "order": order,
+                                "stream_loads": sl, "ms": m}
     _cache[key] = best
     if cache_path:
         try:

@@ -77,6 +77,7 @@ def test_pool_and_batch_argument_checks():
     assert cb.lib.composite_batch_run(None, None, 0, None) == cb.CMP_EINVAL
     t = cb.composite_default_tune()
     assert (t.mode, t.tile_vecs, t.blocks_per_cu, t.use_graph) == (0, 1024, 8, 1)
+    assert (t.order, t.stream_loads) == (cb.CMP_ORDER_ROWS, 0)
     assert C.sizeof(cb.cmp_request) == 48 and C.sizeof(cb.cmp_tune) == 32
     cb.lib.composite_pool_free(None)
 

@@ -11,7 +11,8 @@ import torch
 import oracle
 from paper_2104_14667_amd import synth
 from paper_2104_14667_amd.composite import (CMP_BATCH_PER_REQUEST, CMP_BATCH_PERSISTENT,
-                                            CMP_EINVAL, CompositeError, Pool, make_tune)
+                                            CMP_EINVAL, CMP_ORDER_COST, CMP_ORDER_ROWS,
+                                            CompositeError, Pool, make_tune)
 from paper_2104_14667_amd.tune import autotune
 
 from gpu_common import say
@@ -39,8 +40,12 @@ def _got(r):
     return r["out"][:, : r["w"]].cpu().numpy().view(np.uint32).astype(np.int64)
 
 
-TUNES = [make_tune(CMP_BATCH_PERSISTENT, 64, 1, 0), make_tune(CMP_BATCH_PERSISTENT, 1024, 8, 1),
-         make_tune(CMP_BATCH_PERSISTENT, 256, 3, 1), make_tune(CMP_BATCH_PER_REQUEST)]
+TUNES = [make_tune(CMP_BATCH_PERSISTENT, 64, 1, 0, CMP_ORDER_COST, 1),
+         make_tune(CMP_BATCH_PERSISTENT, 1024, 8, 1, CMP_ORDER_COST, 0),
+         make_tune(CMP_BATCH_PERSISTENT, 256, 3, 1, CMP_ORDER_ROWS, 0),
+         make_tune(CMP_BATCH_PERSISTENT, 64, 16, 1, CMP_ORDER_ROWS, 1),
+         make_tune(CMP_BATCH_PER_REQUEST, stream_loads=1),
+         make_tune(CMP_BATCH_PER_REQUEST, stream_loads=0)]
 
 
 def _small_case(seed):
@@ -140,7 +145,8 @@ def test_full_batched_pool_2048():
     with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
         best = autotune(pool, reqs[:16], reps=1)
         say("autotuned", best)
-        for tune in (make_tune(CMP_BATCH_PERSISTENT, best["tile_vecs"], best["blocks_per_cu"], 1),
+        for tune in (make_tune(CMP_BATCH_PERSISTENT, best["tile_vecs"], best["blocks_per_cu"], 1,
+                               best["order"], best["stream_loads"]),
                      make_tune(CMP_BATCH_PER_REQUEST)):
             _outs(reqs)
             pool.run(reqs, tune)
