@@ -313,6 +313,82 @@ def run_served(torch, duration_s, spill_duration_s):
     return out
 
 
+def run_plain_small(torch, reps=50):
+    """Plain small workload (N=16 masks of 512x512 -> u16 count): 4 MiB of input
+    fits the caches, so it is reported as launch-to-completion latency."""
+    from paper_2104_14667_amd import synth
+    from paper_2104_14667_amd.composite import Composite
+    ens = synth.PLAIN_SMALL
+    e = ens.elevation()
+    dev = device_members(torch, ens, e)
+    ptrs = [dev[i] for i in range(ens.N)]
+    with Composite(ens.W, ens.H, ens.outputs, ens.count_bits, profile=1) as c:
+        for _ in range(3):
+            c.add_device(ptrs)
+        c.sync()
+        c.kernel_stats(reset=True)
+        dev_us, wall_us = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            c.add_device(ptrs)
+            c.sync()
+            wall_us.append((time.perf_counter() - t0) * 1e6)
+            n, ms = c.kernel_stats(reset=True)
+            dev_us.append(ms * 1e3 / max(n, 1))
+        exact = verify(c, ens, e, 3 + reps)
+    return {"workload": "plain small: N=16 x 512x512 masks -> u16 count, resident",
+            "kernel_us_median": round(float(np.median(dev_us)), 2),
+            "kernel_us_p95": round(float(np.percentile(dev_us, 95)), 2),
+            "call_to_sync_us_median": round(float(np.median(wall_us)), 2),
+            "call_to_sync_us_p95": round(float(np.percentile(wall_us, 95)), 2),
+            "exact": exact}
+
+
+def input_hashes():
+    """SHA-256 of each workload's elevation field and levels (the members are a
+    fixed function of both)."""
+    import hashlib
+    from paper_2104_14667_amd import synth
+    out = {}
+    for name, wl in (("plain_small", synth.PLAIN_SMALL), ("streamed", synth.STREAMED),
+                     ("depth", synth.DEPTH), ("batched", synth.BATCHED), ("served", synth.SERVED)):
+        h = hashlib.sha256()
+        h.update(np.ascontiguousarray(wl.elevation()).tobytes())
+        h.update(np.ascontiguousarray(wl.levels()).tobytes())
+        out[name] = h.hexdigest()[:16]
+    return out
+
+
+def cpu_baseline_all_cores(ens, e, seconds):
+    """The same oracle on bands of rows in a thread pool over all host cores
+    (numpy ufuncs release the interpreter lock).  Members of a group of bands
+    are generated first, untimed; only the oracle calls are timed."""
+    import concurrent.futures as cf
+    import oracle
+    from paper_2104_14667_amd import synth
+    lv = ens.levels()
+    make = synth.mask if ens.kind == "mask" else synth.depth
+    cores = os.cpu_count() or 1
+    rows = 16
+    spent = 0.0
+    done = 0
+    y = 0
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        while spent < seconds and y < ens.H:
+            bands = [e[yy:yy + rows] for yy in range(y, min(ens.H, y + rows * cores), rows)]
+            y += rows * len(bands)
+            members = list(ex.map(lambda b: [make(b, int(L)) for L in lv], bands))
+            t0 = time.perf_counter()
+            list(ex.map(lambda bm: oracle.accumulate(bm[1], shape=bm[0].shape, outputs=ens.outputs),
+                        zip(bands, members)))
+            spent += time.perf_counter() - t0
+            done += sum(b.size for b in bands) * len(lv)
+    return dict(value=round(done / spent / 1e9, 4), unit="Gpixel-members/s", cores=cores,
+                kind="oracle", sample=f"{y} of {ens.H} rows x all {ens.N} members "
+                                      f"({done / 1e9:.3f} G px-members, {spent:.1f} s of oracle "
+                                      f"time), row bands in a {cores}-thread pool")
+
+
 def cpu_baseline(ens, e, seconds):
     """The oracle as it stands, single-threaded numpy, on bands of rows of the
     same workload until about `seconds` of CPU work; scaled to px-members/s."""
@@ -419,6 +495,7 @@ def main():
                         "chunk 8, PCIe-inclusive",
             **run_streamed(torch, synth.STREAMED, e1, args.stream_reps, {
                 "dual_buffer_linear": dict(nbuf=2, chunk_depth=8),
+                "dual_buffer_linear_event_waits": dict(nbuf=2, chunk_depth=8, host_paced=0),
                 "single_buffer_linear": dict(nbuf=1, chunk_depth=8),
                 "dual_buffer_tiled": dict(nbuf=2, chunk_depth=8, layout="tiled"),
             })}
@@ -433,8 +510,12 @@ def main():
     if args.served_seconds > 0:
         log("served", synth.SERVED.name)
         out["served"] = run_served(torch, args.served_seconds, args.spill_seconds)
+    log("plain small")
+    out["plain_small"] = run_plain_small(torch)
     log("cpu baseline")
     out["cpu_baseline"] = cpu_baseline(ens, e, args.cpu_seconds)
+    out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(ens, e, args.cpu_seconds)
+    out["inputs_sha256"] = input_hashes()
     out["host"] = {"cpu": platform.processor() or platform.machine(),
                    "os_cpu_count": os.cpu_count()}
     print(json.dumps(out), flush=True)

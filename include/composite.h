@@ -99,7 +99,14 @@ typedef struct cmp_opts {
                              be ordinary pageable memory; the host first copies
                              each chunk into a pinned bounce buffer of the
                              library (one per staging slot).  Default 0 */
-  int32_t reserved[4];    /* must be zero */
+  int32_t host_paced;     /* 0: the copy stream waits on the event of the
+                             kernel that last read a slot (device-side
+                             ordering only).  1: the host waits for that
+                             kernel before queueing the slot's next upload;
+                             the previous chunk's upload is still in flight
+                             then, so the copy engine never idles on a
+                             cross-stream wait.  Default 1 */
+  int32_t reserved[3];    /* must be zero */
 } cmp_opts;
 
 typedef struct cmp_ctx cmp_ctx;
@@ -200,7 +207,9 @@ typedef struct cmp_pool cmp_pool;
  * bytes past the end of the last raster (the kernels read whole 16-byte
  * vectors and may touch up to 15 bytes past a window's right edge).  The
  * caller keeps the memory alive until composite_pool_free.  The pool owns a
- * compute stream (default priority) and its descriptor buffers. */
+ * compute stream (default priority) and its descriptor buffers; one thread at
+ * a time may call composite_batch_run on it (servers created on the pool only
+ * read its rasters and may run concurrently). */
 int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count, int32_t W,
                           int32_t H, int64_t stride_bytes, int64_t pool_bytes, int32_t device);
 
@@ -328,7 +337,8 @@ int composite_session_submit(cmp_server *srv, int64_t sid, int32_t op, const int
 
 /* Waits until the request is complete (its viewport is in dst) or timeout_us
  * passes (CMP_ETIMEDOUT; negative waits forever).  Optionally returns the
- * submit and completion times (CLOCK_MONOTONIC nanoseconds). */
+ * submit and completion times (CLOCK_MONOTONIC nanoseconds).  The server keeps
+ * 16 bytes of timing per ticket until it is freed. */
 int composite_session_wait(cmp_server *srv, uint64_t ticket, int64_t timeout_us,
                            int64_t *t_submit_ns, int64_t *t_done_ns);
 

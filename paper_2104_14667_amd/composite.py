@@ -33,7 +33,7 @@ class cmp_opts(C.Structure):
                 ("copy_stream", C.c_void_p), ("compute_stream", C.c_void_p),
                 ("retain_members", C.c_int32), ("debug_poison", C.c_int32),
                 ("profile", C.c_int32), ("pageable_host", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("host_paced", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class cmp_request(C.Structure):

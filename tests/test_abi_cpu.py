@@ -37,6 +37,7 @@ def test_default_opts():
     assert (o.nbuf, o.chunk_depth, o.layout, o.tile_w, o.tile_h) == (2, 8, cb.CMP_LINEAR, 64, 64)
     assert o.copy_stream is None and o.compute_stream is None
     assert C.sizeof(cb.cmp_opts) == 72
+    assert o.host_paced == 1 and o.pageable_host == 0
 
 
 def test_argument_checks_before_any_device_call():

@@ -73,9 +73,10 @@ def test_ragged_streamed(W, H, nbuf, depth):
     stack = _random_stack(W * 7 + H * 3 + depth, n, H, W)
     exp = expect_oracle(stack, ALL, 32)
     host = pinned_copy(torch.from_numpy(stack))
-    with Composite(W, H, ALL, 32, nbuf=nbuf, chunk_depth=depth) as c:
-        c.add([host[i] for i in range(n)])
-        check_full(c, exp)
+    for paced in (1, 0):
+        with Composite(W, H, ALL, 32, nbuf=nbuf, chunk_depth=depth, host_paced=paced) as c:
+            c.add([host[i] for i in range(n)])
+            check_full(c, exp)
 
 
 def test_streamed_from_pageable_numpy():
@@ -138,9 +139,11 @@ def test_poisoned_staging_stays_exact():
     exp = expect_oracle(stack, ALL, 32)
     host = pinned_copy(torch.from_numpy(stack))
     for layout in (0, CMP_TILED):
-        with Composite(W, H, ALL, 32, chunk_depth=3, debug_poison=1, layout=layout) as c:
-            c.add([host[i] for i in range(n)])
-            check_full(c, exp)
+        for paced in (1, 0):
+            with Composite(W, H, ALL, 32, chunk_depth=3, debug_poison=1, layout=layout,
+                           host_paced=paced) as c:
+                c.add([host[i] for i in range(n)])
+                check_full(c, exp)
 
 
 # ---------------------------------------------------------------- add / remove
