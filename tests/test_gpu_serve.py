@@ -163,3 +163,52 @@ def test_full_served_shape_bursts():
                     exp = len(lvs) - np.searchsorted(lvs, ev, side="right")
                     assert np.array_equal(dst.numpy().view(np.uint32), exp)
             assert srv.stats()["requests"] == len(sched)
+
+
+def test_threaded_submitters_and_close_semantics():
+    """Several host threads submit to their own sessions at once; each result
+    equals the session replayed alone.  A close races with in-flight work only
+    as EBUSY; freeing the server drains what was submitted."""
+    import threading
+    from paper_2104_14667_amd.composite import CMP_EBUSY
+    wl, stack, sched = _small(seed=21, sessions=6, n=240)
+    P, H, W = stack.shape
+    buf = _pool(stack)
+    outs = [None] * len(sched)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        srv = Server(pool, max_batch=8, hbm_budget_bytes=8 * H * W * 4, max_view_pixels=256,
+                     tile_vecs=64, blocks_per_cu=2)
+        sids = [srv.open() for _ in range(wl.sessions)]
+        errors = []
+
+        def run(sid_idx):
+            try:
+                tickets = []
+                for i, r in enumerate(sched):
+                    if r["sid"] != sid_idx:
+                        continue
+                    dst = torch.full((r["vh"], r["vw"]), -1, dtype=torch.int32, pin_memory=True)
+                    op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
+                    tickets.append(srv.submit(sids[sid_idx], op, r["ids"],
+                                              (r["vx0"], r["vy0"], r["vw"], r["vh"]), dst))
+                    outs[i] = dst
+                for t in tickets[: len(tickets) // 2]:
+                    srv.wait(t)
+            except Exception as ex:          # surfaced below
+                errors.append(ex)
+
+        th = [threading.Thread(target=run, args=(k,)) for k in range(wl.sessions)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        try:
+            srv.close_session(sids[0])
+            closed = True
+        except CompositeError as ex:
+            assert ex.status == CMP_EBUSY
+            closed = False
+        srv.close()                          # drains every submitted request
+        assert closed in (True, False)
+    _check_alone(wl, stack, sched, outs)
