@@ -106,7 +106,20 @@ typedef struct cmp_opts {
                              the previous chunk's upload is still in flight
                              then, so the copy engine never idles on a
                              cross-stream wait.  Default 1 */
-  int32_t reserved[3];    /* must be zero */
+  int32_t verify_members; /* 1: keep a 64-bit fingerprint of every member with
+                             its id, so that composite_remove can refuse a
+                             raster that is not one that was added under that
+                             id (CMP_EINVAL, nothing changed).  The fingerprint
+                             is sum_j d_j * w_j mod 2^64 over the raster's
+                             little-endian 32-bit words d_j (the last one
+                             zero-padded), with w_j = lowbias32(j) | 1
+                             (Wellons' integer hash: x ^= x >> 16;
+                             x *= 0x7feb352d; x ^= x >> 15; x *= 0x846ca68b;
+                             x ^= x >> 16).  Costs one more device read of
+                             every added raster, makes add and remove wait for
+                             their kernels, and a remove of host rasters
+                             uploads them twice.  Default 0 */
+  int32_t reserved[2];    /* must be zero */
 } cmp_opts;
 
 typedef struct cmp_ctx cmp_ctx;
@@ -156,7 +169,9 @@ int composite_add_device(cmp_ctx *ctx, const uint8_t *const *dev_maps,
  * memory), or NULL with retain_members = 1 and ids given: the retained rasters
  * of those ids are used.  ids: NULL, or n ids; an id the registry does not
  * hold (counting multiplicity) gives CMP_ENOTMEMBER.  Without ids the caller
- * vouches that the rasters are members. */
+ * vouches that the rasters are members, unless the context verifies members
+ * (cmp_opts.verify_members): then a raster whose fingerprint is not held
+ * under its id (or among the members added without ids) gives CMP_EINVAL. */
 int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps,
                      const int64_t *ids, int32_t n, int32_t maps_on_device);
 

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libcomposite.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kernels.hip", "context.hip", "batch.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "context.hip", "batch.hip", "serve.hip", "verify.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -33,7 +33,8 @@ class cmp_opts(C.Structure):
                 ("copy_stream", C.c_void_p), ("compute_stream", C.c_void_p),
                 ("retain_members", C.c_int32), ("debug_poison", C.c_int32),
                 ("profile", C.c_int32), ("pageable_host", C.c_int32),
-                ("host_paced", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("host_paced", C.c_int32), ("verify_members", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class cmp_request(C.Structure):
@@ -276,7 +277,10 @@ class Composite:
         self.outputs = tuple(outputs)
         self.count_bits = int(count_bits)
         o = composite_default_opts()
+        fields = {f[0] for f in cmp_opts._fields_}
         for k, v in opts.items():
+            if k not in fields or k == "reserved":
+                raise TypeError(f"unknown option {k!r}")
             if k in ("copy_stream", "compute_stream") and v is not None and not isinstance(v, int):
                 v = int(v.cuda_stream)          # torch.cuda.Stream
             setattr(o, k, v)

@@ -27,6 +27,7 @@
 
 #include "../../include/composite.h"
 #include "kernels.h"
+#include "verify.h"
 
 namespace {
 
@@ -88,6 +89,12 @@ struct cmp_ctx {
   int64_t members = 0;
   int64_t host_members = 0;  // members that came through composite_add
   std::unordered_map<int64_t, std::vector<const uint8_t *>> held;
+  // With verify_members: the fingerprints of the members held under each id,
+  // and device/pinned buffers that receive the fingerprints of one call.
+  std::unordered_map<int64_t, std::vector<uint64_t>> fps;
+  unsigned long long *d_fp = nullptr;
+  unsigned long long *h_fp = nullptr;
+  int64_t fp_cap = 0;
 
   // Histogram counters (grown on demand).
   unsigned long long *d_hist = nullptr;
@@ -150,6 +157,8 @@ void free_all(cmp_ctx *ctx) {
   }
   if (ctx->ev_host_done) hipEventDestroy(ctx->ev_host_done);
   hipFree(ctx->d_hist);
+  hipFree(ctx->d_fp);
+  if (ctx->h_fp) hipHostFree(ctx->h_fp);
   for (auto &t : ctx->timed) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
@@ -304,8 +313,11 @@ int ensure_bounce(cmp_ctx *ctx) {
   return CMP_OK;
 }
 
-// Streams n host rasters through the staging slots with op add or sub.
-int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub, uint32_t outs) {
+// Streams n host rasters through the staging slots with op add or sub on the
+// outputs `outs` (none: upload only).  With fp non-null, fp[i] += the
+// fingerprint of raster i, taken from the staging slot.
+int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub, uint32_t outs,
+                   unsigned long long *fp = nullptr) {
   int rc = ensure_staging(ctx);
   if (rc != CMP_OK) return rc;
   const int d = ctx->o.chunk_depth;
@@ -353,7 +365,12 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
     }
     CMP_TRY(hipEventRecord(ctx->ev_copied[slot], ctx->copy_s));
     CMP_TRY(hipStreamWaitEvent(ctx->comp_s, ctx->ev_copied[slot], 0));
-    if (tiled) {
+    if (fp)
+      CMP_TRY(cmp::launch_fingerprint(nullptr, ctx->d_stage[slot], ctx->stage_stride, cnt, plane,
+                                      fp + k0, ctx->comp_s));
+    if (outs == 0) {
+      CMP_TRY(hipEventRecord(ctx->ev_free[slot], ctx->comp_s));
+    } else if (tiled) {
       // The receiving buffer is free again once it is repacked (the paper's
       // decoupled transfer and transform); the tiled copy is only read by the
       // kernel that follows on the same stream.
@@ -377,6 +394,52 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
   CMP_TRY(hipEventRecord(ctx->ev_host_done, ctx->copy_s));
   CMP_TRY(hipEventSynchronize(ctx->ev_host_done));
   return CMP_OK;
+}
+
+// Zeroed device buffer for the fingerprints of n rasters, on the compute stream.
+int begin_fingerprints(cmp_ctx *ctx, int64_t n) {
+  if (n > ctx->fp_cap) {
+    if (hipStreamSynchronize(ctx->comp_s) != hipSuccess) return CMP_EDEVICE;
+    hipFree(ctx->d_fp);
+    if (ctx->h_fp) hipHostFree(ctx->h_fp);
+    ctx->d_fp = nullptr;
+    ctx->h_fp = nullptr;
+    ctx->fp_cap = 0;
+    const int64_t cap = std::max<int64_t>(n, 1024);
+    if (hipMalloc((void **)&ctx->d_fp, cap * 8) != hipSuccess) return CMP_ENOMEM;
+    if (hipHostMalloc((void **)&ctx->h_fp, cap * 8, hipHostMallocDefault) != hipSuccess) return CMP_ENOMEM;
+    ctx->fp_cap = cap;
+  }
+  if (cmp::launch_fill(ctx->d_fp, 0, n * 8, ctx->comp_s) != hipSuccess) return CMP_EDEVICE;
+  return CMP_OK;
+}
+
+// Waits for the fingerprints of n rasters and copies them to the host.
+int end_fingerprints(cmp_ctx *ctx, int64_t n, std::vector<uint64_t> *out) {
+  if (hipMemcpyAsync(ctx->h_fp, ctx->d_fp, n * 8, hipMemcpyDeviceToHost, ctx->comp_s) != hipSuccess ||
+      hipStreamSynchronize(ctx->comp_s) != hipSuccess)
+    return CMP_EDEVICE;
+  out->assign(ctx->h_fp, ctx->h_fp + n);
+  return CMP_OK;
+}
+
+// Fingerprints of n rasters (device pointers, or host rasters uploaded
+// through the staging slots without touching the composite).
+int fingerprints(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool on_device,
+                 std::vector<uint64_t> *out) {
+  int rc = begin_fingerprints(ctx, n);
+  if (rc != CMP_OK) return rc;
+  if (on_device) {
+    const uint8_t **d_tab = nullptr;
+    rc = upload_table(ctx, maps, n, &d_tab);
+    if (rc != CMP_OK) return rc;
+    if (cmp::launch_fingerprint(d_tab, nullptr, 0, n, ctx->npix, ctx->d_fp, ctx->comp_s) != hipSuccess)
+      return CMP_EDEVICE;
+  } else {
+    rc = stream_members(ctx, maps, n, false, 0, ctx->d_fp);
+    if (rc != CMP_OK) return rc;
+  }
+  return end_fingerprints(ctx, n, out);
 }
 
 int check_ids_removable(const cmp_ctx *ctx, const int64_t *ids, int32_t n) {
@@ -420,6 +483,7 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
   if (o.layout != CMP_LINEAR && o.layout != CMP_TILED) return CMP_EINVAL;
   if (o.host_paced != 0 && o.host_paced != 1) return CMP_EINVAL;
   if (o.pageable_host != 0 && o.pageable_host != 1) return CMP_EINVAL;
+  if (o.verify_members != 0 && o.verify_members != 1) return CMP_EINVAL;
   if (o.layout == CMP_TILED) {
     if (o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64 && o.tile_w != 128) return CMP_EINVAL;
     if (o.tile_h < 1 || o.tile_h > 256) return CMP_EINVAL;
@@ -508,6 +572,7 @@ int composite_clear(cmp_ctx *ctx) {
   ctx->members = 0;
   ctx->host_members = 0;
   ctx->held.clear();
+  ctx->fps.clear();
   return CMP_OK;
 }
 
@@ -522,7 +587,14 @@ int composite_add(cmp_ctx *ctx, const uint8_t *const *host_maps, const int64_t *
   CMP_TRY(set_device(ctx));
   int rc = ensure_staging(ctx);
   if (rc != CMP_OK) return rc;
-  rc = stream_members(ctx, host_maps, n, false, ctx->outs);
+  const bool verify = ctx->o.verify_members != 0;
+  if (verify) {
+    rc = begin_fingerprints(ctx, n);
+    if (rc != CMP_OK) return rc;
+  }
+  rc = stream_members(ctx, host_maps, n, false, ctx->outs, verify ? ctx->d_fp : nullptr);
+  std::vector<uint64_t> fp;
+  if (rc == CMP_OK && verify) rc = end_fingerprints(ctx, n, &fp);
   if (rc != CMP_OK) {
     ctx->poisoned = true;
     return rc == CMP_ENOMEM ? CMP_ENOMEM : CMP_EDEVICE;
@@ -530,6 +602,8 @@ int composite_add(cmp_ctx *ctx, const uint8_t *const *host_maps, const int64_t *
   ctx->members += n;
   ctx->host_members += n;
   for (int32_t i = 0; i < n; ++i) ctx->held[ids ? ids[i] : -1].push_back(nullptr);
+  if (verify)
+    for (int32_t i = 0; i < n; ++i) ctx->fps[ids ? ids[i] : -1].push_back(fp[i]);
   return CMP_OK;
 }
 
@@ -550,9 +624,23 @@ int composite_add_device(cmp_ctx *ctx, const uint8_t *const *dev_maps, const int
     return rc;
   }
   CMP_TRY(composite_pass(ctx, d_tab, n, false, ctx->outs, false));
+  std::vector<uint64_t> fp;
+  if (ctx->o.verify_members) {
+    rc = begin_fingerprints(ctx, n);
+    if (rc == CMP_OK && cmp::launch_fingerprint(d_tab, nullptr, 0, n, ctx->npix, ctx->d_fp,
+                                                ctx->comp_s) != hipSuccess)
+      rc = CMP_EDEVICE;
+    if (rc == CMP_OK) rc = end_fingerprints(ctx, n, &fp);
+    if (rc != CMP_OK) {
+      ctx->poisoned = true;
+      return rc;
+    }
+  }
   ctx->members += n;
   for (int32_t i = 0; i < n; ++i)
     ctx->held[ids ? ids[i] : -1].push_back(ctx->o.retain_members ? dev_maps[i] : nullptr);
+  if (ctx->o.verify_members)
+    for (int32_t i = 0; i < n; ++i) ctx->fps[ids ? ids[i] : -1].push_back(fp[i]);
   return CMP_OK;
 }
 
@@ -592,6 +680,29 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *id
   const bool need_max = (ctx->outs & CMP_MAX) != 0;
   if (need_max && (!ctx->o.retain_members || ctx->host_members > 0)) return CMP_EUNSUPPORTED;
 
+  CMP_TRY(set_device(ctx));
+  // With verify_members every raster must carry a fingerprint held under its
+  // id; the check reads the rasters once before anything is changed.
+  auto fps = ctx->fps;
+  if (ctx->o.verify_members) {
+    std::vector<uint64_t> fp;
+    int rc = fingerprints(ctx, rm.data(), n, maps_on_device != 0, &fp);
+    if (rc != CMP_OK) {
+      ctx->poisoned = true;
+      return rc;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+      auto &v = fps[ids ? ids[i] : -1];
+      auto it = std::find(v.begin(), v.end(), fp[i]);
+      if (it == v.end()) return CMP_EINVAL;
+      v.erase(it);
+    }
+    for (auto it = fps.begin(); it != fps.end();) {
+      if (it->second.empty()) it = fps.erase(it);
+      else ++it;
+    }
+  }
+
   // Registry after the removal (committed only on success).
   auto held = ctx->held;
   for (int32_t i = 0; i < n; ++i) {
@@ -607,7 +718,6 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *id
       for (auto *p : kv.second) keep.push_back(p);
   }
 
-  CMP_TRY(set_device(ctx));
   const uint32_t sub_outs = ctx->outs & (CMP_COUNT | CMP_SUM);
   if (sub_outs) {
     int rc;
@@ -645,6 +755,7 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *id
     else ++it;
   }
   ctx->held.swap(held);
+  ctx->fps.swap(fps);
   ctx->members -= n;
   return CMP_OK;
 }
