@@ -263,7 +263,7 @@ def run_served(torch, duration_s, spill_duration_s):
     or removes 1-32 members and reads a 1024x1024 viewport.  Continuous
     batching against unbatched FIFO serving on the same GPU."""
     from paper_2104_14667_amd import synth
-    from paper_2104_14667_amd.composite import Pool, Server
+    from paper_2104_14667_amd.composite import CMP_OP_ADD, Pool, Server
     wl = synth.SERVED
     e = wl.elevation()
     lv = wl.levels()
@@ -280,13 +280,22 @@ def run_served(torch, duration_s, spill_duration_s):
                        "Poisson 2000 req/s, add/remove 1-32 members (60/40), 1024x1024 viewport",
            "requests": n, "offered_rps": wl.rate}
 
-    def one(name, sched, **opts):
+    def one(name, sched, held=None, **opts):
+        """Replays sched; held: per-session member lists loaded untimed first."""
         with Server(pool, **opts) as srv:
             sids = [srv.open() for _ in range(wl.sessions)]
+            if held:
+                dst = torch.empty((16, 16), dtype=torch.int32, pin_memory=True)
+                ts = [srv.submit(sids[k], CMP_OP_ADD, h, (0, 0, 16, 16), dst)
+                      for k, h in enumerate(held) if h]
+                for t in ts:
+                    srv.wait(t)
+            st0 = srv.stats()
             t0 = time.perf_counter()
             lat = srv.replay(sched, sids, ring, wl.view)
             wall = time.perf_counter() - t0
             st = srv.stats()
+        st = {k: st[k] - (st0[k] if k not in ("max_step", "resident_slots") else 0) for k in st}
         lat_ms = lat / 1e6
         pxm = sum(len(r["ids"]) for r in sched) * plane
         out[name] = {"p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
@@ -295,8 +304,25 @@ def run_served(torch, duration_s, spill_duration_s):
                      "completed_rps": round(len(sched) / wall, 1),
                      "steps": st["steps"], "mean_step": round(st["requests"] / max(1, st["steps"]), 2),
                      "max_step": st["max_step"], "spills": st["spills"], "restores": st["restores"],
+                     "drops": st["drops"], "rebuilds": st["rebuilds"],
                      "device_ms_per_request": round(st["device_ms"] / max(1, st["requests"]), 4),
                      "gpx_member_per_s": round(pxm / wall / 1e9, 1)}
+
+    def window(start_s, dur_s):
+        """Requests in [start_s, start_s + dur_s) of the schedule, re-timed from
+        zero, and each session's members at start_s."""
+        k0, k1 = int(wl.rate * start_s), int(wl.rate * (start_s + dur_s))
+        full = sched if k1 <= len(sched) else wl.schedule(k1)
+        held = [[] for _ in range(wl.sessions)]
+        for r in full[:k0]:
+            h = held[r["sid"]]
+            for i in r["ids"]:
+                if r["op"] == "add":
+                    h.append(int(i))
+                else:
+                    h.remove(int(i))
+        t0 = full[k0]["t"] if k0 else 0.0
+        return [dict(r, t=r["t"] - t0) for r in full[k0:k1]], held
 
     with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
         one("continuous_batching", sched, max_batch=64, overlap=1,
@@ -304,10 +330,18 @@ def run_served(torch, duration_s, spill_duration_s):
         one("unbatched_fifo", sched, max_batch=1, overlap=0,
             hbm_budget_bytes=wl.sessions * plane * 4)
         if spill_duration_s > 0:
-            m = int(wl.rate * spill_duration_s)
-            out["spill_requests"] = m
-            one("continuous_batching_budget_half", sched[:m], max_batch=64, overlap=1,
-                hbm_budget_bytes=wl.sessions // 2 * plane * 4)
+            # Half the sessions fit.  Evicted composites are dropped and rebuilt
+            # from their members (default), or copied to host memory and back
+            # (remat_max_members = 0).  Windows: the first seconds of the
+            # schedule, and the seconds from 10 s on with the sessions' members
+            # at 10 s loaded first (about 300 members per session).
+            out["budget_half_window_s"] = spill_duration_s
+            for label, start in (("cold", 0.0), ("from_10s", 10.0)):
+                win, held = window(start, spill_duration_s)
+                for policy, remat in (("rebuild", 2048), ("copy", 0)):
+                    one(f"budget_half_{label}_{policy}", win, held=held if start else None,
+                        max_batch=64, overlap=1, hbm_budget_bytes=wl.sessions // 2 * plane * 4,
+                        remat_max_members=remat)
     del buf
     torch.cuda.empty_cache()
     return out
@@ -424,8 +458,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--served-seconds", type=float, default=20.0,
                     help="length of the open-loop served schedule (0 skips it)")
-    ap.add_argument("--spill-seconds", type=float, default=1.0,
-                    help="length of the served run with half the sessions' HBM budget")
+    ap.add_argument("--spill-seconds", type=float, default=2.0,
+                    help="length of each served window with half the sessions' HBM budget")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy of 1 GiB (torch.neg on int32) "

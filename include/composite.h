@@ -295,9 +295,14 @@ int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items);
  * second stream, so the next step's launch overlaps them.  Requests of one
  * session are applied in submission order; sessions interleave.  Session
  * composites live in a device slab of hbm_budget_bytes; when a request needs
- * a session that is not resident and the slab is full, the least recently
- * used session that is not part of the step is spilled to pinned host memory
- * (and restored when it is next needed).
+ * a session that is not resident and the slab is full, a session that is not
+ * part of the step is evicted: the one with the lowest GreedyDual priority
+ * (Young 1994; Cao and Irani 1997), which is the priority of the last evicted
+ * session at its last use plus the cost of bringing it back, so cheap
+ * sessions go first and the policy is LRU when costs are equal.  An evicted
+ * composite is dropped and later rebuilt from the session's members (the
+ * cost: its member count) or copied to pinned host memory and back (the
+ * cost: remat_max_members), see cmp_server_opts.remat_max_members.
  */
 typedef struct cmp_server cmp_server;
 
@@ -316,7 +321,15 @@ typedef struct cmp_server_opts {
                                viewports are still being copied out; 0: each
                                step completes before the next starts.
                                Default 1 */
-  int32_t reserved[6];      /* must be zero */
+  int32_t remat_max_members; /* eviction of a resident composite when a step
+                               needs its slot: a session holding at most this
+                               many members is dropped, and rebuilt by counting
+                               its members in the resident pool when next used
+                               (reads members * W*H bytes of HBM); a larger one
+                               is copied to pinned host memory and back (2 *
+                               W*H*4 bytes over PCIe).  0 copies all but empty
+                               sessions; at most 65535.  Default 2048 */
+  int32_t reserved[5];      /* must be zero */
 } cmp_server_opts;
 
 void composite_default_server_opts(cmp_server_opts *opts);
@@ -358,8 +371,12 @@ int composite_session_wait(cmp_server *srv, uint64_t ticket, int64_t timeout_us,
                            int64_t *t_submit_ns, int64_t *t_done_ns);
 
 typedef struct cmp_server_stats {
-  int64_t requests, steps, max_step, spills, restores, resident_slots;
+  int64_t requests, steps, max_step;
+  int64_t spills, restores;  /* evictions copied to host memory, and copies back */
+  int64_t resident_slots;
   double device_ms;          /* summed device time of the update launches */
+  int64_t drops, rebuilds;   /* evictions without a copy, and composites
+                                rebuilt from their members */
 } cmp_server_stats;
 
 int composite_server_stats(cmp_server *srv, cmp_server_stats *st);

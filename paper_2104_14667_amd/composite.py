@@ -60,13 +60,13 @@ class cmp_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_sessions", C.c_int32),
                 ("max_batch", C.c_int32), ("max_view_pixels", C.c_int32),
                 ("tile_vecs", C.c_int32), ("blocks_per_cu", C.c_int32), ("overlap", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("remat_max_members", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class cmp_server_stats(C.Structure):
     _fields_ = [("requests", C.c_int64), ("steps", C.c_int64), ("max_step", C.c_int64),
                 ("spills", C.c_int64), ("restores", C.c_int64), ("resident_slots", C.c_int64),
-                ("device_ms", C.c_double)]
+                ("device_ms", C.c_double), ("drops", C.c_int64), ("rebuilds", C.c_int64)]
 
 
 class cmp_replay_req(C.Structure):
@@ -468,7 +468,10 @@ class Server:
 
     def __init__(self, pool: Pool, **opts):
         o = composite_default_server_opts()
+        fields = {f[0] for f in cmp_server_opts._fields_}
         for k, v in opts.items():
+            if k not in fields or k == "reserved":
+                raise TypeError(f"unknown server option {k!r}")
             setattr(o, k, v)
         self.opts = o
         self.pool = pool

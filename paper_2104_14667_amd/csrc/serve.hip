@@ -44,10 +44,12 @@ int64_t now_ns() {
       .count();
 }
 
+enum : int32_t { kModeAdd = 0, kModeSub = 1, kModeSet = 2 };
+
 struct SReq {
   uint32_t *comp;     // session composite (device)
   uint32_t *stage;    // viewport staging (device), vh rows of vw
-  int32_t sub, ids_off, n;
+  int32_t mode, ids_off, n;  // kMode*: composite += / -= / = count of ids
   int32_t vx0, vy0, vw, vh;
   int32_t pad;
 };
@@ -62,8 +64,9 @@ struct SHeader {
 static_assert(sizeof(SHeader) == 64, "arena header is 64 bytes");
 
 // One work item: rows [row0, row0 + nrows) of a session composite.  Each thread
-// updates 16 pixels (count +/- the nonzero members) and copies the pixels that
-// fall in the request's viewport to staging.
+// updates 16 pixels (count +/- the nonzero members, or count set to that of
+// the whole working set when the composite is rebuilt) and copies the pixels
+// that fall in the request's viewport to staging.
 __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base, int64_t stride,
                                                int32_t W, const char *__restrict__ arena,
                                                uint32_t *__restrict__ queue) {
@@ -111,8 +114,9 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       uint32_t nv[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        uint4 o = c[q];
-        if (R.sub) {
+        uint4 o = make_uint4(0u, 0u, 0u, 0u);
+        if (R.mode != kModeSet) o = c[q];
+        if (R.mode == kModeSub) {
           o.x -= cnt[4 * q]; o.y -= cnt[4 * q + 1]; o.z -= cnt[4 * q + 2]; o.w -= cnt[4 * q + 3];
         } else {
           o.x += cnt[4 * q]; o.y += cnt[4 * q + 1]; o.z += cnt[4 * q + 2]; o.w += cnt[4 * q + 3];
@@ -144,10 +148,16 @@ struct Request {
 struct Session {
   bool open = false;
   int slot = -1;            // resident slot or -1
-  bool has_data = false;    // false: all zero (new); true: data in slot or spill
-  uint32_t *spill = nullptr;  // pinned host copy while not resident
+  bool has_data = false;    // false: all zero (new); true: data in slot, spill, or dropped
+  bool dropped = false;     // evicted without a copy: rebuilt from `applied` when next used
+  uint32_t *spill = nullptr;  // pinned host copy while spilled
   std::unordered_map<int32_t, int64_t> projected;  // working set after queued requests
+  std::unordered_map<int32_t, int64_t> applied;    // working set after launched requests
+  int64_t applied_n = 0;
   int64_t inflight = 0;     // requests submitted and not completed
+  // Eviction priority (GreedyDual): the floor at the last use plus the cost
+  // of bringing the composite back; ties go to the least recently used.
+  double gd_h = 0.0;
   uint64_t last_use = 0;
 };
 
@@ -194,6 +204,7 @@ struct cmp_server {
   std::deque<Step> steps;        // launched, not completed (for the completer)
   uint64_t steps_launched = 0, steps_completed = 0;
   uint64_t use_clock = 0;
+  double gd_floor = 0.0;         // priority of the last evicted session
   bool stop = false;
   bool worker_done = false;
   int failed = CMP_OK;           // sticky device failure
@@ -211,8 +222,11 @@ void fail(cmp_server *s, int rc) {
 }
 
 // Makes `sid` resident.  Called by the worker with the server lock held.
+// *rebuild is set when the slot holds no valid composite and the step's
+// kernel must write the composite of the session's whole working set.
 hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
-                         const std::unordered_set<int64_t> &in_step) {
+                         const std::unordered_set<int64_t> &in_step, bool *rebuild) {
+  *rebuild = false;
   if (ss.slot >= 0) return hipSuccess;
   int slot = -1;
   for (size_t i = 0; i < s->slot_owner.size(); ++i)
@@ -221,42 +235,55 @@ hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
       break;
     }
   if (slot < 0) {
-    // spill the least recently used resident session outside this step
+    // evict the resident session outside this step with the lowest priority
     int64_t victim = -1;
-    uint64_t oldest = UINT64_MAX;
+    double low = 0.0;
+    uint64_t oldest = 0;
     for (size_t i = 0; i < s->slot_owner.size(); ++i) {
       const int64_t v = s->slot_owner[i];
       if (in_step.count(v)) continue;
-      const uint64_t lu = s->sessions[v].last_use;
-      if (lu < oldest) {
-        oldest = lu;
+      const Session &c = s->sessions[v];
+      if (victim < 0 || c.gd_h < low || (c.gd_h == low && c.last_use < oldest)) {
+        low = c.gd_h;
+        oldest = c.last_use;
         victim = v;
         slot = (int)i;
       }
     }
     if (victim < 0) return hipErrorOutOfMemory;  // cannot happen: slots >= max_batch
     Session &vs = s->sessions[victim];
-    if (!vs.spill) {
-      hipError_t e = hipHostMalloc((void **)&vs.spill, s->comp_bytes, hipHostMallocDefault);
+    s->gd_floor = vs.gd_h;
+    if (vs.applied_n <= s->o.remat_max_members) {
+      // recounting its members from the resident pool costs less than moving
+      // the composite out and back over PCIe: drop it
+      vs.dropped = true;
+      s->st.drops += 1;
+    } else {
+      if (!vs.spill) {
+        hipError_t e = hipHostMalloc((void **)&vs.spill, s->comp_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+      }
+      // ordered after every kernel that wrote the slot (same stream)
+      hipError_t e = hipMemcpyAsync(vs.spill, s->slab + (int64_t)slot * (s->comp_bytes / 4),
+                                    s->comp_bytes, hipMemcpyDeviceToHost, s->comp);
       if (e != hipSuccess) return e;
+      vs.dropped = false;
+      s->st.spills += 1;
     }
-    // ordered after every kernel that wrote the slot (same stream)
-    hipError_t e = hipMemcpyAsync(vs.spill, s->slab + (int64_t)slot * (s->comp_bytes / 4),
-                                  s->comp_bytes, hipMemcpyDeviceToHost, s->comp);
-    if (e != hipSuccess) return e;
     vs.slot = -1;
     s->slot_owner[slot] = -1;
-    s->st.spills += 1;
   }
   uint32_t *dst = s->slab + (int64_t)slot * (s->comp_bytes / 4);
-  hipError_t e;
-  if (ss.has_data && ss.spill) {
-    e = hipMemcpyAsync(dst, ss.spill, s->comp_bytes, hipMemcpyHostToDevice, s->comp);
+  if (ss.has_data && !ss.dropped) {
+    hipError_t e = hipMemcpyAsync(dst, ss.spill, s->comp_bytes, hipMemcpyHostToDevice, s->comp);
+    if (e != hipSuccess) return e;
     s->st.restores += 1;
   } else {
-    e = cmp::launch_fill(dst, 0, s->comp_bytes, s->comp);
+    // new (all zero) or dropped: the step writes the whole composite
+    *rebuild = true;
+    if (ss.has_data) s->st.rebuilds += 1;
   }
-  if (e != hipSuccess) return e;
+  ss.dropped = false;
   ss.slot = slot;
   ss.has_data = true;
   s->slot_owner[slot] = sid;
@@ -304,23 +331,44 @@ void worker_body(cmp_server *s) {
     for (auto &r : step) in_step.insert(r.sid);
     // residency and descriptors (slots are touched by this thread only)
     std::vector<SReq> rd(step.size());
+    std::vector<std::vector<int32_t>> rebuilt(step.size());  // ids of rebuilt composites
     std::vector<SItem> items;
     int64_t nids = 0;
     hipError_t e = hipSuccess;
     // Residency changes hold the lock: sessions may be opened and closed
     // concurrently, and a close releases the slot of an idle session.
     std::unique_lock<std::mutex> lk(s->mu);
-    for (auto &r : step) s->sessions[r.sid].last_use = ++s->use_clock;
     for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
       Request &r = step[k];
       Session *ss = &s->sessions[r.sid];
-      e = make_resident(s, *ss, r.sid, in_step);
+      bool rebuild = false;
+      e = make_resident(s, *ss, r.sid, in_step, &rebuild);
+      if (e != hipSuccess) break;
+      // the working set the composite holds once this request has run
+      for (int32_t id : r.ids) {
+        if (r.op == CMP_OP_REMOVE) {
+          if (--ss->applied[id] == 0) ss->applied.erase(id);
+          ss->applied_n -= 1;
+        } else {
+          ss->applied[id] += 1;
+          ss->applied_n += 1;
+        }
+      }
+      // GreedyDual: a session stays ahead of the floor by what its eviction
+      // would cost (members to recount, or the copy when that is cheaper)
+      ss->gd_h = s->gd_floor + 1.0 + (double)std::min<int64_t>(ss->applied_n, s->o.remat_max_members);
+      ss->last_use = ++s->use_clock;
       SReq &d = rd[k];
       d.comp = s->slab + (int64_t)ss->slot * (s->comp_bytes / 4);
       d.stage = s->stage[half] + (int64_t)k * view_stride;
-      d.sub = r.op == CMP_OP_REMOVE;
+      d.mode = rebuild ? kModeSet : r.op == CMP_OP_REMOVE ? kModeSub : kModeAdd;
+      if (rebuild) {
+        std::vector<int32_t> &v = rebuilt[k];
+        v.reserve(ss->applied_n);
+        for (auto &kv : ss->applied) v.insert(v.end(), (size_t)kv.second, kv.first);
+      }
       d.ids_off = (int32_t)nids;
-      d.n = (int32_t)r.ids.size();
+      d.n = (int32_t)(rebuild ? rebuilt[k].size() : r.ids.size());
       d.vx0 = r.vx0;
       d.vy0 = r.vy0;
       d.vw = r.vw;
@@ -351,9 +399,10 @@ void worker_body(cmp_server *s) {
     std::memcpy(h, &hd, sizeof(hd));
     std::memcpy(h + hd.reqs_off, rd.data(), sizeof(SReq) * rd.size());
     std::memcpy(h + hd.items_off, items.data(), sizeof(SItem) * items.size());
-    for (size_t k = 0; k < step.size(); ++k)
-      if (!step[k].ids.empty())
-        std::memcpy(h + hd.ids_off + 4 * (int64_t)rd[k].ids_off, step[k].ids.data(), 4 * step[k].ids.size());
+    for (size_t k = 0; k < step.size(); ++k) {
+      const std::vector<int32_t> &v = rd[k].mode == kModeSet ? rebuilt[k] : step[k].ids;
+      if (!v.empty()) std::memcpy(h + hd.ids_off + 4 * (int64_t)rd[k].ids_off, v.data(), 4 * v.size());
+    }
     const int grid = s->pool->cus * s->o.blocks_per_cu;
     e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
     if (e == hipSuccess) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
@@ -446,6 +495,7 @@ void composite_default_server_opts(cmp_server_opts *o) {
   o->tile_vecs = 256;
   o->blocks_per_cu = 2;
   o->overlap = 1;
+  o->remat_max_members = 2048;
 }
 
 int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_opts *opts) {
@@ -461,7 +511,7 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
   const int64_t comp_bytes = (int64_t)pool->W * pool->H * 4;
   if (o.max_batch < 1 || o.max_batch > 4096 || o.max_sessions < 1 || o.max_view_pixels < 1 ||
       o.tile_vecs < 64 || o.tile_vecs > 65536 || o.blocks_per_cu < 1 || o.blocks_per_cu > 16 ||
-      (o.overlap != 0 && o.overlap != 1))
+      (o.overlap != 0 && o.overlap != 1) || o.remat_max_members < 0 || o.remat_max_members > 65535)
     return CMP_EINVAL;
   // a step must fit in the slab: at least max_batch resident composites
   if (o.hbm_budget_bytes / comp_bytes < o.max_batch) return CMP_EINVAL;
@@ -491,9 +541,10 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
     const int64_t nvr = s->W / 16;
     const int64_t rows = std::max<int64_t>(1, o.tile_vecs / nvr);
     const int64_t items = (int64_t)o.max_batch * ((s->H + rows - 1) / rows);
-    // ids per request are capped at 65535 by submit
+    // ids per request are capped at 65535 by submit; a rebuilt composite
+    // takes at most remat_max_members more (its working set before the request)
     s->arena_cap = 64 + 64 + (int64_t)sizeof(SReq) * o.max_batch + 64 + (int64_t)sizeof(SItem) * items +
-                   4 * (int64_t)o.max_batch * 65535;
+                   4 * (int64_t)o.max_batch * (65535 + (int64_t)o.remat_max_members);
     for (int i = 0; i < 2 && rc == CMP_ENOMEM; ++i) {
       if (hipHostMalloc((void **)&s->h_arena[i], s->arena_cap, hipHostMallocDefault) != hipSuccess ||
           hipMalloc((void **)&s->d_arena[i], s->arena_cap) != hipSuccess ||

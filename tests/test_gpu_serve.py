@@ -56,23 +56,33 @@ def _check_alone(wl, stack, sched, outs):
             assert np.array_equal(got, v["count"]), f"request {i} (session {sid})"
 
 
-@pytest.mark.parametrize("max_batch,overlap,budget_slots", [(1, 0, 8), (4, 1, 4), (64, 1, 64),
-                                                            (3, 0, 3), (8, 1, 10)])
-def test_mix_equals_alone(max_batch, overlap, budget_slots):
-    wl, stack, sched = _small(seed=max_batch + 10 * overlap)
+# remat: 0 copies every evicted non-empty composite to host memory and back, 65535
+# drops and rebuilds every one, 4 drops sessions of at most 4 members only
+@pytest.mark.parametrize("max_batch,overlap,budget_slots,remat", [
+    (1, 0, 8, 0), (4, 1, 4, 0), (64, 1, 64, 512), (3, 0, 3, 65535), (8, 1, 10, 4),
+    (4, 1, 4, 512), (1, 0, 3, 4)])
+def test_mix_equals_alone(max_batch, overlap, budget_slots, remat):
+    wl, stack, sched = _small(seed=max_batch + 10 * overlap + remat % 7)
     P, H, W = stack.shape
-    say("serve mix", max_batch, overlap, budget_slots)
+    say("serve mix", max_batch, overlap, budget_slots, remat)
     buf = _pool(stack)
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=max_batch, overlap=overlap,
                     hbm_budget_bytes=budget_slots * H * W * 4, max_view_pixels=16 * 16,
-                    tile_vecs=64, blocks_per_cu=2) as srv:
+                    tile_vecs=64, blocks_per_cu=2, remat_max_members=remat) as srv:
             sids, outs = _run_mix(srv, wl, sched)
             st = srv.stats()
             assert st["requests"] == len(sched)
             assert st["max_step"] <= max_batch
             if budget_slots < wl.sessions:
-                assert st["spills"] > 0 and st["restores"] > 0
+                if remat == 0:
+                    assert st["spills"] > 0 and st["restores"] > 0
+                elif remat >= P * 8:
+                    assert st["drops"] > 0 and st["rebuilds"] > 0 and st["spills"] == 0
+                else:
+                    assert st["drops"] > 0 and st["spills"] > 0
+            else:
+                assert st["spills"] == st["drops"] == 0
     _check_alone(wl, stack, sched, outs)
 
 
@@ -123,11 +133,14 @@ def test_replay_small_open_loop():
             assert srv.stats()["requests"] == len(sched)
 
 
-def test_full_served_shape_bursts():
-    """Sessions of 4096x4096 over a pool of 1024 depth maps; bursts of 64
-    requests are checked against the closed form of each session's ids."""
+@pytest.mark.parametrize("remat", [2048, 0])
+def test_full_served_shape_bursts(remat):
+    """Sessions of 4096x4096 over a pool of 1024 depth maps, half of them
+    resident; bursts of 64 requests are checked against the closed form of
+    each session's ids.  Evicted composites are rebuilt from their members
+    (remat 2048) or copied to host memory and back (remat 0)."""
     wl = synth.SERVED
-    say("full served", wl.name)
+    say("full served", wl.name, remat)
     e = wl.elevation()
     lv = wl.levels()
     et = torch.from_numpy(e).cuda()
@@ -139,7 +152,8 @@ def test_full_served_shape_bursts():
     sched = wl.schedule(256)
     held = [[] for _ in range(wl.sessions)]
     with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
-        with Server(pool, max_batch=64, hbm_budget_bytes=128 * plane * 4) as srv:
+        with Server(pool, max_batch=64, hbm_budget_bytes=128 * plane * 4,
+                    remat_max_members=remat) as srv:
             sids = [srv.open() for _ in range(wl.sessions)]
             for b0 in range(0, len(sched), 64):
                 burst = sched[b0:b0 + 64]
@@ -162,7 +176,12 @@ def test_full_served_shape_bursts():
                     ev = e[r["vy0"]:r["vy0"] + r["vh"], r["vx0"]:r["vx0"] + r["vw"]]
                     exp = len(lvs) - np.searchsorted(lvs, ev, side="right")
                     assert np.array_equal(dst.numpy().view(np.uint32), exp)
-            assert srv.stats()["requests"] == len(sched)
+            st = srv.stats()
+            assert st["requests"] == len(sched)
+            if remat:
+                assert st["drops"] > 0 and st["spills"] == 0
+            else:
+                assert st["spills"] > 0                     # only empty sessions are dropped
 
 
 def test_threaded_submitters_and_close_semantics():
