@@ -240,7 +240,17 @@ typedef struct cmp_request {
   int64_t out_pitch;      /* elements between output rows, >= w */
 } cmp_request;
 
-enum cmp_batch_mode { CMP_BATCH_PERSISTENT = 0, CMP_BATCH_PER_REQUEST = 1 };
+/* PERSISTENT: one persistent launch over (request, band of crop rows) work
+ * items; every item reads its request's members.  PER_REQUEST: one plain
+ * launch per request, in order (the baseline).  SHARED: one persistent
+ * launch over tiles of 1024 pixels of a raster row; a tile reads each pool
+ * member that any request covering it holds once, and adds it to every such
+ * request (accumulators in LDS, up to 32 requests per pass over a tile).  It
+ * needs distinct ids within each request and a pool of at most 65536
+ * rasters whose member masks fit in LDS; a batch that does not qualify runs
+ * in the PERSISTENT mode with the same parameters (composite_batch_last
+ * reports which mode ran). */
+enum cmp_batch_mode { CMP_BATCH_PERSISTENT = 0, CMP_BATCH_PER_REQUEST = 1, CMP_BATCH_SHARED = 2 };
 
 /* Order of the work queue.  COST: largest items first.  ROWS: by the first
  * raster row an item reads, so that concurrently running items of different
@@ -252,21 +262,26 @@ typedef struct cmp_tune {
   int32_t mode;           /* cmp_batch_mode.  PER_REQUEST launches one plain
                              kernel per request, in order (the baseline) */
   int32_t tile_vecs;      /* persistent mode: 16-pixel vectors per work item
-                             (a band of whole crop rows), 64 .. 65536 */
-  int32_t blocks_per_cu;  /* persistent mode: workgroups of 256 per compute
-                             unit, 1 .. 16 */
-  int32_t use_graph;      /* persistent mode: 1 replays a captured hipGraph of
-                             [queue reset, persistent kernel]; captured once
-                             per grid size and load kind, and reused */
+                             (a band of whole crop rows), 64 .. 65536; checked
+                             in the shared mode too (its fallback) */
+  int32_t blocks_per_cu;  /* persistent and shared modes: workgroups of 256
+                             per compute unit, 1 .. 16 */
+  int32_t use_graph;      /* persistent and shared modes: 1 replays a captured
+                             hipGraph of [queue reset, kernel]; captured once
+                             per mode, grid size and load kind, and reused */
   int32_t order;          /* persistent mode: cmp_batch_order */
   int32_t stream_loads;   /* 1: member loads carry the non-temporal hint
                              (nothing is re-read); 0: plain loads, so rows
                              shared by requests can hit in the caches */
-  int32_t reserved[2];    /* must be zero */
+  int32_t slots;          /* shared mode: requests per pass over a tile, 4 .. 32,
+                             or 0 for as many as LDS holds.  Fewer slots use
+                             less LDS (more workgroups per compute unit) but
+                             need more passes where many requests overlap */
+  int32_t reserved[1];    /* must be zero */
 } cmp_tune;
 
-/* Fills *t with the defaults (persistent, tile_vecs 1024, blocks_per_cu 8,
- * use_graph 1, order ROWS, stream_loads 0).  NULL is ignored. */
+/* Fills *t with the defaults (shared, tile_vecs 1024, blocks_per_cu 4,
+ * use_graph 1, order ROWS, stream_loads 0, slots 24).  NULL is ignored. */
 void composite_default_tune(cmp_tune *t);
 
 /* Runs nreq requests and returns when every output is written.  Every
@@ -278,8 +293,9 @@ int composite_batch_run(cmp_pool *pool, const cmp_request *reqs, int32_t nreq,
 
 /* Device time in milliseconds of the last composite_batch_run, measured with
  * HIP events around its launches on the pool's stream (descriptor upload
- * excluded), and the number of work items it ran. */
-int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items);
+ * excluded), the number of work items it ran (tiles in the shared mode), and
+ * (mode: NULL or a cmp_batch_mode out) the mode that ran. */
+int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items, int32_t *mode);
 
 /* ------------------------------------------------------------------------
  * Served sessions: interactive add/remove against per-session composites.

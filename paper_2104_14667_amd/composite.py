@@ -46,13 +46,13 @@ class cmp_request(C.Structure):
 class cmp_tune(C.Structure):
     _fields_ = [("mode", C.c_int32), ("tile_vecs", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("use_graph", C.c_int32), ("order", C.c_int32), ("stream_loads", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("slots", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 CMP_ORDER_COST, CMP_ORDER_ROWS = 0, 1
 
 
-CMP_BATCH_PERSISTENT, CMP_BATCH_PER_REQUEST = 0, 1
+CMP_BATCH_PERSISTENT, CMP_BATCH_PER_REQUEST, CMP_BATCH_SHARED = 0, 1, 2
 CMP_OP_ADD, CMP_OP_REMOVE = 0, 1
 
 
@@ -108,7 +108,7 @@ _SIGS = {
     "composite_pool_free": (None, [_vp]),
     "composite_default_tune": (None, [_P(cmp_tune)]),
     "composite_batch_run": (C.c_int, [_vp, _P(cmp_request), _i32, _P(cmp_tune)]),
-    "composite_batch_last": (C.c_int, [_vp, _P(C.c_double), _P(_i64)]),
+    "composite_batch_last": (C.c_int, [_vp, _P(C.c_double), _P(_i64), _P(_i32)]),
     "composite_default_server_opts": (None, [_P(cmp_server_opts)]),
     "composite_server_create": (C.c_int, [_P(_vp), _vp, _P(cmp_server_opts)]),
     "composite_server_free": (None, [_vp]),
@@ -409,17 +409,20 @@ def composite_batch_run(pool: int, requests, tune: Optional[cmp_tune] = None) ->
 
 
 def composite_batch_last(pool: int):
+    """(device ms, work items, mode that ran) of the last batch."""
     ms = C.c_double()
     items = C.c_int64()
-    _check(lib.composite_batch_last(pool, C.byref(ms), C.byref(items)), "composite_batch_last")
-    return ms.value, items.value
+    mode = C.c_int32()
+    _check(lib.composite_batch_last(pool, C.byref(ms), C.byref(items), C.byref(mode)),
+           "composite_batch_last")
+    return ms.value, items.value, mode.value
 
 
 def make_tune(mode=CMP_BATCH_PERSISTENT, tile_vecs=1024, blocks_per_cu=8, use_graph=1,
-              order=CMP_ORDER_ROWS, stream_loads=0) -> cmp_tune:
+              order=CMP_ORDER_ROWS, stream_loads=0, slots=0) -> cmp_tune:
     t = composite_default_tune()
     t.mode, t.tile_vecs, t.blocks_per_cu, t.use_graph = mode, tile_vecs, blocks_per_cu, use_graph
-    t.order, t.stream_loads = order, stream_loads
+    t.order, t.stream_loads, t.slots = order, stream_loads, slots
     return t
 
 

@@ -10,6 +10,14 @@
 // launch (queue reset + kernel) is captured once into a hipGraph and replayed,
 // its per-batch data living in the arena it reads.  The per-request mode runs
 // one plain launch per request, in order, as the baseline.
+//
+// The shared mode reads each pool raster's bytes once for all the requests
+// that want them: a workgroup owns a tile of 1024 pixels of one raster row,
+// finds the requests whose windows cover it (up to S per pass), marks in LDS
+// which of them hold each pool member, and streams every marked member's
+// tile once, adding its nonzero pixels to an LDS accumulator per covering
+// request that holds it.  The accumulators then go to those requests'
+// outputs.
 
 #include <hip/hip_runtime.h>
 
@@ -112,6 +120,279 @@ __global__ __launch_bounds__(256) void k_batch(const uint8_t *__restrict__ base,
   }
 }
 
+// ---------------------------------------------------------------- shared mode
+
+constexpr int kShTile = 1024;   // pixels per tile
+constexpr int kShMaxSlots = 32; // requests per pass (bits of a member mask)
+constexpr int kShUnroll = 8;    // member loads per group (two groups in flight)
+// Members streamed between flushes of the 8-bit accumulators (each byte lane
+// then holds at most this many, < 256); a multiple of two groups.
+constexpr int kShFlush = 240;
+static_assert(kShFlush % (2 * kShUnroll) == 0 && kShFlush < 256, "flush interval");
+constexpr int kShPad = 3 * kShUnroll;  // list entries the prefetch may read past the end
+
+typedef unsigned int u32u __attribute__((aligned(1)));
+typedef const __attribute__((address_space(1))) u32u gu32u;
+typedef unsigned int u32x2u __attribute__((ext_vector_type(2), aligned(1)));
+typedef const __attribute__((address_space(1))) u32x2u gu32x2u;
+
+// Nonzero flags of the 4 bytes of w, one per byte (0 or 1): bit 7 of
+// (b & 0x7f) + 0x7f is set iff the low 7 bits are nonzero, and b's own bit 7
+// covers the rest; no byte carries into the next.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t w) {
+  const uint32_t t = ((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w;
+  return (t >> 7) & 0x01010101u;
+}
+
+// PX pixels of one raster per thread (4 or 8 bytes, any alignment), and their
+// nonzero flags as 8-bit lanes of one LDS accumulator word.
+template <int PX> struct ShPx;
+template <> struct ShPx<4> {
+  typedef uint32_t Acc;
+  template <bool NT> __device__ static uint32_t load(const uint8_t *p) {
+    if constexpr (NT) return __builtin_nontemporal_load((gu32u *)p);
+    else return *(gu32u *)p;
+  }
+  __device__ static Acc flags(uint32_t w) { return nonzero_bytes(w); }
+};
+template <> struct ShPx<8> {
+  typedef unsigned long long Acc;
+  template <bool NT> __device__ static unsigned long long load(const uint8_t *p) {
+    u32x2u v;
+    if constexpr (NT) v = __builtin_nontemporal_load((gu32x2u *)p);
+    else v = *(gu32x2u *)p;
+    return ((unsigned long long)v.y << 32) | v.x;
+  }
+  __device__ static Acc flags(unsigned long long w) {
+    return ((unsigned long long)nonzero_bytes((uint32_t)(w >> 32)) << 32) | nonzero_bytes((uint32_t)w);
+  }
+};
+
+// LDS of k_shared: acc8[S][TPB] accumulator words (PX 8-bit counts per thread
+// and request), bits[count + kShPad] member masks (compacted in place into the
+// masks of the listed members), ids[count + kShPad] listed member ids.
+__host__ __device__ constexpr int64_t sh_bits_words(int64_t count) { return (count + kShPad + 3) / 4 * 4; }
+__host__ __device__ constexpr int64_t sh_ids_halves(int64_t count) { return (count + kShPad + 7) / 8 * 8; }
+
+// The 8-bit counts are flushed into 16-bit counters in registers every
+// kShFlush members.  Requests must not repeat an id (a member's mask holds one
+// bit per request), the pool must hold at most 65536 rasters, and n <= 65535
+// per request keeps the 16-bit counters from overflowing.
+template <bool NT, int TPB, int PX>
+__global__ __launch_bounds__(TPB) void k_shared(const uint8_t *__restrict__ base, int64_t stride,
+                                                int32_t W, int32_t H, int32_t count, int32_t S,
+                                                const char *__restrict__ arena,
+                                                uint32_t *__restrict__ queue) {
+  static_assert(TPB * PX == kShTile, "a tile is kShTile pixels");
+  typedef ShPx<PX> P;
+  typedef typename P::Acc Acc;
+  constexpr int NW = PX / 4;  // dwords per thread
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Acc *acc8 = reinterpret_cast<Acc *>(lds_raw);
+  uint32_t *bits = reinterpret_cast<uint32_t *>(acc8 + (size_t)S * TPB);
+  uint16_t *ids = reinterpret_cast<uint16_t *>(bits + sh_bits_words(count));
+  __shared__ int s_item, s_ns, s_rnext, s_nlist;
+  __shared__ int s_slot[kShMaxSlots];
+  __shared__ int s_off[kShMaxSlots + 1];  // prefix sums of the slots' id counts
+
+  const Header *hd = reinterpret_cast<const Header *>(arena);
+  const int nreq = hd->nreq;
+  const ReqDesc *reqs = reinterpret_cast<const ReqDesc *>(arena + hd->reqs_off);
+  const int32_t *ids_all = reinterpret_cast<const int32_t *>(arena + hd->ids_off);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int segs = (W + kShTile - 1) / kShTile;
+  const int ntiles = H * segs;
+
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int tile = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (tile >= ntiles) break;  // the queue counter only grows: every wave exits
+    const int y = tile / segs;
+    const int xt = (tile - y * segs) * kShTile;
+    const int tw = min(kShTile, W - xt);
+    const int x = xt + PX * tid;
+    const bool live = x < W;
+    // lanes past the row end read the row start instead; their counts are
+    // never written out
+    const uint8_t *px = base + (uint32_t)y * (uint32_t)W + (live ? (uint32_t)x : 0u);
+    int r_next = 0;
+    while (r_next < nreq) {
+      // the next (up to S) requests whose windows cover this tile
+      if (wave == 0) {
+        int ns = 0, r = r_next;
+        while (r < nreq) {
+          bool cov = false;
+          if (r + lane < nreq) {
+            const ReqDesc &R = reqs[r + lane];
+            cov = y >= R.y0 && y < R.y0 + R.h && R.x0 < xt + tw && R.x0 + R.w > xt;
+          }
+          unsigned long long m = __ballot(cov);
+          while (m != 0 && ns < S) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            if (lane == 0) s_slot[ns] = r + l;
+            ++ns;
+          }
+          if (m != 0) {  // slots full with covering requests left in this chunk
+            r += __builtin_ctzll(m);
+            break;
+          }
+          r += 64;
+          if (ns == S) break;
+        }
+        if (lane == 0) {
+          s_ns = ns;
+          s_rnext = min(r, nreq);
+          int o = 0;
+          for (int j = 0; j < ns; ++j) {
+            s_off[j] = o;
+            o += reqs[s_slot[j]].n;
+          }
+          s_off[ns] = o;
+        }
+      }
+      __syncthreads();
+      const int ns = s_ns;
+      r_next = s_rnext;
+      if (ns == 0) break;
+      for (int m = tid; m < count; m += TPB) bits[m] = 0u;
+      for (int j = 0; j < ns; ++j) acc8[j * TPB + tid] = 0;
+      __syncthreads();
+      // mark the members of each slot's request: the (slot, id) pairs are
+      // spread over the threads, four loads in flight per thread
+      {
+        const int total = s_off[ns];
+        int j = 0;
+        for (int p0 = tid; p0 < total; p0 += 4 * TPB) {
+          int id[4], sj[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int p = p0 + u * TPB;
+            while (j + 1 < ns && s_off[j + 1] <= p) ++j;
+            sj[u] = j;
+            id[u] = p < total ? ids_all[reqs[s_slot[j]].ids_off + (p - s_off[j])] : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (id[u] >= 0) atomicOr(&bits[id[u]], 1u << sj[u]);
+        }
+      }
+      __syncthreads();
+      // compact the marked members in id order (wave 0): their ids, and their
+      // masks moved down in place (an entry moves to a position no later than
+      // its own, after the wave has read it); then the zero padding
+      if (wave == 0) {
+        int nl = 0;
+        for (int c0 = 0; c0 < count; c0 += 64) {
+          const uint32_t v = c0 + lane < count ? bits[c0 + lane] : 0u;
+          const unsigned long long m = __ballot(v != 0u);
+          const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (v) {
+            ids[nl + before] = (uint16_t)(c0 + lane);
+            bits[nl + before] = v;
+          }
+          nl += __builtin_popcountll(m);
+        }
+        if (lane < kShPad) {
+          ids[nl + lane] = 0;
+          bits[nl + lane] = 0u;
+        }
+        if (lane == 0) s_nlist = nl;
+      }
+      __syncthreads();
+      const int nl = s_nlist;
+      // Stream the listed members' tiles: groups of kShUnroll (id, mask)
+      // pairs read from LDS at once; the next group's loads are in flight
+      // while this one is added.  Padding entries have id 0 and an empty mask.
+      typedef decltype(P::template load<NT>(px)) Word;
+      Word wa[kShUnroll], wb[kShUnroll];
+      uint32_t ba[kShUnroll], bb[kShUnroll];
+      auto fetch = [&](int i, Word(&w)[kShUnroll], uint32_t(&b)[kShUnroll]) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(ids + i);
+        const uint4 m0 = *reinterpret_cast<const uint4 *>(bits + i);
+        const uint4 m1 = *reinterpret_cast<const uint4 *>(bits + i + 4);
+        const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+        b[0] = m0.x; b[1] = m0.y; b[2] = m0.z; b[3] = m0.w;
+        b[4] = m1.x; b[5] = m1.y; b[6] = m1.z; b[7] = m1.w;
+#pragma unroll
+        for (int u = 0; u < kShUnroll; ++u) {
+          const uint32_t id = (qw[u >> 1] >> (16 * (u & 1))) & 0xffffu;
+          w[u] = P::template load<NT>(px + (int64_t)id * stride);
+        }
+      };
+      auto add = [&](const Word(&w)[kShUnroll], const uint32_t(&b)[kShUnroll]) {
+#pragma unroll
+        for (int u = 0; u < kShUnroll; ++u) {
+          const Acc nz = P::flags(w[u]);
+          uint32_t m = __builtin_amdgcn_readfirstlane(b[u]);
+          while (m) {
+            const int j = __builtin_ctz(m);
+            m &= m - 1;
+            atomicAdd(&acc8[j * TPB + tid], nz);
+          }
+        }
+      };
+      // 16-bit counters: per dword of pixels, lanes of pixels 0,2 and 1,3
+      uint32_t c02[kShMaxSlots][NW], c13[kShMaxSlots][NW];
+#pragma unroll
+      for (int j = 0; j < kShMaxSlots; ++j)
+#pragma unroll
+        for (int k = 0; k < NW; ++k) c02[j][k] = c13[j][k] = 0u;
+      // widen this thread's 8-bit counts (only this thread touches its
+      // accumulator words: no barrier)
+      auto flush = [&]() {
+#pragma unroll
+        for (int j = 0; j < kShMaxSlots; ++j) {
+          if (j < ns) {
+            const Acc v = acc8[j * TPB + tid];
+            acc8[j * TPB + tid] = 0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+              const uint32_t d = (uint32_t)((unsigned long long)v >> (32 * k));
+              c02[j][k] = cmp::padd(c02[j][k], cmp::lanes_lo(d));
+              c13[j][k] = cmp::padd(c13[j][k], cmp::lanes_hi(d));
+            }
+          }
+        }
+      };
+      fetch(0, wa, ba);
+      for (int i = 0, next_flush = kShFlush; i < nl; i += 2 * kShUnroll) {
+        fetch(i + kShUnroll, wb, bb);
+        add(wa, ba);
+        fetch(i + 2 * kShUnroll, wa, ba);
+        add(wb, bb);
+        if (i + 2 * kShUnroll >= next_flush) {
+          flush();
+          next_flush += kShFlush;
+        }
+      }
+      flush();
+      // the covering requests' pixels of this tile
+#pragma unroll
+      for (int j = 0; j < kShMaxSlots; ++j) {
+        if (j >= ns) continue;
+        const ReqDesc &R = reqs[s_slot[j]];
+        if (y < R.y0 || y >= R.y0 + R.h) continue;
+        const int64_t row = (int64_t)(y - R.y0) * R.pitch - R.x0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+          const uint32_t c[4] = {c02[j][k] & 0xffffu, c13[j][k] & 0xffffu, c02[j][k] >> 16,
+                                 c13[j][k] >> 16};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int xk = x + 4 * k + q;
+            if (xk < W && xk >= R.x0 && xk < R.x0 + R.w) R.out[row + xk] = c[q];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <bool NT>
 __global__ __launch_bounds__(256) void k_crop(const uint8_t *__restrict__ base, int64_t stride,
                                               int32_t W, ReqDesc R,
@@ -161,6 +442,35 @@ int ensure_arena(cmp_pool *p, int64_t bytes) {
   return CMP_OK;
 }
 
+// Threads per workgroup and pixels per thread of k_shared (a tile is 1024).
+constexpr int kShTpb = 128, kShPx = 8;
+
+// LDS bytes of k_shared with S slots over a pool of `count` rasters.
+int64_t shared_lds_bytes(int64_t count, int S) {
+  return (int64_t)S * kShTpb * kShPx + sh_bits_words(count) * 4 + sh_ids_halves(count) * 2;
+}
+
+// Slots per pass the shared mode can use on this pool (0: not usable).
+int shared_slots(const cmp_pool *p) {
+  if (p->count > 65536) return 0;
+  const int64_t room = (int64_t)p->max_lds - 512 - shared_lds_bytes(p->count, 0);
+  const int64_t S = std::min<int64_t>(kShMaxSlots, room / (kShTpb * kShPx));
+  return S >= 4 ? (int)S : 0;
+}
+
+hipError_t launch_shared(cmp_pool *p, int grid, bool nt, int S) {
+  hipError_t e = cmp::launch_fill(p->d_queue, 0, 4, p->s);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)shared_lds_bytes(p->count, S);
+  if (nt)
+    k_shared<true, kShTpb, kShPx><<<grid, kShTpb, lds, p->s>>>(
+        p->base, p->stride, p->W, p->H, (int32_t)p->count, S, p->d_arena, p->d_queue);
+  else
+    k_shared<false, kShTpb, kShPx><<<grid, kShTpb, lds, p->s>>>(
+        p->base, p->stride, p->W, p->H, (int32_t)p->count, S, p->d_arena, p->d_queue);
+  return hipGetLastError();
+}
+
 hipError_t launch_persistent(cmp_pool *p, int grid, bool nt) {
   hipError_t e = cmp::launch_fill(p->d_queue, 0, 4, p->s);
   if (e != hipSuccess) return e;
@@ -178,12 +488,16 @@ extern "C" {
 void composite_default_tune(cmp_tune *t) {
   if (!t) return;
   std::memset(t, 0, sizeof(*t));
-  t->mode = CMP_BATCH_PERSISTENT;
+  // measured on 64 requests over a pool of 2048 masks of 2048x2048: shared
+  // mode, 24 requests per pass, 4 workgroups per compute unit; the persistent
+  // fallback's best there is 1024-vector items in row order with cached loads
+  t->mode = CMP_BATCH_SHARED;
   t->tile_vecs = 1024;
-  t->blocks_per_cu = 8;
+  t->blocks_per_cu = 4;
   t->use_graph = 1;
   t->order = CMP_ORDER_ROWS;
   t->stream_loads = 0;
+  t->slots = 24;
 }
 
 int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count, int32_t W,
@@ -212,6 +526,17 @@ int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count
     if (hipSetDevice(device) != hipSuccess) break;
     if (hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
       break;
+    if (hipDeviceGetAttribute(&p->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+      break;
+    if (const int S = shared_slots(p)) {
+      // allow k_shared its dynamic LDS (beyond the default per-launch limit)
+      const int lds = (int)shared_lds_bytes(p->count, S);
+      if (hipFuncSetAttribute((const void *)k_shared<true, kShTpb, kShPx>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+          hipFuncSetAttribute((const void *)k_shared<false, kShTpb, kShPx>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+        p->max_lds = 0;  // shared mode unavailable; batches fall back to persistent
+    }
     if (hipStreamCreateWithFlags(&p->s, hipStreamNonBlocking) != hipSuccess) break;
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) break;
     rc = CMP_ENOMEM;
@@ -247,13 +572,15 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   cmp_tune t;
   composite_default_tune(&t);
   if (tune) t = *tune;
-  if (t.mode != CMP_BATCH_PERSISTENT && t.mode != CMP_BATCH_PER_REQUEST) return CMP_EINVAL;
-  if (t.mode == CMP_BATCH_PERSISTENT &&
+  if (t.mode != CMP_BATCH_PERSISTENT && t.mode != CMP_BATCH_PER_REQUEST && t.mode != CMP_BATCH_SHARED)
+    return CMP_EINVAL;
+  if (t.mode != CMP_BATCH_PER_REQUEST &&
       (t.tile_vecs < 64 || t.tile_vecs > 65536 || t.blocks_per_cu < 1 || t.blocks_per_cu > 16 ||
        (t.use_graph != 0 && t.use_graph != 1) ||
        (t.order != CMP_ORDER_COST && t.order != CMP_ORDER_ROWS)))
     return CMP_EINVAL;
   if (t.stream_loads != 0 && t.stream_loads != 1) return CMP_EINVAL;
+  if (t.slots != 0 && (t.slots < 4 || t.slots > kShMaxSlots)) return CMP_EINVAL;
   for (int r : t.reserved)
     if (r) return CMP_EINVAL;
   // validate every request before anything is enqueued
@@ -272,7 +599,22 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   if (nreq == 0) {
     p->last_ms = 0.0;
     p->last_items = 0;
+    p->last_mode = t.mode;
     return CMP_OK;
+  }
+  // the shared mode needs distinct ids per request and room in LDS; otherwise
+  // the batch runs in the persistent mode with the same parameters
+  int S = 0;
+  if (t.mode == CMP_BATCH_SHARED) {
+    S = shared_slots(p);
+    if (S && t.slots) S = std::min(S, t.slots);
+    std::vector<int32_t> v;
+    for (int32_t r = 0; r < nreq && S; ++r) {
+      v.assign(reqs[r].ids, reqs[r].ids + reqs[r].n);
+      std::sort(v.begin(), v.end());
+      if (std::adjacent_find(v.begin(), v.end()) != v.end()) S = 0;
+    }
+    if (!S) t.mode = CMP_BATCH_PERSISTENT;
   }
   // work items: bands of whole rows of about tile_vecs vectors
   std::vector<ReqDesc> rd(nreq);
@@ -339,16 +681,22 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
     if (reqs[r].n) std::memcpy(ids + rd[r].ids_off, reqs[r].ids, 4 * (size_t)reqs[r].n);
   POOL_TRY(hipMemcpyAsync(p->d_arena, p->h_arena, bytes, hipMemcpyHostToDevice, p->s));
   POOL_TRY(hipEventRecord(p->ev0, p->s));
-  if (t.mode == CMP_BATCH_PERSISTENT) {
+  if (t.mode != CMP_BATCH_PER_REQUEST) {
+    const bool shared = t.mode == CMP_BATCH_SHARED;
     const int grid = p->cus * t.blocks_per_cu;
+    auto launch = [&]() {
+      return shared ? launch_shared(p, grid, t.stream_loads != 0, S)
+                    : launch_persistent(p, grid, t.stream_loads != 0);
+    };
     if (t.use_graph) {
-      const int key = grid * 2 + t.stream_loads;
+      // graphs by mode, grid, load kind and (shared mode) slots per pass
+      const int key = ((grid * 2 + t.stream_loads) * 2 + (shared ? 1 : 0)) * 64 + S;
       auto it = p->graphs.find(key);
       if (it == p->graphs.end()) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         POOL_TRY(hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal));
-        const hipError_t le = launch_persistent(p, grid, t.stream_loads != 0);
+        const hipError_t le = launch();
         const hipError_t ce = hipStreamEndCapture(p->s, &g);
         if (le != hipSuccess || ce != hipSuccess) {
           if (g) hipGraphDestroy(g);
@@ -365,7 +713,7 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
       }
       POOL_TRY(hipGraphLaunch(it->second, p->s));
     } else {
-      POOL_TRY(launch_persistent(p, grid, t.stream_loads != 0));
+      POOL_TRY(launch());
     }
   } else {
     const int32_t *d_ids = reinterpret_cast<const int32_t *>(p->d_arena + hd.ids_off);
@@ -385,14 +733,18 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   float ms = 0.f;
   POOL_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
   p->last_ms = ms;
-  p->last_items = t.mode == CMP_BATCH_PERSISTENT ? (int64_t)items.size() : nreq;
+  p->last_items = t.mode == CMP_BATCH_PERSISTENT ? (int64_t)items.size()
+                  : t.mode == CMP_BATCH_SHARED ? (int64_t)p->H * ((p->W + kShTile - 1) / kShTile)
+                                               : nreq;
+  p->last_mode = t.mode;
   return CMP_OK;
 }
 
-int composite_batch_last(const cmp_pool *p, double *ms, int64_t *items) {
+int composite_batch_last(const cmp_pool *p, double *ms, int64_t *items, int32_t *mode) {
   if (!p || !ms || !items) return CMP_EINVAL;
   *ms = p->last_ms;
   *items = p->last_items;
+  if (mode) *mode = p->last_mode;
   return CMP_OK;
 }
 

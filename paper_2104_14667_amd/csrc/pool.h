@@ -12,6 +12,7 @@ struct cmp_pool {
   int64_t count = 0, stride = 0, bytes = 0;
   int32_t W = 0, H = 0;
   int cus = 0;
+  int max_lds = 0;  // LDS bytes a workgroup may use (0: shared mode unavailable)
   bool poisoned = false;
   hipStream_t s = nullptr;
   char *d_arena = nullptr, *h_arena = nullptr;
@@ -20,5 +21,6 @@ struct cmp_pool {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   int64_t last_items = 0;
-  std::map<int, hipGraphExec_t> graphs;  // by grid size and load kind; they capture d_arena
+  int32_t last_mode = 0;
+  std::map<int, hipGraphExec_t> graphs;  // by mode, grid size, load kind, slots; they capture d_arena
 };

@@ -1,11 +1,14 @@
-"""Autotuner of the batched persistent launch.
+"""Autotuner of the batched launch.
 
-Sweeps the work-item size (16-pixel vectors per item), the persistent
+Persistent mode: sweeps the work-item size (16-pixel vectors per item), the
 occupancy (workgroups per compute unit), the queue order (largest items first,
 or top to bottom through the raster so that requests sharing members hit in
-the caches) and the load hint (non-temporal or cached) on the actual batch,
-timing each candidate with the library's own event timing, and keeps the
-fastest.  Results
+the caches) and the load hint (non-temporal or cached).  Shared mode: sweeps
+the requests per pass over a tile (fewer use less LDS, so more workgroups fit,
+but re-read members where many requests overlap), the occupancy and the load
+hint; it is skipped when the batch does not qualify (a request repeating an
+id).  Each candidate runs on the actual batch, timed with the library's own
+event timing, and the fastest is kept.  Results
 are cached per shape class (arch, raster size, request count, typical window
 side and set size, each bucketed to a power of two) in memory and, when a path
 is given, in a JSON file."""
@@ -18,13 +21,15 @@ import os
 import time
 from typing import Dict, Optional, Sequence
 
-from .composite import (CMP_BATCH_PERSISTENT, CMP_ORDER_COST, CMP_ORDER_ROWS, Pool,
-                        make_tune)
+from .composite import (CMP_BATCH_PERSISTENT, CMP_BATCH_SHARED, CMP_ORDER_COST, CMP_ORDER_ROWS,
+                        Pool, make_tune)
 
 TILE_VECS = (64, 128, 256, 512, 1024, 2048, 4096)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16)
 ORDERS = (CMP_ORDER_COST, CMP_ORDER_ROWS)
 STREAM_LOADS = (0, 1)
+SHARED_SLOTS = (0, 24, 20, 16)
+SHARED_BLOCKS_PER_CU = (2, 3, 4, 6)
 
 _cache: Dict[str, dict] = {}
 
@@ -42,8 +47,9 @@ def shape_key(pool: Pool, requests: Sequence[dict], arch: str = "gfx950") -> str
 
 def autotune(pool: Pool, requests: Sequence[dict], reps: int = 3,
              cache_path: Optional[str] = None, use_graph: int = 1) -> dict:
-    """Returns {'tile_vecs', 'blocks_per_cu', 'order', 'stream_loads', 'ms', 'key',
-    'seconds', 'cached'}."""
+    """Returns {'mode', 'tile_vecs', 'blocks_per_cu', 'order', 'stream_loads',
+    'slots', 'ms', 'by_mode', 'key', 'seconds', 'cached'}: the fastest candidate,
+    and in 'by_mode' the fastest of each mode that ran (keyed by mode number)."""
     key = shape_key(pool, requests)
     if cache_path and os.path.exists(cache_path) and not _cache:
         try:
@@ -54,19 +60,40 @@ def autotune(pool: Pool, requests: Sequence[dict], reps: int = 3,
         return dict(_cache[key], key=key, cached=True, seconds=0.0)
     t0 = time.perf_counter()
     best = None
+    by_mode: Dict[str, dict] = {}
+
+    def trial(mode, tv, bpc, order, sl, slots):
+        nonlocal best
+        tune = make_tune(mode, tv, bpc, use_graph, order, sl, slots)
+        ms = []
+        for _ in range(reps):
+            pool.run(requests, tune)
+            ms.append(pool.last()[0])
+        if pool.last()[2] != mode:
+            return False                      # the batch does not qualify
+        m = min(ms)
+        cand = {"mode": mode, "tile_vecs": tv, "blocks_per_cu": bpc, "order": order,
+                "stream_loads": sl, "slots": slots, "ms": m}
+        if best is None or m < best["ms"]:
+            best = cand
+        if str(mode) not in by_mode or m < by_mode[str(mode)]["ms"]:
+            by_mode[str(mode)] = cand
+        return True
+
     for order in ORDERS:
         for sl in STREAM_LOADS:
             for tv in TILE_VECS:
                 for bpc in BLOCKS_PER_CU:
-                    tune = make_tune(CMP_BATCH_PERSISTENT, tv, bpc, use_graph, order, sl)
-                    ms = []
-                    for _ in range(reps):
-                        pool.run(requests, tune)
-                        ms.append(pool.last()[0])
-                    m = min(ms)
-                    if best is None or m < best["ms"]:
-                        best = {"tile_vecs": tv, "blocks_per_cu": bpc, "order": order,
-                                "stream_loads": sl, "ms": m}
+                    trial(CMP_BATCH_PERSISTENT, tv, bpc, order, sl, 0)
+    # the shared mode's fallback uses the best persistent parameters
+    fb = dict(by_mode[str(CMP_BATCH_PERSISTENT)])
+    shared_ok = True
+    for slots in SHARED_SLOTS:
+        for bpc in SHARED_BLOCKS_PER_CU:
+            for sl in STREAM_LOADS:
+                if shared_ok:
+                    shared_ok = trial(CMP_BATCH_SHARED, fb["tile_vecs"], bpc, fb["order"], sl, slots)
+    best = dict(best, by_mode=by_mode)
     _cache[key] = best
     if cache_path:
         try:

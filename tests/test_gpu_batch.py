@@ -11,8 +11,8 @@ import torch
 import oracle
 from paper_2104_14667_amd import synth
 from paper_2104_14667_amd.composite import (CMP_BATCH_PER_REQUEST, CMP_BATCH_PERSISTENT,
-                                            CMP_EINVAL, CMP_ORDER_COST, CMP_ORDER_ROWS,
-                                            CompositeError, Pool, make_tune)
+                                            CMP_BATCH_SHARED, CMP_EINVAL, CMP_ORDER_COST,
+                                            CMP_ORDER_ROWS, CompositeError, Pool, make_tune)
 from paper_2104_14667_amd.tune import autotune
 
 from gpu_common import say
@@ -123,6 +123,64 @@ def test_invalid_requests_launch_nothing():
         Pool(buf, P, W, H, H * W, P * H * W)          # no slack after the last raster
 
 
+def _set_requests(rng, P, H, W, nreq):
+    """Requests whose ids are distinct (sets), plus the edge cases."""
+    reqs = [dict(ids=[], x0=0, y0=0, w=W, h=H),
+            dict(ids=[P - 1], x0=W - 1, y0=H - 1, w=1, h=1),
+            dict(ids=list(range(P)), x0=0, y0=0, w=W, h=H)]
+    for _ in range(nreq - len(reqs)):
+        w = int(rng.integers(1, W + 1))
+        h = int(rng.integers(1, H + 1))
+        n = int(rng.integers(0, P + 1))
+        reqs.append(dict(ids=rng.choice(P, n, replace=False).tolist(),
+                         x0=int(rng.integers(0, W - w + 1)), y0=int(rng.integers(0, H - h + 1)),
+                         w=w, h=h))
+    return reqs
+
+
+# (P, H, W, requests): one partial tile; several tiles per row with a ragged
+# last one; exactly one tile; more than 64 requests, so more than one pass of
+# 32 per tile and more than one ballot chunk
+@pytest.mark.parametrize("P,H,W,nreq", [(37, 45, 77, 16), (23, 6, 2501, 40), (16, 9, 1024, 24),
+                                        (29, 4, 3000, 150)])
+@pytest.mark.parametrize("graph,nt,bpc", [(1, 0, 2), (0, 1, 1), (1, 1, 4)])
+def test_shared_mode_small(P, H, W, nreq, graph, nt, bpc):
+    rng = np.random.default_rng(P * W + nreq)
+    stack = synth.random_members(P + H, P, H, W)
+    reqs = _set_requests(rng, P, H, W, nreq)
+    exp = oracle.batch(stack, reqs)
+    buf = _pool_tensor(stack)
+    say("shared", P, H, W, nreq, graph, nt, bpc)
+    tune = make_tune(CMP_BATCH_SHARED, 1024, bpc, graph, CMP_ORDER_ROWS, nt)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        for rep in range(2):                          # the second run replays the graph
+            _outs(reqs, pad=3 * rep)
+            pool.run(reqs, tune)
+            ms, items, mode = pool.last()
+            assert mode == CMP_BATCH_SHARED and items == H * ((W + 1023) // 1024)
+            for k, (r, e) in enumerate(zip(reqs, exp)):
+                assert np.array_equal(_got(r), e), f"run {rep}, request {k}"
+
+
+def test_shared_mode_falls_back_on_repeated_ids():
+    stack, reqs = _small_case(11)                     # has a request with ids [5, 5, 5]
+    P, H, W = stack.shape
+    exp = oracle.batch(stack, reqs)
+    buf = _pool_tensor(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        _outs(reqs)
+        pool.run(reqs, make_tune(CMP_BATCH_SHARED, 256, 2, 1))
+        assert pool.last()[2] == CMP_BATCH_PERSISTENT
+        for k, (r, e) in enumerate(zip(reqs, exp)):
+            assert np.array_equal(_got(r), e), f"request {k}"
+        sets = [dict(r, ids=sorted(set(r["ids"]))) for r in reqs]
+        _outs(sets)
+        pool.run(sets, make_tune(CMP_BATCH_SHARED, 256, 2, 1))
+        assert pool.last()[2] == CMP_BATCH_SHARED
+        for k, (r, e) in enumerate(zip(sets, oracle.batch(stack, sets))):
+            assert np.array_equal(_got(r), e), f"set request {k}"
+
+
 def _closed_form_counts(levels_sorted, e_crop):
     # count of levels L > e, for members e < L of one shared elevation field
     return len(levels_sorted) - np.searchsorted(levels_sorted, e_crop, side="right")
@@ -145,11 +203,16 @@ def test_full_batched_pool_2048():
     with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
         best = autotune(pool, reqs[:16], reps=1)
         say("autotuned", best)
-        for tune in (make_tune(CMP_BATCH_PERSISTENT, best["tile_vecs"], best["blocks_per_cu"], 1,
-                               best["order"], best["stream_loads"]),
+        per = best["by_mode"][str(CMP_BATCH_PERSISTENT)]
+        for tune in (make_tune(best["mode"], best["tile_vecs"], best["blocks_per_cu"], 1,
+                               best["order"], best["stream_loads"], best["slots"]),
+                     make_tune(CMP_BATCH_PERSISTENT, per["tile_vecs"], per["blocks_per_cu"], 1,
+                               per["order"], per["stream_loads"]),
+                     make_tune(CMP_BATCH_SHARED, 1024, 2, 1, CMP_ORDER_ROWS, 1, 16),
                      make_tune(CMP_BATCH_PER_REQUEST)):
             _outs(reqs)
             pool.run(reqs, tune)
+            assert pool.last()[2] == tune.mode
             for k, r in enumerate(reqs):
                 got = _got(r)
                 ec = e[r["y0"]:r["y0"] + r["h"], r["x0"]:r["x0"] + r["w"]]
