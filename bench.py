@@ -191,13 +191,14 @@ def run_streamed(torch, ens, e, reps, variants):
     return res
 
 
-def run_batched(torch, reps):
+def run_batched(torch, reps, tuned=True):
     """Batched crop requests: pool of 2048 masks of 2048x2048, 64 requests;
     one autotuned launch (graph replay; shared or persistent mode) against the
     best persistent launch and 64 plain launches."""
     from paper_2104_14667_amd import synth
     from paper_2104_14667_amd.composite import (CMP_BATCH_PER_REQUEST, CMP_BATCH_PERSISTENT,
-                                                CMP_BATCH_SHARED, Pool, make_tune)
+                                                CMP_BATCH_SHARED, Pool, composite_default_tune,
+                                                make_tune)
     MODE_NAMES = {CMP_BATCH_PERSISTENT: "persistent", CMP_BATCH_PER_REQUEST: "per_request",
                   CMP_BATCH_SHARED: "shared"}
     from paper_2104_14667_amd.tune import autotune
@@ -209,6 +210,8 @@ def run_batched(torch, reps):
     buf = torch.empty(wl.pool * plane + 64, dtype=torch.uint8, device="cuda:0")
     for i, L in enumerate(lv):
         synth.member_torch(et, int(L), "mask", out=buf[i * plane:(i + 1) * plane].view(wl.H, wl.W))
+        if i % 256 == 255:
+            log(f"  pool {i + 1}/{wl.pool}")
     reqs = wl.requests()
     for r in reqs:
         r["out"] = torch.empty((r["h"], r["w"]), dtype=torch.int32, device="cuda:0")
@@ -218,9 +221,17 @@ def run_batched(torch, reps):
                        "square crops of side [512,2048] -> u32 count",
            "px_members": pxm}
     with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
-        best = autotune(pool, reqs, reps=2)
         keys = ("mode", "tile_vecs", "blocks_per_cu", "order", "stream_loads", "slots")
-        out["autotune"] = {k: best[k] for k in keys + ("seconds",)}
+        if tuned:
+            log("  autotune")
+            best = autotune(pool, reqs, reps=2)
+            out["autotune"] = {k: best[k] for k in keys + ("seconds",)}
+        else:
+            # the library's default tune, and its persistent fallback's parameters
+            d = composite_default_tune()
+            best = {k: getattr(d, k) for k in keys}
+            best["by_mode"] = {str(CMP_BATCH_PERSISTENT): dict(best, mode=CMP_BATCH_PERSISTENT)}
+            out["autotune"] = "skipped: default tune"
 
         def tune_of(c, graph=1):
             return make_tune(c["mode"], c["tile_vecs"], c["blocks_per_cu"], graph, c["order"],
@@ -234,6 +245,7 @@ def run_batched(torch, reps):
         }
         out["persistent_tune"] = {k: persistent[k] for k in keys}
         for name, tune in variants.items():
+            log(f"  {name}")
             dev_ms, wall_ms = [], []
             for _ in range(reps + 1):
                 t0 = time.perf_counter()
@@ -284,6 +296,8 @@ def run_served(torch, duration_s, spill_duration_s):
     buf = torch.empty(wl.pool * plane + 64, dtype=torch.uint8, device="cuda:0")
     for i, L in enumerate(lv):
         synth.member_torch(et, int(L), "depth", out=buf[i * plane:(i + 1) * plane].view(wl.H, wl.W))
+        if i % 256 == 255:
+            log(f"  pool {i + 1}/{wl.pool}")
     torch.cuda.synchronize()
     n = int(wl.rate * duration_s)
     sched = wl.schedule(n)
@@ -294,6 +308,7 @@ def run_served(torch, duration_s, spill_duration_s):
 
     def one(name, sched, held=None, **opts):
         """Replays sched; held: per-session member lists loaded untimed first."""
+        log(f"  {name}")
         with Server(pool, **opts) as srv:
             sids = [srv.open() for _ in range(wl.sessions)]
             if held:
@@ -468,6 +483,8 @@ def main():
     ap.add_argument("--stream-reps", type=int, default=3)
     ap.add_argument("--no-streamed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: run the library's default tune instead of autotuning")
     ap.add_argument("--served-seconds", type=float, default=20.0,
                     help="length of the open-loop served schedule (0 skips it)")
     ap.add_argument("--spill-seconds", type=float, default=2.0,
@@ -552,7 +569,7 @@ def main():
                 "dual_buffer_linear": dict(nbuf=2, chunk_depth=8)})}
     if not args.no_batched:
         log("batched", synth.BATCHED.name)
-        out["batched"] = run_batched(torch, args.stream_reps + 2)
+        out["batched"] = run_batched(torch, args.stream_reps + 2, not args.no_autotune)
     if args.served_seconds > 0:
         log("served", synth.SERVED.name)
         out["served"] = run_served(torch, args.served_seconds, args.spill_seconds)
