@@ -121,9 +121,37 @@ def run_resident(torch, ens, e, steps, warmup):
         t1 = time.perf_counter()
         launches, kms = c.kernel_stats(reset=True)
         exact = verify(c, ens, e, steps + warmup)
+    ceiling = same_traffic_ceiling(torch, dev)
     del dev, ptrs
     torch.cuda.empty_cache()
-    return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact)
+    return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact, ceiling=ceiling)
+
+
+def same_traffic_ceiling(torch, dev):
+    """Best time of the same-traffic reference kernel (libceiling.so) on the
+    resident members: read + composite read-modify-write, and read only."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2104_14667_amd", "libceiling.so"))
+    lib.traffic_ceiling.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.POINTER(C.c_float)]
+    n, H, W = dev.shape
+    npix = H * W
+    cnt = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
+    sm = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
+    mx = torch.zeros(npix, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    out = {}
+    for rmw, name in ((1, "rmw_ms"), (0, "read_only_ms")):
+        ms = C.c_float()
+        rc = lib.traffic_ceiling(dev.data_ptr(), npix, n, npix, cnt.data_ptr(), sm.data_ptr(),
+                                 mx.data_ptr(), rmw, 6, torch.cuda.current_stream().cuda_stream,
+                                 C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"traffic_ceiling failed: hip error {rc}")
+        out[name] = ms.value
+    del cnt, sm, mx
+    return out
 
 
 def h2d_copy_rate(torch, host, chunk, reps):
@@ -548,7 +576,17 @@ def main():
                                      "calibrated on a 1 GiB copy)",
                      "kernel": "k_composite<count|sum|max> (linear)",
                      "kernel_avg_ms": round(kavg_s * 1e3, 4),
-                     "algorithmic_bytes_per_launch": algo_bytes},
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     # what the memory system sustains for the same loads and
+                     # stores with trivial arithmetic (libceiling.so), and for
+                     # the member reads alone
+                     "attainable": {
+                         "kernel": "same-traffic reference: 128 NT 16-byte member streams + 9 B/px "
+                                   "composite read-modify-write, trivial arithmetic",
+                         "GBps": round(algo_bytes / (r["ceiling"]["rmw_ms"] * 1e-3) / 1e9, 1),
+                         "frac": round(r["ceiling"]["rmw_ms"] * 1e-3 / kavg_s, 4),
+                         "read_only_GBps": round(px / (r["ceiling"]["read_only_ms"] * 1e-3)
+                                                 / 1e9, 1)}},
     }
     if not args.no_streamed:
         log("streamed", synth.STREAMED.name)

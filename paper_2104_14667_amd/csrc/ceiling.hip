@@ -1,0 +1,112 @@
+// Same-traffic reference kernel for the roofline of the resident compositing
+// kernel (measurement only; built as its own library, libceiling.so, and
+// loaded by the benchmark, never by the compositing library).
+//
+// It issues the loads and stores of the compositing kernel's linear path with
+// trivial arithmetic in place of the compositing: n member streams read with
+// non-temporal 16-byte loads, 16 pixels per thread, then (rmw = 1) 9 bytes per
+// pixel of composite read and written (uint32 count, uint32 sum, uint8 max),
+// or nothing (rmw = 0, the read-only rate).  Its rate is what the memory
+// system sustains for that access pattern, the attainable bound for the
+// compositing kernel on the same data.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 gu32x4;
+
+template <bool RMW>
+__global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem, int64_t stride, int n,
+                                                 uint32_t *__restrict__ cnt, uint32_t *__restrict__ sum,
+                                                 uint8_t *__restrict__ mx, uint32_t nvec, uint32_t never) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= nvec) return;
+  uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    u32x4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load((gu32x4 *)(mem + (i + u) * stride + t * 16u));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a0 += v[u].x;
+      a1 += v[u].y;
+      a2 += v[u].z;
+      a3 ^= v[u].w;
+    }
+  }
+  for (; i < n; ++i) {
+    const u32x4 v = __builtin_nontemporal_load((gu32x4 *)(mem + i * stride + t * 16u));
+    a0 += v.x;
+    a1 += v.y;
+    a2 += v.z;
+    a3 ^= v.w;
+  }
+  uint4 *c = reinterpret_cast<uint4 *>(cnt + t * 16u);
+  uint4 *s = reinterpret_cast<uint4 *>(sum + t * 16u);
+  uint4 *x = reinterpret_cast<uint4 *>(mx + t * 16u);
+  if (RMW) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 o = c[q], p = s[q];
+      c[q] = make_uint4(o.x + a0, o.y + a1, o.z + a2, o.w + a3);
+      s[q] = make_uint4(p.x ^ a0, p.y ^ a1, p.z ^ a2, p.w ^ a3);
+    }
+    const uint4 o = x[0];
+    x[0] = make_uint4(o.x | a0, o.y | a1, o.z | a2, o.w | a3);
+  } else if (a0 == never && a1 == never && a2 == never && a3 == never) {
+    c[0] = make_uint4(a0, a1, a2, a3);  // keeps the loads live; not taken
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Runs the kernel reps times on `stream` (a hipStream_t, or NULL) over n
+// rasters at members + i * stride (npix bytes each, npix a multiple of 16,
+// 16-byte aligned) and composite buffers count, sum (npix uint32 each) and
+// max (npix bytes), and returns in *best_ms the fastest of the runs after the
+// first.  Returns 0 or a hipError_t.  The composite buffers are overwritten.
+int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t npix, void *count,
+                    void *sum, void *max, int32_t rmw, int32_t reps, void *stream, float *best_ms) {
+  if (!members || !count || !sum || !max || !best_ms || n < 1 || reps < 2 || npix < 16 ||
+      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix)
+    return (int)hipErrorInvalidValue;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t nvec = (uint32_t)(npix / 16);
+  const unsigned grid = (nvec + 255) / 256;
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return (int)e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    hipEventDestroy(e0);
+    return (int)e;
+  }
+  float best = 0.f;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, s);
+    if (e != hipSuccess) break;
+    if (rmw)
+      k_ceiling<true><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
+                                           (uint8_t *)max, nvec, 0x9e3779b9u);
+    else
+      k_ceiling<false><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
+                                            (uint8_t *)max, nvec, 0x9e3779b9u);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && r > 0 && (r == 1 || ms < best)) best = ms;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *best_ms = best;
+  return (int)e;
+}
+
+}  // extern "C"
