@@ -608,11 +608,19 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   if (t.mode == CMP_BATCH_SHARED) {
     S = shared_slots(p);
     if (S && t.slots) S = std::min(S, t.slots);
-    std::vector<int32_t> v;
+    // repeated ids: one bit per pool raster, set and cleared per request
+    std::vector<uint64_t> seen(S ? (size_t)(p->count + 63) / 64 : 0, 0);
     for (int32_t r = 0; r < nreq && S; ++r) {
-      v.assign(reqs[r].ids, reqs[r].ids + reqs[r].n);
-      std::sort(v.begin(), v.end());
-      if (std::adjacent_find(v.begin(), v.end()) != v.end()) S = 0;
+      const cmp_request &q = reqs[r];
+      int32_t i = 0;
+      for (; i < q.n; ++i) {
+        uint64_t &w = seen[q.ids[i] >> 6];
+        const uint64_t b = uint64_t(1) << (q.ids[i] & 63);
+        if (w & b) break;
+        w |= b;
+      }
+      if (i < q.n) S = 0;
+      for (int32_t k = 0; k < i; ++k) seen[q.ids[k] >> 6] = 0;
     }
     if (!S) t.mode = CMP_BATCH_PERSISTENT;
   }

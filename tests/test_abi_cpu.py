@@ -115,3 +115,22 @@ def test_server_opts_and_stats_layout():
     assert cb.lib.composite_server_create(None, None, None) == cb.CMP_EINVAL
     h = C.c_void_p()
     assert cb.lib.composite_server_create(C.byref(h), None, C.byref(o)) == cb.CMP_EINVAL
+
+
+def test_ceiling_library_checks_arguments():
+    """The benchmark's same-traffic reference kernel (libceiling.so) rejects
+    bad arguments before any device call."""
+    import os
+    lib = C.CDLL(os.path.join(os.path.dirname(cb.LIB_PATH), "libceiling.so"))
+    f = lib.traffic_ceiling
+    f.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                  C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_float)]
+    ms = C.c_float()
+    ok = dict(members=16, stride=64, n=2, npix=64, count=16, sum=16, max=16, rmw=1, reps=3)
+    bads = [dict(members=None), dict(n=0), dict(npix=40), dict(stride=32), dict(reps=1),
+            dict(count=None), dict(npix=1 << 33, stride=1 << 33)]
+    for bad in bads:
+        a = dict(ok, **bad)
+        rc = f(a["members"], a["stride"], a["n"], a["npix"], a["count"], a["sum"], a["max"],
+               a["rmw"], a["reps"], None, C.byref(ms))
+        assert rc == 1, bad                                  # hipErrorInvalidValue
