@@ -68,6 +68,11 @@ enum cmp_dst_kind { CMP_DST_HOST = 0, CMP_DST_DEVICE = 1, CMP_DST_PINNED = 2 };
  * paper's buffer-to-image transform and image reads, Section 4, third
  * implementation method).  Results are identical. */
 enum cmp_layout { CMP_LINEAR = 0, CMP_TILED = 1 };
+/* In a CMP_TILED context, rasters given in device memory (composite_add_device,
+ * composite_remove with maps_on_device) are already in the tiled layout, as
+ * composite_repack_tiled writes them (composite_tiled_bytes bytes each): the
+ * counterpart of the paper's images kept on the device.  Host rasters are
+ * always row-major and are repacked on the device after upload. */
 
 typedef struct cmp_opts {
   int32_t nbuf;           /* staging slots for composite_add: 1 or 2.  1 is the
@@ -118,8 +123,17 @@ typedef struct cmp_opts {
                              x ^= x >> 16).  Costs one more device read of
                              every added raster, makes add and remove wait for
                              their kernels, and a remove of host rasters
-                             uploads them twice.  Default 0 */
-  int32_t reserved[2];    /* must be zero */
+                             uploads them twice.  In a CMP_TILED context the
+                             fingerprint is taken over the tiled layout's bytes.
+                             Default 0 */
+  int32_t pingpong;       /* 1: two accumulators per output, used in turn: each
+                             compositing launch reads the current one and writes
+                             the other (the paper's image kernels and its
+                             buffer-kernel 2, Section 5.3); 0: one accumulator
+                             updated in place (its buffer-kernel 1).  Results
+                             are identical; pingpong doubles the composite's
+                             device memory.  Default 0 */
+  int32_t reserved[1];    /* must be zero */
 } cmp_opts;
 
 typedef struct cmp_ctx cmp_ctx;
@@ -156,7 +170,7 @@ int composite_add(cmp_ctx *ctx, const uint8_t *const *host_maps,
 
 /* Composites n members that are already in device memory (one kernel pass over
  * all of them, no staging).  dev_maps[i]: device pointers to W*H bytes, any
- * alignment.  The rasters must stay valid until composite_sync returns, and,
+ * alignment (in a CMP_TILED context: to the tiled layout, see cmp_layout).  The rasters must stay valid until composite_sync returns, and,
  * with retain_members, for as long as they are members.  Returns without
  * waiting for the device. */
 int composite_add_device(cmp_ctx *ctx, const uint8_t *const *dev_maps,

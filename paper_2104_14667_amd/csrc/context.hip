@@ -52,10 +52,14 @@ struct cmp_ctx {
   hipStream_t copy_s = nullptr, comp_s = nullptr;
   bool own_copy = false, own_comp = false;
 
-  cmp::Outputs out;
   void *d_count = nullptr;
   uint32_t *d_sum = nullptr;
   uint8_t *d_max = nullptr;
+  // With pingpong: the other accumulator of each output; a pass reads the
+  // current one (above), writes this one, and the two are swapped.
+  void *d_count_alt = nullptr;
+  uint32_t *d_sum_alt = nullptr;
+  uint8_t *d_max_alt = nullptr;
 
   // Staging ring (allocated on the first streamed call).
   int64_t stage_stride = 0;          // bytes between members in a slot
@@ -141,6 +145,9 @@ void free_all(cmp_ctx *ctx) {
   hipFree(ctx->d_count);
   hipFree(ctx->d_sum);
   hipFree(ctx->d_max);
+  hipFree(ctx->d_count_alt);
+  hipFree(ctx->d_sum_alt);
+  hipFree(ctx->d_max_alt);
   for (int i = 0; i < 2; ++i) {
     hipFree(ctx->d_stage[i]);
     hipFree(ctx->d_tiled[i]);
@@ -207,19 +214,50 @@ hipError_t harvest_timing(cmp_ctx *ctx) {
   return hipSuccess;
 }
 
+// One compositing launch over n members (device table d_tab; tiled: the
+// members are in the tiled layout).  In place, or with pingpong from the
+// current accumulators into the other ones, which then become current.
 hipError_t composite_pass(cmp_ctx *ctx, const uint8_t *const *d_tab, int n, bool sub,
                           uint32_t outs, bool tiled) {
+  if (sub) outs &= ~(uint32_t)CMP_MAX;  // max has no inverse: never subtracted
+  cmp::Outputs o;
+  o.count16 = ctx->count_bits == 16;
+  const bool pp = ctx->o.pingpong != 0;
+  if (outs & CMP_COUNT) {
+    o.count = pp ? ctx->d_count_alt : ctx->d_count;
+    if (pp) o.count_in = ctx->d_count;
+  }
+  if (outs & CMP_SUM) {
+    o.sum = pp ? ctx->d_sum_alt : ctx->d_sum;
+    if (pp) o.sum_in = ctx->d_sum;
+  }
+  if (outs & CMP_MAX) {
+    o.max = pp ? ctx->d_max_alt : ctx->d_max;
+    if (pp) o.max_in = ctx->d_max;
+  }
   Timed *t = nullptr;
   hipError_t e = timed_begin(ctx, &t);
   if (e != hipSuccess) return e;
   if (tiled) {
     cmp::Tiling tl{ctx->W, ctx->H, ctx->o.tile_w, ctx->o.tile_h};
-    e = cmp::launch_composite_tiled(d_tab, n, tl, ctx->out, outs, sub, ctx->comp_s);
+    e = cmp::launch_composite_tiled(d_tab, n, tl, o, outs, sub, ctx->comp_s);
   } else {
-    e = cmp::launch_composite_linear(d_tab, n, ctx->npix, ctx->out, outs, sub, ctx->comp_s);
+    e = cmp::launch_composite_linear(d_tab, n, ctx->npix, o, outs, sub, ctx->comp_s);
   }
   if (e != hipSuccess) return e;
+  if (pp) {
+    if (outs & CMP_COUNT) std::swap(ctx->d_count, ctx->d_count_alt);
+    if (outs & CMP_SUM) std::swap(ctx->d_sum, ctx->d_sum_alt);
+    if (outs & CMP_MAX) std::swap(ctx->d_max, ctx->d_max_alt);
+  }
   return timed_end(ctx, t);
+}
+
+// Bytes of one member raster as the device kernels read it: W*H, or the
+// padded tiled plane in a CMP_TILED context (device rasters are tiled there).
+int64_t member_bytes(const cmp_ctx *ctx) {
+  if (ctx->o.layout != CMP_TILED) return ctx->npix;
+  return cmp::Tiling{ctx->W, ctx->H, ctx->o.tile_w, ctx->o.tile_h}.plane();
 }
 
 void drop_staging(cmp_ctx *ctx) {
@@ -365,10 +403,18 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
     }
     CMP_TRY(hipEventRecord(ctx->ev_copied[slot], ctx->copy_s));
     CMP_TRY(hipStreamWaitEvent(ctx->comp_s, ctx->ev_copied[slot], 0));
-    if (fp)
+    if (fp && !tiled)
       CMP_TRY(cmp::launch_fingerprint(nullptr, ctx->d_stage[slot], ctx->stage_stride, cnt, plane,
                                       fp + k0, ctx->comp_s));
-    if (outs == 0) {
+    if (tiled && outs == 0) {
+      // fingerprints only: of the tiled copy, as for device rasters here
+      cmp::Tiling tl{ctx->W, ctx->H, ctx->o.tile_w, ctx->o.tile_h};
+      CMP_TRY(cmp::launch_repack_tiled(ctx->d_stage[slot], ctx->stage_stride, ctx->d_tiled[slot],
+                                       ctx->tiled_stride, cnt, tl, ctx->comp_s));
+      CMP_TRY(hipEventRecord(ctx->ev_free[slot], ctx->comp_s));
+      CMP_TRY(cmp::launch_fingerprint(nullptr, ctx->d_tiled[slot], ctx->tiled_stride, cnt,
+                                      tl.plane(), fp + k0, ctx->comp_s));
+    } else if (outs == 0) {
       CMP_TRY(hipEventRecord(ctx->ev_free[slot], ctx->comp_s));
     } else if (tiled) {
       // The receiving buffer is free again once it is repacked (the paper's
@@ -383,6 +429,9 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
       if (ctx->o.debug_poison)
         CMP_TRY(cmp::launch_fill(ctx->d_stage[slot], 0xA5, ctx->stage_stride * d, ctx->comp_s));
       CMP_TRY(hipEventRecord(ctx->ev_free[slot], ctx->comp_s));
+      if (fp)  // of the tiled copy, as for device rasters in a tiled context
+        CMP_TRY(cmp::launch_fingerprint(nullptr, ctx->d_tiled[slot], ctx->tiled_stride, cnt,
+                                        tl.plane(), fp + k0, ctx->comp_s));
       CMP_TRY(composite_pass(ctx, ctx->d_slot_tab[slot], cnt, sub, outs, true));
     } else {
       CMP_TRY(composite_pass(ctx, ctx->d_slot_tab[slot], cnt, sub, outs, false));
@@ -433,7 +482,8 @@ int fingerprints(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool on_de
     const uint8_t **d_tab = nullptr;
     rc = upload_table(ctx, maps, n, &d_tab);
     if (rc != CMP_OK) return rc;
-    if (cmp::launch_fingerprint(d_tab, nullptr, 0, n, ctx->npix, ctx->d_fp, ctx->comp_s) != hipSuccess)
+    if (cmp::launch_fingerprint(d_tab, nullptr, 0, n, member_bytes(ctx), ctx->d_fp, ctx->comp_s) !=
+        hipSuccess)
       return CMP_EDEVICE;
   } else {
     rc = stream_members(ctx, maps, n, false, 0, ctx->d_fp);
@@ -484,6 +534,7 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
   if (o.host_paced != 0 && o.host_paced != 1) return CMP_EINVAL;
   if (o.pageable_host != 0 && o.pageable_host != 1) return CMP_EINVAL;
   if (o.verify_members != 0 && o.verify_members != 1) return CMP_EINVAL;
+  if (o.pingpong != 0 && o.pingpong != 1) return CMP_EINVAL;
   if (o.layout == CMP_TILED) {
     if (o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64 && o.tile_w != 128) return CMP_EINVAL;
     if (o.tile_h < 1 || o.tile_h > 256) return CMP_EINVAL;
@@ -535,19 +586,19 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
     }
     if (!ok || hipEventCreateWithFlags(&ctx->ev_host_done, hipEventDisableTiming) != hipSuccess) break;
     rc = CMP_ENOMEM;
+    const bool pp = o.pingpong != 0;
     if (outputs & CMP_COUNT) {
       if (hipMalloc(&ctx->d_count, ctx->npix * (ctx->count_bits / 8) + 64) != hipSuccess) break;
+      if (pp && hipMalloc(&ctx->d_count_alt, ctx->npix * (ctx->count_bits / 8) + 64) != hipSuccess) break;
     }
     if (outputs & CMP_SUM) {
       if (hipMalloc((void **)&ctx->d_sum, ctx->npix * 4 + 64) != hipSuccess) break;
+      if (pp && hipMalloc((void **)&ctx->d_sum_alt, ctx->npix * 4 + 64) != hipSuccess) break;
     }
     if (outputs & CMP_MAX) {
       if (hipMalloc((void **)&ctx->d_max, ctx->npix + 64) != hipSuccess) break;
+      if (pp && hipMalloc((void **)&ctx->d_max_alt, ctx->npix + 64) != hipSuccess) break;
     }
-    ctx->out.count = ctx->d_count;
-    ctx->out.sum = ctx->d_sum;
-    ctx->out.max = ctx->d_max;
-    ctx->out.count16 = ctx->count_bits == 16;
     rc = CMP_EDEVICE;
     if (clear_outputs(ctx) != hipSuccess) break;
     if (hipStreamSynchronize(ctx->comp_s) != hipSuccess) break;
@@ -623,11 +674,11 @@ int composite_add_device(cmp_ctx *ctx, const uint8_t *const *dev_maps, const int
     ctx->poisoned = true;
     return rc;
   }
-  CMP_TRY(composite_pass(ctx, d_tab, n, false, ctx->outs, false));
+  CMP_TRY(composite_pass(ctx, d_tab, n, false, ctx->outs, ctx->o.layout == CMP_TILED));
   std::vector<uint64_t> fp;
   if (ctx->o.verify_members) {
     rc = begin_fingerprints(ctx, n);
-    if (rc == CMP_OK && cmp::launch_fingerprint(d_tab, nullptr, 0, n, ctx->npix, ctx->d_fp,
+    if (rc == CMP_OK && cmp::launch_fingerprint(d_tab, nullptr, 0, n, member_bytes(ctx), ctx->d_fp,
                                                 ctx->comp_s) != hipSuccess)
       rc = CMP_EDEVICE;
     if (rc == CMP_OK) rc = end_fingerprints(ctx, n, &fp);
@@ -724,7 +775,8 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *id
     if (maps_on_device) {
       const uint8_t **d_tab = nullptr;
       rc = upload_table(ctx, rm.data(), n, &d_tab);
-      if (rc == CMP_OK && composite_pass(ctx, d_tab, n, true, sub_outs, false) != hipSuccess)
+      if (rc == CMP_OK &&
+          composite_pass(ctx, d_tab, n, true, sub_outs, ctx->o.layout == CMP_TILED) != hipSuccess)
         rc = CMP_EDEVICE;
     } else {
       rc = ensure_staging(ctx);
@@ -747,7 +799,7 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *id
         ctx->poisoned = true;
         return rc;
       }
-      CMP_TRY(composite_pass(ctx, d_tab, cnt, false, CMP_MAX, false));
+      CMP_TRY(composite_pass(ctx, d_tab, cnt, false, CMP_MAX, ctx->o.layout == CMP_TILED));
     }
   }
   for (auto it = held.begin(); it != held.end();) {

@@ -12,11 +12,18 @@ constexpr int kGroup = 256;
 
 enum : uint32_t { kCount = 1, kSum = 2, kMax = 4 };
 
+// Where a launch writes the composite and, when the *_in pointers are set,
+// where it reads the previous values from (two accumulators used in turn);
+// otherwise the update is in place.  A launch that writes an output reads it
+// from its *_in pointer if any *_in pointer is set.
 struct Outputs {
   void *count = nullptr;     // uint16_t* or uint32_t*
   uint32_t *sum = nullptr;
   uint8_t *max = nullptr;
   bool count16 = false;
+  const void *count_in = nullptr;
+  const uint32_t *sum_in = nullptr;
+  const uint8_t *max_in = nullptr;
 };
 
 // Geometry of the tiled staging layout: tiles of tw bytes x th rows, stored

@@ -10,9 +10,12 @@
 // outputs, about half of what the VALU can issue per dword at HBM rate, so
 // the kernel stays bound by memory.  After a group of at most 256 members the
 // lanes are widened to 32 bits, and at the end the composite is updated in
-// place once (read-modify-write), not ping-ponged: HIP buffers may be read and
-// written by one kernel, which is what forced the paper's image kernels to use
-// two accumulators.  No matrix cores: nothing here is a contraction.
+// place once (read-modify-write): HIP buffers may be read and written by one
+// kernel, while the paper's image kernels needed two accumulators used in turn
+// (image objects are read-only or write-only inside a kernel, Section 5.3).
+// That ping-pong form is kept as an option (PP: read one accumulator, write the
+// other) to measure the paper's kernel variants.  No matrix cores: nothing here
+// is a contraction.
 
 #include "lanes.h"
 
@@ -125,12 +128,15 @@ struct TiledMap {
   }
 };
 
-template <uint32_t OUTS, bool SUB, bool C16, bool MULTI, class Map>
+template <uint32_t OUTS, bool SUB, bool C16, bool MULTI, class Map, bool PP>
 __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restrict__ tab,
                                                    int n, uint32_t nvec, Map map,
                                                    void *__restrict__ count,
                                                    uint32_t *__restrict__ sum,
-                                                   uint8_t *__restrict__ mx) {
+                                                   uint8_t *__restrict__ mx,
+                                                   const void *__restrict__ count_in,
+                                                   const uint32_t *__restrict__ sum_in,
+                                                   const uint8_t *__restrict__ mx_in) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvec) return;
   uint32_t p;
@@ -156,7 +162,8 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 #pragma unroll
       for (int k = 0; k < 8; ++k) a.c[k] = a.s[k] = 0u;
     }
-    load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
+    if constexpr (PP) load_old<OUTS, SUB, C16>(old, p, count_in, sum_in, mx_in);
+    else load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
   } else {
     // The old composite is requested before the last members are read, so
     // its latency overlaps them instead of trailing the wave (+1-2%).
@@ -168,7 +175,8 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) a.fold(x[u]);
     }
-    load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
+    if constexpr (PP) load_old<OUTS, SUB, C16>(old, p, count_in, sum_in, mx_in);
+    else load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
     {  // the last 1..UNROLL members (n >= 1)
       uint4 x[UNROLL];
 #pragma unroll
@@ -192,12 +200,15 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 }
 
 // Pixels [p0, npix) that do not fill a 16-pixel vector: one thread per pixel.
-template <uint32_t OUTS, bool SUB, bool C16>
+template <uint32_t OUTS, bool SUB, bool C16, bool PP>
 __global__ __launch_bounds__(64) void k_composite_tail(const uint8_t *const *__restrict__ tab,
                                                        int n, int64_t p0, int64_t npix,
                                                        void *__restrict__ count,
                                                        uint32_t *__restrict__ sum,
-                                                       uint8_t *__restrict__ mx) {
+                                                       uint8_t *__restrict__ mx,
+                                                       const void *__restrict__ count_in,
+                                                       const uint32_t *__restrict__ sum_in,
+                                                       const uint8_t *__restrict__ mx_in) {
   const int64_t p = p0 + threadIdx.x;
   if (p >= npix) return;
   uint32_t c = 0, s = 0, m = 0;
@@ -209,15 +220,21 @@ __global__ __launch_bounds__(64) void k_composite_tail(const uint8_t *const *__r
   }
   if constexpr (OUTS & kCount) {
     if constexpr (C16) {
-      uint16_t *d = static_cast<uint16_t *>(count) + p;
-      *d = (uint16_t)(SUB ? *d - c : *d + c);
+      const uint16_t o = static_cast<const uint16_t *>(PP ? count_in : count)[p];
+      static_cast<uint16_t *>(count)[p] = (uint16_t)(SUB ? o - c : o + c);
     } else {
-      uint32_t *d = static_cast<uint32_t *>(count) + p;
-      *d = SUB ? *d - c : *d + c;
+      const uint32_t o = static_cast<const uint32_t *>(PP ? count_in : count)[p];
+      static_cast<uint32_t *>(count)[p] = SUB ? o - c : o + c;
     }
   }
-  if constexpr (OUTS & kSum) sum[p] = SUB ? sum[p] - s : sum[p] + s;
-  if constexpr ((OUTS & kMax) && !SUB) mx[p] = (uint8_t)(m > mx[p] ? m : mx[p]);
+  if constexpr (OUTS & kSum) {
+    const uint32_t o = (PP ? sum_in : sum)[p];
+    sum[p] = SUB ? o - s : o + s;
+  }
+  if constexpr ((OUTS & kMax) && !SUB) {
+    const uint32_t o = (PP ? mx_in : mx)[p];
+    mx[p] = (uint8_t)(m > o ? m : o);
+  }
 }
 
 template <uint32_t OUTS, bool SUB, bool C16, class Map>
@@ -226,10 +243,18 @@ hipError_t go(const uint8_t *const *tab, int n, int64_t nvec, const Map &map,
   if (nvec <= 0) return hipSuccess;
   if (nvec >= (int64_t(1) << 28)) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((nvec + 255) / 256);
-  if (n > kGroup)
-    k_composite<OUTS, SUB, C16, true, Map><<<blocks, 256, 0, s>>>(tab, n, (uint32_t)nvec, map, o.count, o.sum, o.max);
-  else
-    k_composite<OUTS, SUB, C16, false, Map><<<blocks, 256, 0, s>>>(tab, n, (uint32_t)nvec, map, o.count, o.sum, o.max);
+  const bool pp = o.count_in || o.sum_in || o.max_in;
+#define CMP_GO(MULTI, PP)                                                                        \
+  k_composite<OUTS, SUB, C16, MULTI, Map, PP><<<blocks, 256, 0, s>>>(                            \
+      tab, n, (uint32_t)nvec, map, o.count, o.sum, o.max, o.count_in, o.sum_in, o.max_in)
+  if (n > kGroup) {
+    if (pp) CMP_GO(true, true);
+    else CMP_GO(true, false);
+  } else {
+    if (pp) CMP_GO(false, true);
+    else CMP_GO(false, false);
+  }
+#undef CMP_GO
   return hipGetLastError();
 }
 
@@ -237,7 +262,12 @@ template <uint32_t OUTS, bool SUB, bool C16>
 hipError_t go_tail(const uint8_t *const *tab, int n, int64_t p0, int64_t npix,
                    const Outputs &o, hipStream_t s) {
   if (npix <= p0) return hipSuccess;
-  k_composite_tail<OUTS, SUB, C16><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum, o.max);
+  if (o.count_in || o.sum_in || o.max_in)
+    k_composite_tail<OUTS, SUB, C16, true><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum, o.max,
+                                                            o.count_in, o.sum_in, o.max_in);
+  else
+    k_composite_tail<OUTS, SUB, C16, false><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum, o.max,
+                                                             o.count_in, o.sum_in, o.max_in);
   return hipGetLastError();
 }
 

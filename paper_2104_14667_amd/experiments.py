@@ -16,8 +16,21 @@
   into a pinned bounce buffer first, as the runtime did behind the paper's
   clWriteImage), and this library's default (linear layout, 8 rasters per
   slot).
+* ``kernel-table``: the kernel-runtime comparison of Section 5.3 (its table of
+  four kernels): one ~4k raster per launch, 10,000 launches each, timed with
+  HIP events around every launch.  Image kernels read images and accumulate
+  into two images used in turn; buffer-kernel 1 accumulates in place in one
+  buffer, buffer-kernel 2 in two buffers used in turn.  Here: tiled or linear
+  device-resident input, and one accumulator in place (cmp_opts.pingpong 0) or
+  two used in turn (pingpong 1).  The paper's image-kernel 2 differs from
+  image-kernel 1 only in taking the raster size as kernel arguments, which
+  HIP kernels always do, so it is the same kernel here.
+* ``h2d-sweep``: the host-to-device copy rate of a plain copy from pinned
+  memory as a function of buffer size, 64 KiB to 64 MiB in steps of 64 KiB
+  (the copy baseline of Section 6, its buffer-size figure).
 
-Usage: python -m paper_2104_14667_amd.experiments {repack-sweep,paper-table} [--out FILE]
+Usage: python -m paper_2104_14667_amd.experiments
+           {repack-sweep,paper-table,kernel-table,h2d-sweep} [--out FILE]
 """
 
 from __future__ import annotations
@@ -143,6 +156,80 @@ def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"
     return {"ring": ring_size, "rows": rows}
 
 
+def kernel_table(size: str = "4k", launches: int = 10000, seed: int = 12) -> dict:
+    """Mean kernel time per launch of one raster, for the four kernels."""
+    import torch
+
+    from . import synth
+    from .composite import (CMP_TILED, Composite, composite_repack_tiled,
+                            composite_tiled_bytes)
+    W, H = PAPER_SIZES[size]
+    tw, th = 64, 64
+    e = synth.elevation(seed, H, W, 32.0)
+    m = torch.from_numpy(synth.mask(e, 128)).to("cuda:0")
+    tb = composite_tiled_bytes(W, H, tw, th)
+    tiled = torch.zeros(tb, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    composite_repack_tiled(m, W * H, tiled, tb, 1, W, H, tw, th)
+    torch.cuda.synchronize()
+    rows = []
+    for name, layout, pp in (("image-kernel 1 and 2: tiled input, two accumulators in turn", "tiled", 1),
+                             ("buffer-kernel 1: linear input, one accumulator in place", "linear", 0),
+                             ("buffer-kernel 2: linear input, two accumulators in turn", "linear", 1),
+                             ("tiled input, one accumulator in place (no counterpart)", "tiled", 0)):
+        kw = dict(profile=1, pingpong=pp)
+        if layout == "tiled":
+            kw.update(layout=CMP_TILED, tile_w=tw, tile_h=th)
+        src = tiled if layout == "tiled" else m
+        with Composite(W, H, ("count",), 32, **kw) as c:
+            for _ in range(20):
+                c.add_device([src])
+            c.sync()
+            c.kernel_stats(reset=True)
+            t0 = time.perf_counter()
+            for _ in range(launches):
+                c.add_device([src])
+            c.sync()
+            wall = time.perf_counter() - t0
+            n, ms = c.kernel_stats(reset=True)
+            got = c.read("count")
+        exact = bool(np.array_equal(got, (launches + 20) * (e < 128).astype(np.uint32)))
+        rows.append({"kernel": name, "launches": n, "avg_us": round(ms * 1e3 / n, 2),
+                     "total_us": round(ms * 1e3, 0), "wall_per_launch_us": round(wall * 1e6 / launches, 2),
+                     "exact": exact})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"size": size, "W": W, "H": H, "tile": [tw, th], "output": "count u32", "rows": rows}
+
+
+def h2d_sweep(lo: int = 64 << 10, hi: int = 64 << 20, step: int = 64 << 10, reps: int = 10) -> dict:
+    """Plain pinned host-to-device copy rate (GB/s) by buffer size."""
+    import torch
+    host = torch.empty(hi, dtype=torch.uint8, pin_memory=True)
+    host.fill_(1)
+    dev = torch.empty(hi, dtype=torch.uint8, device="cuda:0")
+    s = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    sizes = list(range(lo, hi + 1, step))
+    rate = []
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        dev[:lo].copy_(host[:lo], non_blocking=True)          # warm-up
+        for n in sizes:
+            ev[0].record(s)
+            for _ in range(reps):
+                dev[:n].copy_(host[:n], non_blocking=True)
+            ev[1].record(s)
+            ev[1].synchronize()
+            rate.append(n * reps / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9)
+    r = np.array(rate)
+    big = r[np.array(sizes) >= (8 << 20)]
+    return {"sizes": sizes, "GBps": [round(x, 3) for x in rate], "reps": reps,
+            "seconds": round(time.perf_counter() - t0, 1),
+            "summary": {"at_64KiB": round(float(r[0]), 2), "at_1MiB": round(float(r[15]), 2),
+                        "mean_8MiB_up": round(float(big.mean()), 2),
+                        "max": round(float(r.max()), 2)}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -156,10 +243,23 @@ def main(argv=None):
     b.add_argument("--ns", default="10,100,1000")
     b.add_argument("--sizes", default="2k,4k,8k")
     b.add_argument("--out", default=None)
+    c = sub.add_parser("kernel-table")
+    c.add_argument("--size", default="4k", choices=sorted(PAPER_SIZES))
+    c.add_argument("--launches", type=int, default=10000)
+    c.add_argument("--out", default=None)
+    d = sub.add_parser("h2d-sweep")
+    d.add_argument("--reps", type=int, default=10)
+    d.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     if args.cmd == "repack-sweep":
         res = repack_sweep(args.lo, args.hi, args.step, args.reps)
         res["summary"] = summarize_sweep(res)
+        print(json.dumps(res["summary"]))
+    elif args.cmd == "kernel-table":
+        res = kernel_table(args.size, args.launches)
+        print(json.dumps(res))
+    elif args.cmd == "h2d-sweep":
+        res = h2d_sweep(reps=args.reps)
         print(json.dumps(res["summary"]))
     else:
         res = paper_table(tuple(int(x) for x in args.ns.split(",")),

@@ -44,3 +44,20 @@ def colliding(raster: np.ndarray, j: int, k: int) -> np.ndarray:
     out = words.view(np.uint8)[: b.size]
     assert np.all(words.view(np.uint8)[b.size:] == 0), "padding must stay zero"
     return out.reshape(raster.shape).copy()
+
+
+def tile(raster: np.ndarray, tw: int, th: int) -> np.ndarray:
+    """The tiled layout of include/composite.h (cmp_layout): tiles of tw bytes
+    x th rows, stored tile after tile in row-major tile order, each tile
+    row-major, zero padding past the raster's edges; returned flat."""
+    H, W = raster.shape
+    ntx, nty = -(-W // tw), -(-H // th)
+    pad = np.zeros((nty * th, ntx * tw), np.uint8)
+    pad[:H, :W] = raster
+    return pad.reshape(nty, th, ntx, tw).transpose(0, 2, 1, 3).reshape(-1).copy()
+
+
+def untile(flat: np.ndarray, W: int, H: int, tw: int, th: int) -> np.ndarray:
+    ntx, nty = -(-W // tw), -(-H // th)
+    pad = flat.reshape(nty, ntx, th, tw).transpose(0, 2, 1, 3).reshape(nty * th, ntx * tw)
+    return pad[:H, :W].copy()

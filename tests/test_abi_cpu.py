@@ -37,7 +37,7 @@ def test_default_opts():
     assert (o.nbuf, o.chunk_depth, o.layout, o.tile_w, o.tile_h) == (2, 8, cb.CMP_LINEAR, 64, 64)
     assert o.copy_stream is None and o.compute_stream is None
     assert C.sizeof(cb.cmp_opts) == 72
-    assert o.host_paced == 1 and o.pageable_host == 0 and o.verify_members == 0
+    assert o.host_paced == 1 and o.pageable_host == 0 and o.verify_members == 0 and o.pingpong == 0
 
 
 def test_argument_checks_before_any_device_call():
@@ -55,7 +55,10 @@ def test_argument_checks_before_any_device_call():
     o.layout = cb.CMP_TILED
     assert cb.lib.composite_init(C.byref(h), 24, 4, 1, 32, C.byref(o)) == cb.CMP_EUNSUPPORTED
     o = cb.composite_default_opts()
-    o.reserved[1] = 1
+    o.reserved[0] = 1
+    assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
+    o = cb.composite_default_opts()
+    o.pingpong = 2
     assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
     o = cb.composite_default_opts()
     o.verify_members = 2

@@ -51,3 +51,15 @@ def test_colliding_raster_is_different_with_equal_fingerprint():
     c = colliding(r, 3, 10)
     assert not np.array_equal(c, r)
     assert fingerprint(c) == fingerprint(r)
+
+
+def test_tile_layout_round_trip_and_order():
+    from fingerprint_ref import tile, untile
+    r = np.arange(37 * 70, dtype=np.int64).reshape(37, 70).astype(np.uint8)
+    t = tile(r, 32, 16)                       # 3 x 3 tiles of 32x16
+    assert t.size == 9 * 32 * 16
+    assert np.array_equal(untile(t, 70, 37, 32, 16), r)
+    assert np.array_equal(t[:32], r[0, :32])          # tile 0, row 0
+    assert np.array_equal(t[32:64], r[1, :32])        # tile 0, row 1
+    assert np.array_equal(t[512:544], r[0, 32:64])    # tile 1, row 0
+    assert not t[2 * 512 + 6:2 * 512 + 32].any()       # tile 2, row 0: x 70..95 is padding

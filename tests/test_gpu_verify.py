@@ -10,7 +10,7 @@ from paper_2104_14667_amd import synth
 from paper_2104_14667_amd.composite import (CMP_EINVAL, CMP_ENOTMEMBER, CMP_TILED, Composite,
                                             CompositeError)
 
-from fingerprint_ref import colliding
+from fingerprint_ref import colliding, tile, untile
 from gpu_common import check_full, dev_of, expect_oracle, pinned_copy, say
 
 pytestmark = pytest.mark.gpu
@@ -123,19 +123,28 @@ def test_retained_raster_changed_in_place_is_refused():
 def test_fingerprint_is_the_documented_sum(layout):
     """A raster built to collide under the documented definition is accepted
     (the fingerprint detects mistakes, not forgeries); the same change without
-    its compensating word is refused.  Words 3 and the last one are used, so a
-    wrong weight or word index anywhere between them shows."""
-    W, H = 256, 37                              # 9472 px = 2368 words
+    its compensating word is refused.  The two words are far apart (a wrong
+    weight or word index anywhere between them shows).  In a tiled context the
+    fingerprint is over the tiled layout, so the words are chosen there."""
+    W, H, tw, th = 256, 37, 64, 64                # 9472 px; tiled: 4 tiles of 64x64
     A = synth.random_members(25, 1, H, W)[0].copy()
-    flat = A.ravel()
-    nw = flat.size // 4
-    flat[12:16] = 0                             # word 3 zero
-    flat[4 * (nw - 1):] = 255                   # last word all ones
-    B = colliding(A, 3, nw - 1)
-    C = B.copy().ravel()
-    C[4 * (nw - 1):] = 255                      # uncompensated change
-    C = C.reshape(H, W)
-    kw = {"layout": CMP_TILED} if layout == "tiled" else {}
+    if layout == "linear":
+        flat = A.ravel().copy()
+        j, k = 3, flat.size // 4 - 1              # first row, x 12..15; last word
+        to_raster = lambda f: f.reshape(H, W)
+    else:
+        flat = tile(A, tw, th)
+        j, k = 3, (36 * tw + 60) // 4            # tile 0: row 0 x 12..15; row 36 x 60..63
+        to_raster = lambda f: untile(f, W, H, tw, th)
+    flat[4 * j:4 * j + 4] = 0                     # word j zero
+    flat[4 * k:4 * k + 4] = 255                   # word k all ones
+    A = to_raster(flat)
+    Bf = colliding(flat, j, k)
+    Cf = Bf.copy()
+    Cf[4 * k:4 * k + 4] = 255                     # uncompensated change
+    B, C = to_raster(Bf), to_raster(Cf)
+    assert not np.array_equal(A, B) and not np.array_equal(A, C)
+    kw = {"layout": CMP_TILED, "tile_w": tw, "tile_h": th} if layout == "tiled" else {}
     hA = pinned_copy(torch.from_numpy(A))
     hB = pinned_copy(torch.from_numpy(B))
     hC = pinned_copy(torch.from_numpy(C))
