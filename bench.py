@@ -616,6 +616,15 @@ def main():
     log("cpu baseline")
     out["cpu_baseline"] = cpu_baseline(ens, e, args.cpu_seconds)
     out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(ens, e, args.cpu_seconds)
+    # data per frame at 10 FPS (the paper's interactivity budget, Section 7.1)
+    from paper_2104_14667_amd.metrics import frame_budget_mb
+    fb = {"resident_depth8192": round(frame_budget_mb(value), 0)}
+    if "streamed" in out:
+        fb["streamed_mask4096"] = round(frame_budget_mb(
+            out["streamed"]["dual_buffer_linear"]["gpx_member_per_s"]), 0)
+        fb["streamed_depth8192"] = round(frame_budget_mb(
+            out["streamed_depth"]["dual_buffer_linear"]["gpx_member_per_s"]), 0)
+    out["frame_budget_10fps_MB"] = fb
     out["inputs_sha256"] = input_hashes()
     out["host"] = {"cpu": platform.processor() or platform.machine(),
                    "os_cpu_count": os.cpu_count()}

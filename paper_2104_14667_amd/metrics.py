@@ -10,6 +10,8 @@
 * The pipeline model of Section 7.1 bounds the time of a staged pipeline in
   which member i needs copy time c_i, transform time m_i and processing time
   p_i: the run takes at least max(c_1 + sum(m + p), sum(c) + m_n + p_n).
+* The frame budget of Section 7.1 is the data a pipeline processes within one
+  frame at an interactive rate: rate (GB/s) divided by the frame rate.
 """
 
 from __future__ import annotations
@@ -20,6 +22,11 @@ from typing import Sequence
 def gpx_members_per_s(n_members: int, W: int, H: int, seconds: float) -> float:
     """Gpixel-members per second."""
     return float(n_members) * float(W) * float(H) / float(seconds) / 1e9
+
+
+def frame_budget_mb(rate_gbps: float, fps: float = 10.0) -> float:
+    """MB (1e6 bytes) of 1-byte pixels processed per frame at `fps` frames/s."""
+    return float(rate_gbps) * 1e3 / float(fps)
 
 
 def efficiency(rate: float, copy_rate: float) -> float:

@@ -100,3 +100,18 @@ def test_bench_traffic_is_null_when_kernel_sources_change(tmp_path, monkeypatch)
     assert bench.measured_traffic() == 123
     f.write_text("kernel_sources_sha256 = 00\ntraffic_bytes = 123\n")
     assert bench.measured_traffic() is None
+
+
+def test_frame_budget_reproduces_the_papers_figures():
+    """The paper's data-per-frame figures at 10 FPS (Section 7.1) follow from
+    its dual-buffer ("2b final") rates at N=100 (its transfer-rate tables)
+    within 3%: the budget is the rate times the frame time."""
+    from paper_2104_14667_amd.metrics import frame_budget_mb
+    fb = GOLD["frame_budget"]
+    for size, mb in fb["mb_per_frame"].items():
+        row = [r for r in GOLD["rows"] if r["set"] == size and r["alg"] == "2b final" and r["N"] == 100]
+        assert len(row) == 1
+        got = frame_budget_mb(row[0]["rate_gbs"], fb["fps"])
+        assert abs(got - mb) / mb < 0.03, (size, got, mb)
+    assert frame_budget_mb(56.0) == 5600.0
+    assert frame_budget_mb(1.0, fps=20) == 50.0
