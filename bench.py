@@ -127,6 +127,18 @@ def run_resident(torch, ens, e, steps, warmup):
     return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact, ceiling=ceiling)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), else the machine type."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def same_traffic_ceiling(torch, dev):
     """Best time of the same-traffic reference kernel (libceiling.so) on the
     resident members: read + composite read-modify-write, and read only."""
@@ -334,6 +346,33 @@ def run_served(torch, duration_s, spill_duration_s):
                        "Poisson 2000 req/s, add/remove 1-32 members (60/40), 1024x1024 viewport",
            "requests": n, "offered_rps": wl.rate}
 
+    def final_views_exact(srv, sids, sched, held, every=8):
+        """After a replay: one 1024x1024 viewport of every `every`-th session,
+        read by an empty add, against the closed form of the session's final
+        members (count = #{member levels L > e} for depth members)."""
+        cur = [dict() for _ in range(wl.sessions)]
+        for k, h in enumerate(held or []):
+            for i in h:
+                cur[k][i] = cur[k].get(i, 0) + 1
+        for r in sched:
+            c = cur[r["sid"]]
+            for i in (int(x) for x in r["ids"]):
+                c[i] = c.get(i, 0) + (1 if r["op"] == "add" else -1)
+                if c[i] == 0:
+                    del c[i]
+        dst = torch.empty((wl.view, wl.view), dtype=torch.int32, pin_memory=True)
+        ok, checked = True, 0
+        for k in range(0, wl.sessions, every):
+            x0, y0 = (k * 97) % (wl.W - wl.view + 1), (k * 89) % (wl.H - wl.view + 1)
+            srv.wait(srv.submit(sids[k], CMP_OP_ADD, [], (x0, y0, wl.view, wl.view), dst))
+            c = cur[k]
+            lvs = np.sort(np.repeat(lv[list(c)], list(c.values()))) if c else np.zeros(0, lv.dtype)
+            ev = e[y0:y0 + wl.view, x0:x0 + wl.view]
+            exp = len(lvs) - np.searchsorted(lvs, ev, side="right")
+            ok = ok and bool(np.array_equal(dst.numpy().view(np.uint32), exp))
+            checked += 1
+        return ok, checked
+
     def one(name, sched, held=None, **opts):
         """Replays sched; held: per-session member lists loaded untimed first."""
         log(f"  {name}")
@@ -350,6 +389,7 @@ def run_served(torch, duration_s, spill_duration_s):
             lat = srv.replay(sched, sids, ring, wl.view)
             wall = time.perf_counter() - t0
             st = srv.stats()
+            exact, checked = final_views_exact(srv, sids, sched, held)
         st = {k: st[k] - (st0[k] if k not in ("max_step", "resident_slots") else 0) for k in st}
         lat_ms = lat / 1e6
         pxm = sum(len(r["ids"]) for r in sched) * plane
@@ -361,7 +401,9 @@ def run_served(torch, duration_s, spill_duration_s):
                      "max_step": st["max_step"], "spills": st["spills"], "restores": st["restores"],
                      "drops": st["drops"], "rebuilds": st["rebuilds"],
                      "device_ms_per_request": round(st["device_ms"] / max(1, st["requests"]), 4),
-                     "gpx_member_per_s": round(pxm / wall / 1e9, 1)}
+                     "gpx_member_per_s": round(pxm / wall / 1e9, 1),
+                     "exact": exact, "sessions_checked": checked}
+
 
     def window(start_s, dur_s):
         """Requests in [start_s, start_s + dur_s) of the schedule, re-timed from
@@ -626,8 +668,7 @@ def main():
             out["streamed_depth"]["dual_buffer_linear"]["gpx_member_per_s"]), 0)
     out["frame_budget_10fps_MB"] = fb
     out["inputs_sha256"] = input_hashes()
-    out["host"] = {"cpu": platform.processor() or platform.machine(),
-                   "os_cpu_count": os.cpu_count()}
+    out["host"] = {"cpu": cpu_model(), "os_cpu_count": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 
