@@ -77,6 +77,8 @@ struct cmp_ctx {
   const uint8_t **d_tab[2] = {nullptr, nullptr};
   int64_t tab_cap = 0;
   int tab_half = 0;
+  int tab_last = -1;        // half holding the last uploaded table, or -1
+  int64_t tab_last_n = 0;
   hipEvent_t ev_tab[2] = {nullptr, nullptr};
 
   // Pinned bounce buffers for uploads from pageable host memory, and pinned
@@ -303,9 +305,18 @@ int alloc_staging(cmp_ctx *ctx) {
 }
 
 // Uploads a device pointer table through the pinned double buffer and returns
-// its device address (valid for work enqueued on the compute stream next).
+// its device address (valid for work enqueued on the compute stream next).  A
+// table equal to the last one uploaded is not uploaded again: its device copy
+// is only overwritten by a later upload, which goes to the other half and is
+// ordered on the compute stream after every kernel that reads this one.
 int upload_table(cmp_ctx *ctx, const uint8_t *const *ptrs, int64_t n, const uint8_t ***d_out) {
+  if (ctx->tab_last >= 0 && n == ctx->tab_last_n &&
+      std::memcmp(ctx->h_tab[ctx->tab_last], ptrs, n * sizeof(void *)) == 0) {
+    *d_out = ctx->d_tab[ctx->tab_last];
+    return CMP_OK;
+  }
   if (n > ctx->tab_cap) {
+    ctx->tab_last = -1;
     for (int i = 0; i < 2; ++i) {
       if (ctx->ev_tab[i] && hipEventSynchronize(ctx->ev_tab[i]) != hipSuccess) return CMP_EDEVICE;
       if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
@@ -332,6 +343,8 @@ int upload_table(cmp_ctx *ctx, const uint8_t *const *ptrs, int64_t n, const uint
                      ctx->comp_s) != hipSuccess)
     return CMP_EDEVICE;
   if (hipEventRecord(ctx->ev_tab[h], ctx->comp_s) != hipSuccess) return CMP_EDEVICE;
+  ctx->tab_last = h;
+  ctx->tab_last_n = n;
   *d_out = ctx->d_tab[h];
   return CMP_OK;
 }

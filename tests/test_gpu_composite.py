@@ -288,3 +288,23 @@ def test_full_depth_8192_n128(mode):
             torch.cuda.empty_cache()
             c.add([host[i] for i in range(ens.N)])
         check_closed_form_and_samples(c, ens, e, lv)
+
+
+def test_repeated_and_alternating_member_tables():
+    """Calls that repeat the previous call's rasters reuse its device table;
+    alternating and repeated tables give the oracle's composite."""
+    W, H = 200, 9
+    A = _random_stack(41, 3, H, W)
+    B = _random_stack(42, 2, H, W)
+    dA, dB = dev_of(A), dev_of(B)
+    a = [dA[i] for i in range(3)]
+    b = [dB[i] for i in range(2)]
+    with Composite(W, H, ALL, 32, retain_members=1) as c:
+        for maps in (a, a, b, a, b, b, a[:2], a[:2]):
+            c.add_device(maps)
+        stack = np.concatenate([A, A, B, A, B, B, A[:2], A[:2]])
+        check_full(c, expect_oracle(stack, ALL, 32))
+        c.remove(maps=b, on_device=True)
+        c.remove(maps=b, on_device=True)
+        check_full(c, expect_oracle(np.concatenate([A, A, B, A, A[:2], A[:2]]), ("count", "sum"), 32)
+                   | {"max": expect_oracle(stack, ("max",), 32)["max"]})
