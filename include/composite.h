@@ -88,6 +88,19 @@ typedef struct cmp_opts {
   void *copy_stream;      /* hipStream_t for uploads, or NULL: the library
                              creates a default-priority stream */
   void *compute_stream;   /* hipStream_t for kernels, or NULL (as above) */
+  void *(*dev_alloc)(size_t bytes, void *alloc_ctx);
+                          /* device allocator for the context's composite,
+                             staging, tables and scratch (for instance a
+                             framework's caching allocator), or NULL for
+                             hipMalloc.  It must return memory of the context's
+                             device, 256-byte aligned, or NULL (then the call
+                             that needed it returns CMP_ENOMEM).  Given with
+                             dev_free or not at all.  Default NULL */
+  void (*dev_free)(void *ptr, void *alloc_ctx);
+                          /* frees what dev_alloc returned; the library calls
+                             it only once its streams no longer use the memory.
+                             Default NULL */
+  void *alloc_ctx;        /* passed to both hooks.  Default NULL */
   int32_t retain_members; /* 1: remember the device pointer of every member
                              added with composite_add_device, so a remove can
                              recompute max.  The caller keeps those rasters

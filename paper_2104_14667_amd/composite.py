@@ -27,10 +27,16 @@ CMP_DST_HOST, CMP_DST_DEVICE, CMP_DST_PINNED = 0, 1, 2
 OUTPUT_BITS = {"count": CMP_COUNT, "sum": CMP_SUM, "max": CMP_MAX}
 
 
+# cmp_opts.dev_alloc / dev_free: device allocator hooks.
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class cmp_opts(C.Structure):
     _fields_ = [("nbuf", C.c_int32), ("chunk_depth", C.c_int32), ("layout", C.c_int32),
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("device", C.c_int32),
                 ("copy_stream", C.c_void_p), ("compute_stream", C.c_void_p),
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("retain_members", C.c_int32), ("debug_poison", C.c_int32),
                 ("profile", C.c_int32), ("pageable_host", C.c_int32),
                 ("host_paced", C.c_int32), ("verify_members", C.c_int32),
@@ -269,17 +275,42 @@ def composite_free(ctx: int) -> None:
 _DT = {CMP_SUM: np.uint32, CMP_MAX: np.uint8}
 
 
-class Composite:
-    """One compositing context (owner of a device composite)."""
+def torch_allocator(device: int = 0):
+    """(alloc, free) over torch's caching allocator, for Composite(allocator=...).
+    Blocks are associated with torch's current stream of `device`; the library
+    frees them only once its own streams no longer use them."""
+    import torch
 
-    def __init__(self, W: int, H: int, outputs=("count",), count_bits: int = 32, **opts):
+    def alloc(nbytes: int) -> int:
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes), device))
+
+    def free(ptr: int) -> None:
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return alloc, free
+
+
+class Composite:
+    """One compositing context (owner of a device composite).
+
+    allocator: None (hipMalloc), "torch" (torch's caching allocator), or a pair
+    of callables alloc(nbytes) -> device address and free(address)."""
+
+    def __init__(self, W: int, H: int, outputs=("count",), count_bits: int = 32, allocator=None,
+                 **opts):
         self.W, self.H = int(W), int(H)
         self.outputs = tuple(outputs)
         self.count_bits = int(count_bits)
         o = composite_default_opts()
+        if allocator is not None:
+            a, f = torch_allocator(int(opts.get("device", 0))) if allocator == "torch" else allocator
+            # the callbacks must outlive the context
+            self._hooks = (DEV_ALLOC_FN(lambda n, _ctx: a(n) or None),
+                           DEV_FREE_FN(lambda ptr, _ctx: f(ptr)))
+            o.dev_alloc, o.dev_free = self._hooks
         fields = {f[0] for f in cmp_opts._fields_}
         for k, v in opts.items():
-            if k not in fields or k == "reserved":
+            if k not in fields or k in ("reserved", "dev_alloc", "dev_free", "alloc_ctx"):
                 raise TypeError(f"unknown option {k!r}")
             if k in ("copy_stream", "compute_stream") and v is not None and not isinstance(v, int):
                 v = int(v.cuda_stream)          # torch.cuda.Stream

@@ -132,6 +132,21 @@ int elem_bytes(const cmp_ctx *ctx, uint32_t which) {
 
 hipError_t set_device(const cmp_ctx *ctx) { return hipSetDevice(ctx->dev); }
 
+// Device memory of the context: through the caller's allocator hooks when
+// given (cmp_opts.dev_alloc / dev_free), else hipMalloc / hipFree.  Memory is
+// freed only once the context's streams no longer use it.
+bool dalloc(cmp_ctx *ctx, void **p, size_t bytes) {
+  *p = nullptr;
+  if (ctx->o.dev_alloc) *p = ctx->o.dev_alloc(bytes, ctx->o.alloc_ctx);
+  else if (hipMalloc(p, bytes) != hipSuccess) *p = nullptr;
+  return *p != nullptr;
+}
+void dfree(cmp_ctx *ctx, void *p) {
+  if (!p) return;
+  if (ctx->o.dev_free) ctx->o.dev_free(p, ctx->o.alloc_ctx);
+  else hipFree(p);
+}
+
 // Range guard: refuse any add that could overflow a stored value.
 bool fits(const cmp_ctx *ctx, int64_t add) {
   const int64_t total = ctx->members + add;
@@ -144,17 +159,17 @@ void free_all(cmp_ctx *ctx) {
   hipSetDevice(ctx->dev);
   if (ctx->comp_s) hipStreamSynchronize(ctx->comp_s);
   if (ctx->copy_s) hipStreamSynchronize(ctx->copy_s);
-  hipFree(ctx->d_count);
-  hipFree(ctx->d_sum);
-  hipFree(ctx->d_max);
-  hipFree(ctx->d_count_alt);
-  hipFree(ctx->d_sum_alt);
-  hipFree(ctx->d_max_alt);
+  dfree(ctx, ctx->d_count);
+  dfree(ctx, ctx->d_sum);
+  dfree(ctx, ctx->d_max);
+  dfree(ctx, ctx->d_count_alt);
+  dfree(ctx, ctx->d_sum_alt);
+  dfree(ctx, ctx->d_max_alt);
   for (int i = 0; i < 2; ++i) {
-    hipFree(ctx->d_stage[i]);
-    hipFree(ctx->d_tiled[i]);
-    hipFree(ctx->d_slot_tab[i]);
-    hipFree(ctx->d_tab[i]);
+    dfree(ctx, ctx->d_stage[i]);
+    dfree(ctx, ctx->d_tiled[i]);
+    dfree(ctx, ctx->d_slot_tab[i]);
+    dfree(ctx, ctx->d_tab[i]);
     if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
     if (ctx->h_bounce[i]) hipHostFree(ctx->h_bounce[i]);
     if (ctx->h_read[i]) hipHostFree(ctx->h_read[i]);
@@ -165,8 +180,8 @@ void free_all(cmp_ctx *ctx) {
     if (ctx->ev_tab[i]) hipEventDestroy(ctx->ev_tab[i]);
   }
   if (ctx->ev_host_done) hipEventDestroy(ctx->ev_host_done);
-  hipFree(ctx->d_hist);
-  hipFree(ctx->d_fp);
+  dfree(ctx, ctx->d_hist);
+  dfree(ctx, ctx->d_fp);
   if (ctx->h_fp) hipHostFree(ctx->h_fp);
   for (auto &t : ctx->timed) {
     hipEventDestroy(t.a);
@@ -264,9 +279,9 @@ int64_t member_bytes(const cmp_ctx *ctx) {
 
 void drop_staging(cmp_ctx *ctx) {
   for (int i = 0; i < 2; ++i) {
-    hipFree(ctx->d_stage[i]);
-    hipFree(ctx->d_tiled[i]);
-    hipFree(ctx->d_slot_tab[i]);
+    dfree(ctx, ctx->d_stage[i]);
+    dfree(ctx, ctx->d_tiled[i]);
+    dfree(ctx, ctx->d_slot_tab[i]);
     ctx->d_stage[i] = ctx->d_tiled[i] = nullptr;
     ctx->d_slot_tab[i] = nullptr;
   }
@@ -291,9 +306,9 @@ int alloc_staging(cmp_ctx *ctx) {
     ctx->tiled_stride = (tl.plane() + 255) / 256 * 256;
   }
   for (int sidx = 0; sidx < ctx->o.nbuf; ++sidx) {
-    if (hipMalloc(&ctx->d_stage[sidx], ctx->stage_stride * d) != hipSuccess) return CMP_ENOMEM;
-    if (tiled && hipMalloc(&ctx->d_tiled[sidx], ctx->tiled_stride * d) != hipSuccess) return CMP_ENOMEM;
-    if (hipMalloc(&ctx->d_slot_tab[sidx], sizeof(void *) * d) != hipSuccess) return CMP_ENOMEM;
+    if (!dalloc(ctx, (void **)&ctx->d_stage[sidx], ctx->stage_stride * d)) return CMP_ENOMEM;
+    if (tiled && !dalloc(ctx, (void **)&ctx->d_tiled[sidx], ctx->tiled_stride * d)) return CMP_ENOMEM;
+    if (!dalloc(ctx, (void **)&ctx->d_slot_tab[sidx], sizeof(void *) * d)) return CMP_ENOMEM;
     std::vector<const uint8_t *> tab(d);
     uint8_t *base = tiled ? ctx->d_tiled[sidx] : ctx->d_stage[sidx];
     const int64_t stride = tiled ? ctx->tiled_stride : ctx->stage_stride;
@@ -320,7 +335,7 @@ int upload_table(cmp_ctx *ctx, const uint8_t *const *ptrs, int64_t n, const uint
     for (int i = 0; i < 2; ++i) {
       if (ctx->ev_tab[i] && hipEventSynchronize(ctx->ev_tab[i]) != hipSuccess) return CMP_EDEVICE;
       if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
-      hipFree(ctx->d_tab[i]);
+      dfree(ctx, ctx->d_tab[i]);
       ctx->h_tab[i] = nullptr;
       ctx->d_tab[i] = nullptr;
     }
@@ -330,7 +345,7 @@ int upload_table(cmp_ctx *ctx, const uint8_t *const *ptrs, int64_t n, const uint
     for (int i = 0; i < 2; ++i) {
       if (hipHostMalloc((void **)&ctx->h_tab[i], cap * sizeof(void *), hipHostMallocDefault) != hipSuccess)
         return CMP_ENOMEM;
-      if (hipMalloc((void **)&ctx->d_tab[i], cap * sizeof(void *)) != hipSuccess) return CMP_ENOMEM;
+      if (!dalloc(ctx, (void **)&ctx->d_tab[i], cap * sizeof(void *))) return CMP_ENOMEM;
     }
     ctx->tab_cap = cap;
   }
@@ -462,13 +477,13 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
 int begin_fingerprints(cmp_ctx *ctx, int64_t n) {
   if (n > ctx->fp_cap) {
     if (hipStreamSynchronize(ctx->comp_s) != hipSuccess) return CMP_EDEVICE;
-    hipFree(ctx->d_fp);
+    dfree(ctx, ctx->d_fp);
     if (ctx->h_fp) hipHostFree(ctx->h_fp);
     ctx->d_fp = nullptr;
     ctx->h_fp = nullptr;
     ctx->fp_cap = 0;
     const int64_t cap = std::max<int64_t>(n, 1024);
-    if (hipMalloc((void **)&ctx->d_fp, cap * 8) != hipSuccess) return CMP_ENOMEM;
+    if (!dalloc(ctx, (void **)&ctx->d_fp, cap * 8)) return CMP_ENOMEM;
     if (hipHostMalloc((void **)&ctx->h_fp, cap * 8, hipHostMallocDefault) != hipSuccess) return CMP_ENOMEM;
     ctx->fp_cap = cap;
   }
@@ -548,6 +563,7 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
   if (o.pageable_host != 0 && o.pageable_host != 1) return CMP_EINVAL;
   if (o.verify_members != 0 && o.verify_members != 1) return CMP_EINVAL;
   if (o.pingpong != 0 && o.pingpong != 1) return CMP_EINVAL;
+  if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) return CMP_EINVAL;
   if (o.layout == CMP_TILED) {
     if (o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64 && o.tile_w != 128) return CMP_EINVAL;
     if (o.tile_h < 1 || o.tile_h > 256) return CMP_EINVAL;
@@ -601,16 +617,16 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
     rc = CMP_ENOMEM;
     const bool pp = o.pingpong != 0;
     if (outputs & CMP_COUNT) {
-      if (hipMalloc(&ctx->d_count, ctx->npix * (ctx->count_bits / 8) + 64) != hipSuccess) break;
-      if (pp && hipMalloc(&ctx->d_count_alt, ctx->npix * (ctx->count_bits / 8) + 64) != hipSuccess) break;
+      if (!dalloc(ctx, &ctx->d_count, ctx->npix * (ctx->count_bits / 8) + 64)) break;
+      if (pp && !dalloc(ctx, &ctx->d_count_alt, ctx->npix * (ctx->count_bits / 8) + 64)) break;
     }
     if (outputs & CMP_SUM) {
-      if (hipMalloc((void **)&ctx->d_sum, ctx->npix * 4 + 64) != hipSuccess) break;
-      if (pp && hipMalloc((void **)&ctx->d_sum_alt, ctx->npix * 4 + 64) != hipSuccess) break;
+      if (!dalloc(ctx, (void **)&ctx->d_sum, ctx->npix * 4 + 64)) break;
+      if (pp && !dalloc(ctx, (void **)&ctx->d_sum_alt, ctx->npix * 4 + 64)) break;
     }
     if (outputs & CMP_MAX) {
-      if (hipMalloc((void **)&ctx->d_max, ctx->npix + 64) != hipSuccess) break;
-      if (pp && hipMalloc((void **)&ctx->d_max_alt, ctx->npix + 64) != hipSuccess) break;
+      if (!dalloc(ctx, (void **)&ctx->d_max, ctx->npix + 64)) break;
+      if (pp && !dalloc(ctx, (void **)&ctx->d_max_alt, ctx->npix + 64)) break;
     }
     rc = CMP_EDEVICE;
     if (clear_outputs(ctx) != hipSuccess) break;
@@ -950,10 +966,10 @@ int composite_histogram(cmp_ctx *ctx, int64_t *bins, int32_t nbins, int64_t *ove
   CMP_TRY(hipStreamSynchronize(ctx->copy_s));
   if (ctx->hist_cap < nbins + 1) {
     CMP_TRY(hipStreamSynchronize(ctx->comp_s));
-    hipFree(ctx->d_hist);
+    dfree(ctx, ctx->d_hist);
     ctx->d_hist = nullptr;
     ctx->hist_cap = 0;
-    if (hipMalloc((void **)&ctx->d_hist, sizeof(unsigned long long) * (nbins + 1)) != hipSuccess)
+    if (!dalloc(ctx, (void **)&ctx->d_hist, sizeof(unsigned long long) * (nbins + 1)))
       return CMP_ENOMEM;
     ctx->hist_cap = nbins + 1;
   }

@@ -36,7 +36,7 @@ def test_default_opts():
     o = cb.composite_default_opts()
     assert (o.nbuf, o.chunk_depth, o.layout, o.tile_w, o.tile_h) == (2, 8, cb.CMP_LINEAR, 64, 64)
     assert o.copy_stream is None and o.compute_stream is None
-    assert C.sizeof(cb.cmp_opts) == 72
+    assert C.sizeof(cb.cmp_opts) == 96
     assert o.host_paced == 1 and o.pageable_host == 0 and o.verify_members == 0 and o.pingpong == 0
 
 
@@ -59,6 +59,9 @@ def test_argument_checks_before_any_device_call():
     assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
     o = cb.composite_default_opts()
     o.pingpong = 2
+    assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
+    o = cb.composite_default_opts()
+    o.dev_alloc = cb.DEV_ALLOC_FN(lambda n, ctx: None)        # without dev_free
     assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
     o = cb.composite_default_opts()
     o.verify_members = 2
