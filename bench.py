@@ -121,10 +121,29 @@ def run_resident(torch, ens, e, steps, warmup):
         t1 = time.perf_counter()
         launches, kms = c.kernel_stats(reset=True)
         exact = verify(c, ens, e, steps + warmup)
+        hist = overlap_histogram(c, ens, steps + warmup)
     ceiling = same_traffic_ceiling(torch, dev)
     del dev, ptrs
     torch.cuda.empty_cache()
-    return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact, ceiling=ceiling)
+    return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact, ceiling=ceiling,
+                histogram=hist)
+
+
+def overlap_histogram(c, ens, times, reps=10):
+    """Overlap-class histogram of the working composite (Figure 1): one bin per
+    possible count (times x N + 1), call to host bins; checked against numpy on
+    the composite read back."""
+    nb = times * ens.N + 1
+    c.histogram(nb)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bins, over = c.histogram(nb)
+    dt = (time.perf_counter() - t0) / reps
+    ref = np.bincount(c.read("count").ravel(), minlength=nb)
+    npix = ens.W * ens.H
+    return {"bins": nb, "call_us": round(dt * 1e6, 1),
+            "count_GBps": round(npix * 4 / dt / 1e9, 1),
+            "exact": bool(over == 0 and np.array_equal(bins, ref[:nb]))}
 
 
 def cpu_model() -> str:
@@ -611,6 +630,7 @@ def main():
                                "max u8; device-resident, one launch per step",
                    "members": ens.N, "W": ens.W, "H": ens.H, "seed": ens.seed},
         "bit_exact": r["exact"],
+        "histogram": r["histogram"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),

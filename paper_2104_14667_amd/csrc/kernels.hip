@@ -351,7 +351,8 @@ __global__ __launch_bounds__(256) void k_pack(const T *__restrict__ src, int32_t
 
 // One workgroup walks vectors of 8 counts with a grid stride and counts them
 // into bins privatized in LDS (or straight into global memory for large bin
-// counts); LDS bins are flushed once per workgroup.
+// counts), one atomic per run of equal values; LDS bins are flushed once per
+// workgroup.
 template <bool C16, bool LDS>
 __global__ __launch_bounds__(256) void k_histogram(const void *__restrict__ count, uint32_t npix,
                                                    int32_t nbins,
@@ -361,32 +362,45 @@ __global__ __launch_bounds__(256) void k_histogram(const void *__restrict__ coun
     for (int b = threadIdx.x; b <= nbins; b += blockDim.x) sh[b] = 0u;
     __syncthreads();
   }
-  auto put = [&](uint32_t c) {
+  auto put = [&](uint32_t c, uint32_t k) {
     const int b = c < (uint32_t)nbins ? (int)c : nbins;
-    if constexpr (LDS) atomicAdd(&sh[b], 1u);
-    else atomicAdd(&bins[b], 1ull);
+    if constexpr (LDS) atomicAdd(&sh[b], k);
+    else atomicAdd(&bins[b], (unsigned long long)k);
+  };
+  // Neighbouring pixels of a composite mostly share their class: a run of
+  // equal values among a thread's 8 pixels costs one atomic.
+  auto put8 = [&](const uint32_t (&c)[8]) {
+    uint32_t cur = c[0], run = 1;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      if (c[k] == cur) {
+        ++run;
+      } else {
+        put(cur, run);
+        cur = c[k];
+        run = 1;
+      }
+    }
+    put(cur, run);
   };
   const uint32_t nv = npix / 8;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
     if constexpr (C16) {
       const uint4 x = reinterpret_cast<const uint4 *>(count)[v];
-      const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        put(w[k] & 0xffffu);
-        put(w[k] >> 16);
-      }
+      const uint32_t c[8] = {x.x & 0xffffu, x.x >> 16, x.y & 0xffffu, x.y >> 16,
+                             x.z & 0xffffu, x.z >> 16, x.w & 0xffffu, x.w >> 16};
+      put8(c);
     } else {
       const uint4 *p = reinterpret_cast<const uint4 *>(count) + 2 * (size_t)v;
       const uint4 a = p[0], b = p[1];
-      put(a.x); put(a.y); put(a.z); put(a.w);
-      put(b.x); put(b.y); put(b.z); put(b.w);
+      const uint32_t c[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      put8(c);
     }
   }
   // the last npix % 8 values
   if (blockIdx.x == 0 && threadIdx.x < npix - nv * 8) {
     const uint32_t i = nv * 8 + threadIdx.x;
-    put(C16 ? static_cast<const uint16_t *>(count)[i] : static_cast<const uint32_t *>(count)[i]);
+    put(C16 ? static_cast<const uint16_t *>(count)[i] : static_cast<const uint32_t *>(count)[i], 1u);
   }
   if constexpr (LDS) {
     __syncthreads();
@@ -403,7 +417,7 @@ hipError_t launch_histogram(const void *count, bool count16, int64_t npix, int32
   if (npix >= (int64_t(1) << 32) || nbins < 1) return hipErrorInvalidValue;
   const bool lds = nbins <= kLdsBins;
   const int64_t nv = npix / 8;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nv + 255) / 256, (int64_t)cus * 4));
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nv + 255) / 256, (int64_t)cus * 2));
   const size_t shm = lds ? sizeof(uint32_t) * (nbins + 1) : 0;
   if (count16) {
     if (lds) k_histogram<true, true><<<grid, 256, shm, s>>>(count, (uint32_t)npix, nbins, bins);
