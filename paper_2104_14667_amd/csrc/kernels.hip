@@ -469,15 +469,21 @@ hipError_t launch_pack_window(const void *src, int elem, int32_t W, int32_t x0, 
                               int32_t w, int32_t h, void *dst, int64_t dst_pitch,
                               hipStream_t s) {
   if (w <= 0 || h <= 0) return hipSuccess;
-  dim3 grid((unsigned)((w + 255) / 256), (unsigned)h);
-  uint8_t *d = static_cast<uint8_t *>(dst);
-  switch (elem) {
-    case 1: k_pack<uint8_t><<<grid, 256, 0, s>>>(static_cast<const uint8_t *>(src), W, x0, y0, w, h, d, dst_pitch); break;
-    case 2: k_pack<uint16_t><<<grid, 256, 0, s>>>(static_cast<const uint16_t *>(src), W, x0, y0, w, h, d, dst_pitch); break;
-    case 4: k_pack<uint32_t><<<grid, 256, 0, s>>>(static_cast<const uint32_t *>(src), W, x0, y0, w, h, d, dst_pitch); break;
-    default: return hipErrorInvalidValue;
+  if (elem != 1 && elem != 2 && elem != 4) return hipErrorInvalidValue;
+  // one grid row per window row, at most 65535 rows per launch
+  for (int32_t r0 = 0; r0 < h; r0 += 65535) {
+    const int32_t hr = std::min<int32_t>(65535, h - r0);
+    dim3 grid((unsigned)((w + 255) / 256), (unsigned)hr);
+    uint8_t *d = static_cast<uint8_t *>(dst) + (int64_t)r0 * dst_pitch;
+    switch (elem) {
+      case 1: k_pack<uint8_t><<<grid, 256, 0, s>>>(static_cast<const uint8_t *>(src), W, x0, y0 + r0, w, hr, d, dst_pitch); break;
+      case 2: k_pack<uint16_t><<<grid, 256, 0, s>>>(static_cast<const uint16_t *>(src), W, x0, y0 + r0, w, hr, d, dst_pitch); break;
+      default: k_pack<uint32_t><<<grid, 256, 0, s>>>(static_cast<const uint32_t *>(src), W, x0, y0 + r0, w, hr, d, dst_pitch); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace cmp
