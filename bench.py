@@ -255,11 +255,11 @@ def run_batched(torch, reps, tuned=True):
     one autotuned launch (graph replay; shared or persistent mode) against the
     best persistent launch and 64 plain launches."""
     from paper_2104_14667_amd import synth
-    from paper_2104_14667_amd.composite import (CMP_BATCH_PER_REQUEST, CMP_BATCH_PERSISTENT,
-                                                CMP_BATCH_SHARED, Pool, composite_default_tune,
-                                                make_tune)
+    from paper_2104_14667_amd.composite import (CMP_BATCH_MATRIX, CMP_BATCH_PER_REQUEST,
+                                                CMP_BATCH_PERSISTENT, CMP_BATCH_SHARED, Pool,
+                                                composite_default_tune, make_tune)
     MODE_NAMES = {CMP_BATCH_PERSISTENT: "persistent", CMP_BATCH_PER_REQUEST: "per_request",
-                  CMP_BATCH_SHARED: "shared"}
+                  CMP_BATCH_SHARED: "shared", CMP_BATCH_MATRIX: "matrix"}
     from paper_2104_14667_amd.tune import autotune
     wl = synth.BATCHED
     e = wl.elevation()
@@ -289,7 +289,8 @@ def run_batched(torch, reps, tuned=True):
             # the library's default tune, and its persistent fallback's parameters
             d = composite_default_tune()
             best = {k: getattr(d, k) for k in keys}
-            best["by_mode"] = {str(CMP_BATCH_PERSISTENT): dict(best, mode=CMP_BATCH_PERSISTENT)}
+            best["by_mode"] = {str(m): dict(best, mode=m)
+                               for m in (CMP_BATCH_PERSISTENT, CMP_BATCH_SHARED, CMP_BATCH_MATRIX)}
             out["autotune"] = "skipped: default tune"
 
         def tune_of(c, graph=1):
@@ -302,6 +303,9 @@ def run_batched(torch, reps, tuned=True):
             "persistent_graph": tune_of(persistent),
             "per_request_launches": make_tune(CMP_BATCH_PER_REQUEST, stream_loads=1),
         }
+        for mode in (CMP_BATCH_SHARED, CMP_BATCH_MATRIX):
+            if str(mode) in best["by_mode"] and best["mode"] != mode:
+                variants[MODE_NAMES[mode] + "_graph"] = tune_of(best["by_mode"][str(mode)])
         out["persistent_tune"] = {k: persistent[k] for k in keys}
         for name, tune in variants.items():
             log(f"  {name}")

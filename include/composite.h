@@ -276,8 +276,21 @@ typedef struct cmp_request {
  * needs distinct ids within each request and a pool of at most 65536
  * rasters whose member masks fit in LDS; a batch that does not qualify runs
  * in the PERSISTENT mode with the same parameters (composite_batch_last
- * reports which mode ran). */
-enum cmp_batch_mode { CMP_BATCH_PERSISTENT = 0, CMP_BATCH_PER_REQUEST = 1, CMP_BATCH_SHARED = 2 };
+ * reports which mode ran).  MATRIX: one persistent launch over (block of 64
+ * requests, tile of 512 pixels of a raster row); the counts of a tile for
+ * all 64 requests are an int8 matrix-core product of the members' nonzero
+ * flags with the requests' membership, so a tile reads each pool member that
+ * a covering request holds once, with no limit on the covering requests per
+ * pass.  It needs distinct ids within each request, a pool of at most 8192
+ * rasters and 31 * stride + W + 8 < 2^32; a batch that does not qualify runs
+ * in the SHARED mode (and from there maybe PERSISTENT) with the same
+ * parameters. */
+enum cmp_batch_mode {
+  CMP_BATCH_PERSISTENT = 0,
+  CMP_BATCH_PER_REQUEST = 1,
+  CMP_BATCH_SHARED = 2,
+  CMP_BATCH_MATRIX = 3
+};
 
 /* Order of the work queue.  COST: largest items first.  ROWS: by the first
  * raster row an item reads, so that concurrently running items of different
@@ -291,8 +304,9 @@ typedef struct cmp_tune {
   int32_t tile_vecs;      /* persistent mode: 16-pixel vectors per work item
                              (a band of whole crop rows), 64 .. 65536; checked
                              in the shared mode too (its fallback) */
-  int32_t blocks_per_cu;  /* persistent and shared modes: workgroups of 256
-                             per compute unit, 1 .. 16 */
+  int32_t blocks_per_cu;  /* persistent, shared and matrix modes: workgroups
+                             per compute unit, 1 .. 16 (the matrix mode uses
+                             at most 2, all it fits at once) */
   int32_t use_graph;      /* persistent and shared modes: 1 replays a captured
                              hipGraph of [queue reset, kernel]; captured once
                              per mode, grid size and load kind, and reused */
@@ -307,8 +321,8 @@ typedef struct cmp_tune {
   int32_t reserved[1];    /* must be zero */
 } cmp_tune;
 
-/* Fills *t with the defaults (shared, tile_vecs 1024, blocks_per_cu 4,
- * use_graph 1, order ROWS, stream_loads 0, slots 24).  NULL is ignored. */
+/* Fills *t with the defaults (matrix, tile_vecs 1024, blocks_per_cu 4,
+ * use_graph 1, order ROWS, stream_loads 1, slots 24).  NULL is ignored. */
 void composite_default_tune(cmp_tune *t);
 
 /* Runs nreq requests and returns when every output is written.  Every

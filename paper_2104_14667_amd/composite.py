@@ -58,7 +58,7 @@ class cmp_tune(C.Structure):
 CMP_ORDER_COST, CMP_ORDER_ROWS = 0, 1
 
 
-CMP_BATCH_PERSISTENT, CMP_BATCH_PER_REQUEST, CMP_BATCH_SHARED = 0, 1, 2
+CMP_BATCH_PERSISTENT, CMP_BATCH_PER_REQUEST, CMP_BATCH_SHARED, CMP_BATCH_MATRIX = 0, 1, 2, 3
 CMP_OP_ADD, CMP_OP_REMOVE = 0, 1
 
 

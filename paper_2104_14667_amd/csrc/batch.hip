@@ -48,16 +48,24 @@ struct Item {
 struct Header {
   int32_t nitems, nreq;
   int64_t reqs_off, items_off, ids_off;  // byte offsets in the arena
-  int64_t pad[4];
+  int64_t bits_off;                      // matrix mode: M of each request block
+  int64_t pad[3];
 };
 static_assert(sizeof(Header) == 64, "arena header is 64 bytes");
+
+// Output pointers read from the arena are generic; as global-space pointers
+// their stores are global (not flat) stores, which count only against the
+// vector-memory counter.
+typedef __attribute__((address_space(1))) uint32_t gu32_t;
+typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));  // 4-byte aligned
+__device__ __forceinline__ gu32_t *as_global(uint32_t *p) { return (gu32_t *)p; }
 
 // Counts of one 16-pixel vector of a request: pixels (y, x .. x+15) of the
 // pool rasters ids[0..n), written to out[0..valid).
 template <bool NT>
 __device__ __forceinline__ void crop_vector(const uint8_t *__restrict__ base, int64_t stride,
                                             const int32_t *__restrict__ ids, int n, uint32_t off,
-                                            uint32_t *__restrict__ out, int valid) {
+                                            gu32_t *__restrict__ out, int valid) {
   constexpr int U = 8;
   uint32_t cnt[16];
 #pragma unroll
@@ -81,8 +89,12 @@ __device__ __forceinline__ void crop_vector(const uint8_t *__restrict__ base, in
   if (valid == 16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint4 v = make_uint4(cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]);
-      __builtin_memcpy(out + 4 * q, &v, 16);
+      u32x4a4 v;
+      v.x = cnt[4 * q];
+      v.y = cnt[4 * q + 1];
+      v.z = cnt[4 * q + 2];
+      v.w = cnt[4 * q + 3];
+      *(__attribute__((address_space(1))) u32x4a4 *)(out + 4 * q) = v;
     }
   } else {
 #pragma unroll
@@ -114,7 +126,7 @@ __global__ __launch_bounds__(256) void k_batch(const uint8_t *__restrict__ base,
     for (int v = threadIdx.x; v < total; v += blockDim.x) {
       const int row = v / R.nvr, j = v - row * R.nvr;
       const uint32_t off = (uint32_t)(R.y0 + I.row0 + row) * (uint32_t)W + (uint32_t)(R.x0 + 16 * j);
-      uint32_t *out = R.out + (int64_t)(I.row0 + row) * R.pitch + 16 * j;
+      gu32_t *out = as_global(R.out) + (int64_t)(I.row0 + row) * R.pitch + 16 * j;
       crop_vector<NT>(base, stride, ids, R.n, off, out, min(16, R.w - 16 * j));
     }
   }
@@ -384,11 +396,332 @@ __global__ __launch_bounds__(TPB) void k_shared(const uint8_t *__restrict__ base
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int xk = x + 4 * k + q;
-            if (xk < W && xk >= R.x0 && xk < R.x0 + R.w) R.out[row + xk] = c[q];
+            if (xk < W && xk >= R.x0 && xk < R.x0 + R.w) as_global(R.out)[row + xk] = c[q];
           }
         }
       }
       __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- matrix mode
+//
+// The counts of a batch are a product of 0/1 matrices: over the pixels p of a
+// tile, the pool members k and the requests r,
+//   count[p][r] = sum_k F[p][k] * M[k][r],
+// F[p][k] = [raster k is nonzero at p], M[k][r] = [k is one of r's ids].  A
+// workgroup owns 128 pixels of one raster row per wave, and blocks of 64
+// requests at a time: the counts of a wave's pixels for all 64 requests are
+// 128 x 64 int32 accumulators of int8 matrix-core products (8 x 4 blocks of
+// 16 x 16, in registers), so every (member, tile) is read once however many
+// of the tile's covering requests hold it.  Members of the pool are taken in
+// chunks of 32 consecutive ids; a chunk is streamed when one of the tile's
+// covering requests holds one of its members, and only those members are
+// read (the others load one shared cache line whose bytes meet zeros in M).
+//
+// Operands of one 16x16x32 int8 product, per lane l (row or column l % 16,
+// k-group l / 16 of 8 consecutive k):
+//   A: 8 bytes, the flags of members 8*(l/16) .. +7 of the chunk at one
+//      pixel (0x80 for nonzero, i.e. -128, else 0);
+//   B: 8 bytes, 1 where that member belongs to request l % 16 of the group;
+//   D: 4 int32, rows 4*(l/16) .. +3, column l % 16;
+// so D = -128 * count.  The flags come from 8-byte loads of 8 pixels of 8
+// members, transposed in registers (an 8 x 8 byte transpose by byte permutes).
+// M lives in LDS as one byte per (chunk, k-group, request): bit i = member
+// 32*chunk + 8*kgroup + i, laid out [chunk][kgroup][request % 16][request / 16].
+// The product's 64 columns are the tile's covering requests packed in order,
+// and only the groups of 16 columns that hold one are multiplied.
+
+constexpr int kMxReqs = 64;        // requests per block (4 groups of 16 columns)
+constexpr int kMxMaxCount = 8192;  // pool rasters (M of a block: 256 B per chunk of 32)
+
+__host__ __device__ constexpr int64_t mx_chunks(int64_t count) { return (count + 31) / 32; }
+// LDS of k_matrix: M of one request block, the union byte of each (chunk,
+// k-group), the list of chunks to stream.
+__host__ __device__ constexpr int64_t mx_lds_bytes(int64_t count) {
+  return mx_chunks(count) * (256 + 4) + (mx_chunks(count) * 2 + 15) / 16 * 16;
+}
+
+typedef int mx_i32x4 __attribute__((ext_vector_type(4)));
+
+// 0x80 in every byte of w that is nonzero, 0 elsewhere (see nonzero_bytes).
+__device__ __forceinline__ uint32_t nonzero_sign(uint32_t w) {
+  return (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+}
+
+// 4x4 byte transpose: u[c] = (w0[c], w1[c], w2[c], w3[c]).
+__device__ __forceinline__ void transpose4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                           uint32_t &u0, uint32_t &u1, uint32_t &u2, uint32_t &u3) {
+  const uint32_t a = __builtin_amdgcn_perm(w1, w0, 0x05010400u);  // w0[0] w1[0] w0[1] w1[1]
+  const uint32_t b = __builtin_amdgcn_perm(w1, w0, 0x07030602u);  // w0[2] w1[2] w0[3] w1[3]
+  const uint32_t c = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+  const uint32_t d = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+  u0 = __builtin_amdgcn_perm(c, a, 0x05040100u);
+  u1 = __builtin_amdgcn_perm(c, a, 0x07060302u);
+  u2 = __builtin_amdgcn_perm(d, b, 0x05040100u);
+  u3 = __builtin_amdgcn_perm(d, b, 0x07060302u);
+}
+
+// The 8 bits of x as 8 bytes of 0 or 1 (bit i -> byte i): multiplying a
+// nibble by 2^0 + 2^7 + 2^14 + 2^21 puts bit i at 8i with no two partial
+// products meeting.
+__device__ __forceinline__ long spread_bits(uint32_t x) {
+  const uint32_t lo = ((x & 0xfu) * 0x204081u) & 0x01010101u;
+  const uint32_t hi = (((x >> 4) & 0xfu) * 0x204081u) & 0x01010101u;
+  return (long)(((unsigned long)hi << 32) | lo);
+}
+
+// Requests must not repeat an id (M is a set), the pool must hold at most
+// kMxMaxCount rasters, and 31 * stride + W + 8 < 2^32 (per-lane 32-bit
+// offsets from a chunk's first raster).
+template <bool NT, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 8 / WAVES) void k_matrix(const uint8_t *__restrict__ base,
+                                                          int64_t stride, int32_t W, int32_t H,
+                                                          int32_t count,
+                                                          const char *__restrict__ arena,
+                                                          uint32_t *__restrict__ queue) {
+  constexpr int TPB = WAVES * 64, T = WAVES * 128;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int nc = (int)mx_chunks(count);
+  uint32_t *memb = reinterpret_cast<uint32_t *>(lds_raw);  // [nc][4][16] dwords
+  uint32_t *ub = memb + nc * 64;                            // [nc]: union byte per k-group
+  uint16_t *list = reinterpret_cast<uint16_t *>(ub + nc);   // chunks to stream
+  __shared__ int s_item, s_nl;
+  __shared__ unsigned long long s_cov;
+  __shared__ uint32_t s_cmask[16];
+  __shared__ int8_t s_slot[kMxReqs];  // covering requests in order (block-local index)
+
+  const Header *hd = reinterpret_cast<const Header *>(arena);
+  const int nreq = hd->nreq;
+  const ReqDesc *reqs = reinterpret_cast<const ReqDesc *>(arena + hd->reqs_off);
+  const uint4 *bits_all = reinterpret_cast<const uint4 *>(arena + hd->bits_off);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row16 = lane & 15, kg = lane >> 4;
+  const int segs = (W + T - 1) / T;
+  const int ntiles = H * segs;
+  const int nitems = ((nreq + kMxReqs - 1) / kMxReqs) * ntiles;
+  int cur = -1;
+
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (item >= nitems) break;  // the queue counter only grows: every wave exits
+    const int rb = item / ntiles, tile = item - rb * ntiles;
+    if (rb != cur) {  // M of this request block into LDS
+      const uint4 *src = bits_all + (int64_t)rb * nc * 16;
+      uint4 *dst = reinterpret_cast<uint4 *>(memb);
+      for (int q = tid; q < nc * 16; q += TPB) dst[q] = src[q];
+      cur = rb;
+    }
+    const int y = tile / segs;
+    const int xt = (tile - y * segs) * T;
+    const int tw = min(T, W - xt);
+    if (wave == 0) {  // the block's requests whose windows cover the tile
+      const int r = rb * kMxReqs + lane;
+      bool c = false;
+      if (r < nreq) {
+        const ReqDesc &R = reqs[r];
+        c = y >= R.y0 && y < R.y0 + R.h && R.x0 < xt + tw && R.x0 + R.w > xt;
+      }
+      const unsigned long long cov = __ballot(c);
+      if (lane < 16) {  // byte g of s_cmask[n]: request 16g + n covers
+        uint32_t mk = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          if ((cov >> (16 * g + lane)) & 1ull) mk |= 0xffu << (8 * g);
+        s_cmask[lane] = mk;
+      }
+      // product columns: the covering requests packed in order, so that only
+      // ceil(covering / 16) groups of 16 columns are multiplied
+      if (c)
+        s_slot[__builtin_amdgcn_mbcnt_hi((uint32_t)(cov >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)cov, 0u))] = (int8_t)lane;
+      if (lane == 0) s_cov = cov;
+    }
+    __syncthreads();
+    const unsigned long long cov = s_cov;
+    if (cov == 0ull) continue;
+    // members any covering request holds, per (chunk, k-group) byte
+    for (int q = tid; q < nc * 4; q += TPB) {
+      const uint4 *e = reinterpret_cast<const uint4 *>(memb) + q * 4;
+      uint32_t u = 0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint4 d = e[v];
+        u |= (d.x & s_cmask[4 * v]) | (d.y & s_cmask[4 * v + 1]) | (d.z & s_cmask[4 * v + 2]) |
+             (d.w & s_cmask[4 * v + 3]);
+      }
+      u |= u >> 16;
+      u |= u >> 8;
+      reinterpret_cast<uint8_t *>(ub)[q] = (uint8_t)u;
+    }
+    __syncthreads();
+    if (wave == 0) {  // chunks with a member to stream, in id order
+      int nl = 0;
+      for (int c0 = 0; c0 < nc; c0 += 64) {
+        const uint32_t v = c0 + lane < nc ? ub[c0 + lane] : 0u;
+        const unsigned long long mm = __ballot(v != 0u);
+        const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+        if (v) list[nl + before] = (uint16_t)(c0 + lane);
+        nl += __builtin_popcountll(mm);
+      }
+      if (lane == 0) s_nl = nl;
+    }
+    __syncthreads();
+    const int nl = s_nl;
+    const int xw = xt + 128 * wave;
+    if (xw >= W) continue;  // wave-uniform; no barrier until the next item
+    // A role: pixels xw + 8*row16 .. +7 of members 8*kg .. +7 of each chunk.
+    // Lanes past the row end read the row's last byte onwards instead (at
+    // most 7 bytes past the row; the pool has 16 bytes of slack).
+    const uint32_t loff = xw + 8 * row16 < W ? 8u * row16 : (uint32_t)(W - 1 - xw);
+    // byte offsets from the chunk's first raster (32-bit: 31 * stride + W + 8 < 2^32)
+    uint32_t off[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) off[i] = (uint32_t)(8 * kg + i) * (uint32_t)stride + loff;
+    const uint8_t *rowb = base + (uint32_t)y * (uint32_t)W + xw;  // wave-uniform
+    const uint8_t *ub8 = reinterpret_cast<const uint8_t *>(ub);
+    const uint8_t *memb8 = reinterpret_cast<const uint8_t *>(memb);
+    // B and D roles: column row16 of group g is slot 16g + row16; its
+    // request's byte in a (chunk, k-group) row of M is 4 * (r % 16) + r / 16
+    const int ncov = __builtin_popcountll(cov);
+    const int ng = (ncov + 15) >> 4;
+    int rq[4], boff[4];
+    uint32_t vmask[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int sl = 16 * g + row16;
+      rq[g] = sl < ncov ? (int)s_slot[sl] : -1;
+      boff[g] = rq[g] < 0 ? 0 : 4 * (rq[g] & 15) + (rq[g] >> 4);
+      vmask[g] = rq[g] < 0 ? 0u : 0xffu;
+    }
+
+    mx_i32x4 acc[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) acc[j][g] = mx_i32x4{0, 0, 0, 0};
+
+    // member loads of list entry li (past the end: one cached line, unused)
+    auto fetch = [&](int li, uint32_t (&d)[16], int &chunk) {
+      const bool in = li < nl;  // branch-free, so the loads stay ahead of the math
+      const int cl = __builtin_amdgcn_readfirstlane((int)list[min(li, nc - 1)]);
+      const int c = in ? cl : 0;
+      const uint32_t uu = ub8[4 * c + kg];
+      const uint32_t u = in ? uu : 0u;
+      const uint8_t *cb = rowb + (int64_t)c * 32 * stride;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t o = (u >> i) & 1u ? off[i] : loff;
+        u32x2u v;
+        if constexpr (NT) v = __builtin_nontemporal_load((gu32x2u *)(cb + o));
+        else v = *(gu32x2u *)(cb + o);
+        d[2 * i] = v.x;
+        d[2 * i + 1] = v.y;
+      }
+      chunk = in ? c : -1;
+    };
+    auto mma = [&](const uint32_t (&d)[16], int c) {
+      // B role: the four slots' bytes of M, read first so that the
+      // conversion below hides their latency
+      const uint8_t *mrow = memb8 + max(c, 0) * 256 + kg * 64;
+      uint32_t xb[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) xb[g] = mrow[boff[g]];
+      uint32_t f[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) f[k] = nonzero_sign(d[k]);
+      // f[2i + h]: member i, pixels 4h .. 4h+3 -> a[j]: pixel j, members 0..7
+      uint32_t lo[8], hi[8];
+      transpose4(f[0], f[2], f[4], f[6], lo[0], lo[1], lo[2], lo[3]);
+      transpose4(f[8], f[10], f[12], f[14], hi[0], hi[1], hi[2], hi[3]);
+      transpose4(f[1], f[3], f[5], f[7], lo[4], lo[5], lo[6], lo[7]);
+      transpose4(f[9], f[11], f[13], f[15], hi[4], hi[5], hi[6], hi[7]);
+      long a[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j] = (long)(((unsigned long)hi[j] << 32) | lo[j]);
+      // zero for an empty slot and past the list's end, so those products
+      // add nothing; one register pair per group, so the products of all
+      // groups in use issue back to back
+      const uint32_t live = c >= 0 ? 0xffu : 0u;  // wave-uniform
+      long b[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        b[g] = spread_bits(xb[g] & live & vmask[g]);
+        asm volatile("" ::"v"(b[g]));  // built here, not sunk into the branches below
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if (g < ng) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            acc[j][g] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a[j], b[g], acc[j][g], 0, 0, 0);
+        }
+      }
+    };
+    uint32_t da[16], db[16], dc[16];
+    int ca = 0, cb2 = 0, cc = 0;
+    // Three chunk buffers, two chunks' loads in flight while one is
+    // converted and multiplied; the scheduling barriers keep each chunk's
+    // loads issued ahead of the math.  The previous tile's output stores are
+    // retired first: with stores and loads both outstanding, every wait below
+    // would have to be a full one.
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+    fetch(0, da, ca);
+    fetch(1, db, cb2);
+    int li = 0;
+    for (; li + 2 < nl; li += 3) {
+      fetch(li + 2, dc, cc);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(da, ca);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(li + 3, da, ca);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(db, cb2);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(li + 4, db, cb2);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(dc, cc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // the last one or two chunks (products of entries past the end use a
+    // zero B and add nothing)
+    if (li < nl) {
+      mma(da, ca);
+      mma(db, cb2);
+    }
+    // D role: lane (row16 = request column n, kg = row group): pixels
+    // xw + 32*kg + 8i + j in register i of block j
+    const int p0 = xw + 32 * kg;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (rq[g] < 0) continue;
+      const ReqDesc &R = reqs[rb * kMxReqs + rq[g]];
+      gu32_t *o = as_global(R.out) + (int64_t)(y - R.y0) * R.pitch - R.x0;
+      if (p0 >= R.x0 && p0 + 32 <= R.x0 + R.w) {
+        // the whole run inside the window: eight 16-byte stores
+#pragma unroll
+        for (int q = 0; q < 32; q += 4) {
+          u32x4a4 v;
+          v.x = (uint32_t)(-acc[(q + 0) & 7][g][(q + 0) >> 3]) >> 7;
+          v.y = (uint32_t)(-acc[(q + 1) & 7][g][(q + 1) >> 3]) >> 7;
+          v.z = (uint32_t)(-acc[(q + 2) & 7][g][(q + 2) >> 3]) >> 7;
+          v.w = (uint32_t)(-acc[(q + 3) & 7][g][(q + 3) >> 3]) >> 7;
+          *(__attribute__((address_space(1))) u32x4a4 *)(o + p0 + q) = v;
+        }
+      } else {
+        const int lo_x = max(p0, R.x0), hi_x = min(p0 + 32, R.x0 + R.w);
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+          const int p = p0 + q;
+          if (p >= lo_x && p < hi_x) o[p] = (uint32_t)(-acc[q & 7][g][q >> 3]) >> 7;
+        }
+      }
     }
   }
 }
@@ -401,7 +734,7 @@ __global__ __launch_bounds__(256) void k_crop(const uint8_t *__restrict__ base, 
   if (v >= R.h * R.nvr) return;
   const int row = v / R.nvr, j = v - row * R.nvr;
   const uint32_t off = (uint32_t)(R.y0 + row) * (uint32_t)W + (uint32_t)(R.x0 + 16 * j);
-  crop_vector<NT>(base, stride, ids, R.n, off, R.out + (int64_t)row * R.pitch + 16 * j,
+  crop_vector<NT>(base, stride, ids, R.n, off, as_global(R.out) + (int64_t)row * R.pitch + 16 * j,
               min(16, R.w - 16 * j));
 }
 
@@ -471,6 +804,28 @@ hipError_t launch_shared(cmp_pool *p, int grid, bool nt, int S) {
   return hipGetLastError();
 }
 
+// Waves per workgroup of k_matrix (a tile is 128 pixels per wave).
+constexpr int kMxWaves = 4;
+
+// Whether k_matrix can run on this pool (request sets are checked per batch).
+bool matrix_pool_ok(const cmp_pool *p) {
+  return p->count <= kMxMaxCount && 31 * p->stride + p->W + 8 < (int64_t(1) << 32) &&
+         p->max_lds_matrix >= mx_lds_bytes(p->count);
+}
+
+hipError_t launch_matrix(cmp_pool *p, int grid, bool nt) {
+  hipError_t e = cmp::launch_fill(p->d_queue, 0, 4, p->s);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)mx_lds_bytes(p->count);
+  if (nt)
+    k_matrix<true, kMxWaves><<<grid, kMxWaves * 64, lds, p->s>>>(
+        p->base, p->stride, p->W, p->H, (int32_t)p->count, p->d_arena, p->d_queue);
+  else
+    k_matrix<false, kMxWaves><<<grid, kMxWaves * 64, lds, p->s>>>(
+        p->base, p->stride, p->W, p->H, (int32_t)p->count, p->d_arena, p->d_queue);
+  return hipGetLastError();
+}
+
 hipError_t launch_persistent(cmp_pool *p, int grid, bool nt) {
   hipError_t e = cmp::launch_fill(p->d_queue, 0, 4, p->s);
   if (e != hipSuccess) return e;
@@ -488,15 +843,16 @@ extern "C" {
 void composite_default_tune(cmp_tune *t) {
   if (!t) return;
   std::memset(t, 0, sizeof(*t));
-  // measured on 64 requests over a pool of 2048 masks of 2048x2048: shared
-  // mode, 24 requests per pass, 4 workgroups per compute unit; the persistent
-  // fallback's best there is 1024-vector items in row order with cached loads
-  t->mode = CMP_BATCH_SHARED;
+  // measured on 64 requests over a pool of 2048 masks of 2048x2048: matrix
+  // mode with non-temporal loads (two workgroups per compute unit at once);
+  // its fallbacks there are best with 24 requests per pass and 4 workgroups
+  // per compute unit (shared), 1024-vector items in row order (persistent)
+  t->mode = CMP_BATCH_MATRIX;
   t->tile_vecs = 1024;
   t->blocks_per_cu = 4;
   t->use_graph = 1;
   t->order = CMP_ORDER_ROWS;
-  t->stream_loads = 0;
+  t->stream_loads = 1;
   t->slots = 24;
 }
 
@@ -528,6 +884,7 @@ int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count
       break;
     if (hipDeviceGetAttribute(&p->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
       break;
+    p->max_lds_matrix = p->max_lds - 1024;  // the kernel's static LDS
     if (const int S = shared_slots(p)) {
       // allow k_shared its dynamic LDS (beyond the default per-launch limit)
       const int lds = (int)shared_lds_bytes(p->count, S);
@@ -536,6 +893,15 @@ int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count
           hipFuncSetAttribute((const void *)k_shared<false, kShTpb, kShPx>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         p->max_lds = 0;  // shared mode unavailable; batches fall back to persistent
+    }
+    if (p->count <= kMxMaxCount) {
+      const int lds = (int)mx_lds_bytes(p->count);
+      if (lds <= p->max_lds_matrix &&
+          (hipFuncSetAttribute((const void *)k_matrix<true, kMxWaves>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+           hipFuncSetAttribute((const void *)k_matrix<false, kMxWaves>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess))
+        p->max_lds_matrix = 0;  // matrix mode unavailable
     }
     if (hipStreamCreateWithFlags(&p->s, hipStreamNonBlocking) != hipSuccess) break;
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) break;
@@ -572,7 +938,8 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   cmp_tune t;
   composite_default_tune(&t);
   if (tune) t = *tune;
-  if (t.mode != CMP_BATCH_PERSISTENT && t.mode != CMP_BATCH_PER_REQUEST && t.mode != CMP_BATCH_SHARED)
+  if (t.mode != CMP_BATCH_PERSISTENT && t.mode != CMP_BATCH_PER_REQUEST && t.mode != CMP_BATCH_SHARED &&
+      t.mode != CMP_BATCH_MATRIX)
     return CMP_EINVAL;
   if (t.mode != CMP_BATCH_PER_REQUEST &&
       (t.tile_vecs < 64 || t.tile_vecs > 65536 || t.blocks_per_cu < 1 || t.blocks_per_cu > 16 ||
@@ -602,15 +969,16 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
     p->last_mode = t.mode;
     return CMP_OK;
   }
-  // the shared mode needs distinct ids per request and room in LDS; otherwise
-  // the batch runs in the persistent mode with the same parameters
-  int S = 0;
-  if (t.mode == CMP_BATCH_SHARED) {
-    S = shared_slots(p);
-    if (S && t.slots) S = std::min(S, t.slots);
+  // the shared and matrix modes need distinct ids per request (sets); the
+  // matrix mode also a pool it can address, and falls back to the shared
+  // mode; the shared mode needs room in LDS and falls back to the persistent
+  // mode with the same parameters
+  bool sets = false;
+  if (t.mode == CMP_BATCH_SHARED || t.mode == CMP_BATCH_MATRIX) {
     // repeated ids: one bit per pool raster, set and cleared per request
-    std::vector<uint64_t> seen(S ? (size_t)(p->count + 63) / 64 : 0, 0);
-    for (int32_t r = 0; r < nreq && S; ++r) {
+    sets = true;
+    std::vector<uint64_t> seen((size_t)(p->count + 63) / 64, 0);
+    for (int32_t r = 0; r < nreq && sets; ++r) {
       const cmp_request &q = reqs[r];
       int32_t i = 0;
       for (; i < q.n; ++i) {
@@ -619,9 +987,20 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
         if (w & b) break;
         w |= b;
       }
-      if (i < q.n) S = 0;
+      if (i < q.n) sets = false;
       for (int32_t k = 0; k < i; ++k) seen[q.ids[k] >> 6] = 0;
     }
+  }
+  const int64_t mx_segs = (p->W + kMxWaves * 128 - 1) / (kMxWaves * 128);
+  const int64_t mx_blocks = (nreq + kMxReqs - 1) / kMxReqs;
+  const int64_t mx_items = mx_blocks * p->H * mx_segs;
+  if (t.mode == CMP_BATCH_MATRIX &&
+      !(sets && matrix_pool_ok(p) && mx_items + (int64_t)p->cus * 2 < INT32_MAX))
+    t.mode = CMP_BATCH_SHARED;
+  int S = 0;
+  if (t.mode == CMP_BATCH_SHARED) {
+    S = sets ? shared_slots(p) : 0;
+    if (S && t.slots) S = std::min(S, t.slots);
     if (!S) t.mode = CMP_BATCH_PERSISTENT;
   }
   // work items: bands of whole rows of about tile_vecs vectors
@@ -672,7 +1051,10 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   hd.reqs_off = 64;
   hd.items_off = align64(hd.reqs_off + (int64_t)sizeof(ReqDesc) * nreq);
   hd.ids_off = align64(hd.items_off + (int64_t)sizeof(Item) * items.size());
-  const int64_t bytes = hd.ids_off + 4 * total_ids;
+  hd.bits_off = (hd.ids_off + 4 * total_ids + 255) / 256 * 256;
+  const int64_t mx_nc = mx_chunks(p->count);
+  const int64_t bits_bytes = t.mode == CMP_BATCH_MATRIX ? mx_blocks * mx_nc * 256 : 0;
+  const int64_t bytes = hd.bits_off + bits_bytes;
 
   if (hipSetDevice(p->dev) != hipSuccess) {
     p->poisoned = true;
@@ -687,18 +1069,33 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   int32_t *ids = reinterpret_cast<int32_t *>(p->h_arena + hd.ids_off);
   for (int32_t r = 0; r < nreq; ++r)
     if (reqs[r].n) std::memcpy(ids + rd[r].ids_off, reqs[r].ids, 4 * (size_t)reqs[r].n);
+  if (bits_bytes) {
+    // M of each block of 64 requests: byte [chunk][k-group][r % 16][(r % 64) / 16],
+    // bit i = member 32 * chunk + 8 * k-group + i
+    uint8_t *bits = reinterpret_cast<uint8_t *>(p->h_arena + hd.bits_off);
+    std::memset(bits, 0, (size_t)bits_bytes);
+    for (int32_t r = 0; r < nreq; ++r) {
+      uint8_t *blk = bits + (int64_t)(r / kMxReqs) * mx_nc * 256 + ((r % 16) * 4 + (r % kMxReqs) / 16);
+      for (int32_t i = 0; i < reqs[r].n; ++i) {
+        const int32_t id = reqs[r].ids[i];
+        blk[(id >> 5) * 256 + ((id >> 3) & 3) * 64] |= (uint8_t)(1u << (id & 7));
+      }
+    }
+  }
   POOL_TRY(hipMemcpyAsync(p->d_arena, p->h_arena, bytes, hipMemcpyHostToDevice, p->s));
   POOL_TRY(hipEventRecord(p->ev0, p->s));
   if (t.mode != CMP_BATCH_PER_REQUEST) {
-    const bool shared = t.mode == CMP_BATCH_SHARED;
-    const int grid = p->cus * t.blocks_per_cu;
+    const int kind = t.mode == CMP_BATCH_SHARED ? 1 : t.mode == CMP_BATCH_MATRIX ? 2 : 0;
+    // k_matrix fits two workgroups per compute unit at once (registers)
+    const int grid = p->cus * (kind == 2 ? std::min(t.blocks_per_cu, 2) : t.blocks_per_cu);
     auto launch = [&]() {
-      return shared ? launch_shared(p, grid, t.stream_loads != 0, S)
-                    : launch_persistent(p, grid, t.stream_loads != 0);
+      return kind == 1   ? launch_shared(p, grid, t.stream_loads != 0, S)
+             : kind == 2 ? launch_matrix(p, grid, t.stream_loads != 0)
+                         : launch_persistent(p, grid, t.stream_loads != 0);
     };
     if (t.use_graph) {
       // graphs by mode, grid, load kind and (shared mode) slots per pass
-      const int key = ((grid * 2 + t.stream_loads) * 2 + (shared ? 1 : 0)) * 64 + S;
+      const int key = ((grid * 2 + t.stream_loads) * 4 + kind) * 64 + S;
       auto it = p->graphs.find(key);
       if (it == p->graphs.end()) {
         hipGraph_t g = nullptr;
@@ -743,6 +1140,7 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
   p->last_ms = ms;
   p->last_items = t.mode == CMP_BATCH_PERSISTENT ? (int64_t)items.size()
                   : t.mode == CMP_BATCH_SHARED ? (int64_t)p->H * ((p->W + kShTile - 1) / kShTile)
+                  : t.mode == CMP_BATCH_MATRIX ? mx_items
                                                : nreq;
   p->last_mode = t.mode;
   return CMP_OK;

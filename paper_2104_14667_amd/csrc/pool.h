@@ -13,6 +13,7 @@ struct cmp_pool {
   int32_t W = 0, H = 0;
   int cus = 0;
   int max_lds = 0;  // LDS bytes a workgroup may use (0: shared mode unavailable)
+  int max_lds_matrix = 0;  // dynamic LDS k_matrix may use (0: matrix mode unavailable)
   bool poisoned = false;
   hipStream_t s = nullptr;
   char *d_arena = nullptr, *h_arena = nullptr;

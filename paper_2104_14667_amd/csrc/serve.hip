@@ -110,17 +110,18 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
 #pragma unroll
         for (int k = 0; k < 16; ++k) cnt[k] += cmp::lane_px(a.c, k);
       }
-      uint4 *c = reinterpret_cast<uint4 *>(R.comp + off);
+      // global-space pointers (the arena's are generic): global, not flat,
+      // loads and stores
+      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+      __attribute__((address_space(1))) v4u *c = (__attribute__((address_space(1))) v4u *)(R.comp + off);
       uint32_t nv[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        uint4 o = make_uint4(0u, 0u, 0u, 0u);
+        v4u o = {0u, 0u, 0u, 0u};
         if (R.mode != kModeSet) o = c[q];
-        if (R.mode == kModeSub) {
-          o.x -= cnt[4 * q]; o.y -= cnt[4 * q + 1]; o.z -= cnt[4 * q + 2]; o.w -= cnt[4 * q + 3];
-        } else {
-          o.x += cnt[4 * q]; o.y += cnt[4 * q + 1]; o.z += cnt[4 * q + 2]; o.w += cnt[4 * q + 3];
-        }
+        const v4u d = {cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]};
+        if (R.mode == kModeSub) o -= d;
+        else o += d;
         c[q] = o;
         nv[4 * q] = o.x; nv[4 * q + 1] = o.y; nv[4 * q + 2] = o.z; nv[4 * q + 3] = o.w;
       }
@@ -128,7 +129,8 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
         const int64_t row_base = (int64_t)(y - R.vy0) * R.vw;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-          if (x + k >= R.vx0 && x + k < R.vx0 + R.vw) R.stage[row_base + (x + k - R.vx0)] = nv[k];
+          if (x + k >= R.vx0 && x + k < R.vx0 + R.vw)
+            ((__attribute__((address_space(1))) uint32_t *)R.stage)[row_base + (x + k - R.vx0)] = nv[k];
       }
     }
   }

@@ -7,7 +7,9 @@ the caches) and the load hint (non-temporal or cached).  Shared mode: sweeps
 the requests per pass over a tile (fewer use less LDS, so more workgroups fit,
 but re-read members where many requests overlap), the occupancy and the load
 hint; it is skipped when the batch does not qualify (a request repeating an
-id).  Each candidate runs on the actual batch, timed with the library's own
+id).  Matrix mode: sweeps the occupancy (one or two workgroups per compute
+unit) and the load hint, and is skipped when the batch or pool does not
+qualify.  Each candidate runs on the actual batch, timed with the library's own
 event timing, and the fastest is kept.  Results
 are cached per shape class (arch, raster size, request count, typical window
 side and set size, each bucketed to a power of two) in memory and, when a path
@@ -21,8 +23,8 @@ import os
 import time
 from typing import Dict, Optional, Sequence
 
-from .composite import (CMP_BATCH_PERSISTENT, CMP_BATCH_SHARED, CMP_ORDER_COST, CMP_ORDER_ROWS,
-                        Pool, make_tune)
+from .composite import (CMP_BATCH_MATRIX, CMP_BATCH_PERSISTENT, CMP_BATCH_SHARED, CMP_ORDER_COST,
+                        CMP_ORDER_ROWS, Pool, make_tune)
 
 TILE_VECS = (64, 128, 256, 512, 1024, 2048, 4096)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16)
@@ -30,6 +32,7 @@ ORDERS = (CMP_ORDER_COST, CMP_ORDER_ROWS)
 STREAM_LOADS = (0, 1)
 SHARED_SLOTS = (0, 24, 20, 16)
 SHARED_BLOCKS_PER_CU = (2, 3, 4, 6)
+MATRIX_BLOCKS_PER_CU = (1, 2)
 
 _cache: Dict[str, dict] = {}
 
@@ -93,6 +96,12 @@ def autotune(pool: Pool, requests: Sequence[dict], reps: int = 3,
             for sl in STREAM_LOADS:
                 if shared_ok:
                     shared_ok = trial(CMP_BATCH_SHARED, fb["tile_vecs"], bpc, fb["order"], sl, slots)
+    # the matrix mode (its fallback: the shared mode with these parameters)
+    matrix_ok = True
+    for bpc in MATRIX_BLOCKS_PER_CU:
+        for sl in STREAM_LOADS:
+            if matrix_ok:
+                matrix_ok = trial(CMP_BATCH_MATRIX, fb["tile_vecs"], bpc, fb["order"], sl, 0)
     best = dict(best, by_mode=by_mode)
     _cache[key] = best
     if cache_path:

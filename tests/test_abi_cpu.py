@@ -88,8 +88,8 @@ def test_pool_and_batch_argument_checks():
     assert cb.lib.composite_pool_create(C.byref(h), 4096, 2, 4, 4, 8, 64, 0) == cb.CMP_EINVAL
     assert cb.lib.composite_batch_run(None, None, 0, None) == cb.CMP_EINVAL
     t = cb.composite_default_tune()
-    assert (t.mode, t.tile_vecs, t.blocks_per_cu, t.use_graph) == (cb.CMP_BATCH_SHARED, 1024, 4, 1)
-    assert (t.order, t.stream_loads, t.slots) == (cb.CMP_ORDER_ROWS, 0, 24)
+    assert (t.mode, t.tile_vecs, t.blocks_per_cu, t.use_graph) == (cb.CMP_BATCH_MATRIX, 1024, 4, 1)
+    assert (t.order, t.stream_loads, t.slots) == (cb.CMP_ORDER_ROWS, 1, 24)
     assert C.sizeof(cb.cmp_request) == 48 and C.sizeof(cb.cmp_tune) == 32
     cb.lib.composite_pool_free(None)
 

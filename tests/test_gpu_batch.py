@@ -10,8 +10,9 @@ import torch
 
 import oracle
 from paper_2104_14667_amd import synth
-from paper_2104_14667_amd.composite import (CMP_BATCH_PER_REQUEST, CMP_BATCH_PERSISTENT,
-                                            CMP_BATCH_SHARED, CMP_EINVAL, CMP_ORDER_COST,
+from paper_2104_14667_amd.composite import (CMP_BATCH_MATRIX, CMP_BATCH_PER_REQUEST,
+                                            CMP_BATCH_PERSISTENT, CMP_BATCH_SHARED, CMP_EINVAL,
+                                            CMP_ORDER_COST,
                                             CMP_ORDER_ROWS, CompositeError, Pool, make_tune)
 from paper_2104_14667_amd.tune import autotune
 
@@ -181,6 +182,94 @@ def test_shared_mode_falls_back_on_repeated_ids():
             assert np.array_equal(_got(r), e), f"set request {k}"
 
 
+# (P, H, W, requests): one partial tile narrower than a wave's 128 pixels;
+# several tiles per row with a ragged last one; exactly two tiles; three
+# blocks of 64 requests, the last partial; pools ending in a partial chunk of
+# 32 members, and spanning ten chunks
+@pytest.mark.parametrize("P,H,W,nreq", [(37, 45, 77, 16), (23, 6, 2501, 40), (16, 9, 1024, 24),
+                                        (29, 4, 3000, 150), (70, 5, 640, 70), (300, 3, 130, 20),
+                                        (1, 7, 1, 5)])
+@pytest.mark.parametrize("graph,nt,bpc", [(1, 0, 2), (0, 1, 1), (1, 1, 2)])
+def test_matrix_mode_small(P, H, W, nreq, graph, nt, bpc):
+    rng = np.random.default_rng(P * W + nreq + 1)
+    stack = synth.random_members(P + H + 1, P, H, W)
+    reqs = _set_requests(rng, P, H, W, nreq)
+    exp = oracle.batch(stack, reqs)
+    buf = _pool_tensor(stack)
+    say("matrix", P, H, W, nreq, graph, nt, bpc)
+    tune = make_tune(CMP_BATCH_MATRIX, 1024, bpc, graph, CMP_ORDER_ROWS, nt)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        for rep in range(2):                          # the second run replays the graph
+            _outs(reqs, pad=3 * rep)
+            pool.run(reqs, tune)
+            ms, items, mode = pool.last()
+            assert mode == CMP_BATCH_MATRIX
+            assert items == (nreq + 63) // 64 * H * ((W + 511) // 512)
+            for k, (r, e) in enumerate(zip(reqs, exp)):
+                assert np.array_equal(_got(r), e), f"run {rep}, request {k}"
+
+
+def test_matrix_mode_nonzero_values_and_dense_sets():
+    """Members with every byte value (the nonzero test, not a mask), and
+    requests holding every member of a pool of 96 (three full chunks)."""
+    P, H, W = 96, 3, 515
+    rng = np.random.default_rng(5)
+    stack = rng.integers(0, 256, (P, H, W), dtype=np.uint8)
+    stack[:, :, ::3] = 0                              # zeros at known places
+    stack[5] = np.arange(H * W, dtype=np.int64).reshape(H, W) % 256
+    reqs = [dict(ids=list(range(P)), x0=0, y0=0, w=W, h=H),
+            dict(ids=list(range(P - 1, -1, -2)), x0=3, y0=1, w=W - 7, h=2),
+            dict(ids=[5], x0=0, y0=0, w=W, h=H)]
+    exp = oracle.batch(stack, reqs)
+    buf = _pool_tensor(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        _outs(reqs)
+        pool.run(reqs, make_tune(CMP_BATCH_MATRIX, 1024, 1, 1, CMP_ORDER_ROWS, 0))
+        assert pool.last()[2] == CMP_BATCH_MATRIX
+        for k, (r, e) in enumerate(zip(reqs, exp)):
+            assert np.array_equal(_got(r), e), f"request {k}"
+
+
+def test_matrix_mode_falls_back():
+    """Repeated ids run in the persistent mode; a stride the matrix mode
+    cannot address runs in the shared mode; both exact."""
+    stack, reqs = _small_case(12)                     # has a request with ids [5, 5, 5]
+    P, H, W = stack.shape
+    buf = _pool_tensor(stack)
+    tune = make_tune(CMP_BATCH_MATRIX, 256, 2, 1)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        _outs(reqs)
+        pool.run(reqs, tune)
+        assert pool.last()[2] == CMP_BATCH_PERSISTENT
+        for k, (r, e) in enumerate(zip(reqs, oracle.batch(stack, reqs))):
+            assert np.array_equal(_got(r), e), f"request {k}"
+    # one raster with a stride of 2^28 bytes: 31 strides exceed 32-bit offsets
+    one = stack[:1]
+    reqs1 = [dict(ids=[0], x0=0, y0=0, w=W, h=H), dict(ids=[], x0=2, y0=3, w=5, h=4)]
+    buf1 = _pool_tensor(one)
+    with Pool(buf1, 1, W, H, 1 << 28, buf1.numel()) as pool:
+        _outs(reqs1)
+        pool.run(reqs1, tune)
+        assert pool.last()[2] == CMP_BATCH_SHARED
+        for k, (r, e) in enumerate(zip(reqs1, oracle.batch(one, reqs1))):
+            assert np.array_equal(_got(r), e), f"request {k}"
+
+
+def test_matrix_mode_pool_above_limit_runs_shared():
+    P, H, W = 8193, 2, 9
+    stack = synth.random_members(77, P, H, W)
+    rng = np.random.default_rng(3)
+    reqs = [dict(ids=rng.choice(P, 40, replace=False).tolist(), x0=1, y0=0, w=7, h=2),
+            dict(ids=[P - 1, 0], x0=0, y0=1, w=W, h=1)]
+    buf = _pool_tensor(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        _outs(reqs)
+        pool.run(reqs, make_tune(CMP_BATCH_MATRIX, 256, 2, 1))
+        assert pool.last()[2] == CMP_BATCH_SHARED
+        for k, (r, e) in enumerate(zip(reqs, oracle.batch(stack, reqs))):
+            assert np.array_equal(_got(r), e), f"request {k}"
+
+
 def _closed_form_counts(levels_sorted, e_crop):
     # count of levels L > e, for members e < L of one shared elevation field
     return len(levels_sorted) - np.searchsorted(levels_sorted, e_crop, side="right")
@@ -209,6 +298,8 @@ def test_full_batched_pool_2048():
                      make_tune(CMP_BATCH_PERSISTENT, per["tile_vecs"], per["blocks_per_cu"], 1,
                                per["order"], per["stream_loads"]),
                      make_tune(CMP_BATCH_SHARED, 1024, 2, 1, CMP_ORDER_ROWS, 1, 16),
+                     make_tune(CMP_BATCH_MATRIX, 1024, 2, 1, CMP_ORDER_ROWS, 0),
+                     make_tune(CMP_BATCH_MATRIX, 1024, 1, 0, CMP_ORDER_ROWS, 1),
                      make_tune(CMP_BATCH_PER_REQUEST)):
             _outs(reqs)
             pool.run(reqs, tune)
