@@ -844,9 +844,12 @@ void composite_default_tune(cmp_tune *t) {
   if (!t) return;
   std::memset(t, 0, sizeof(*t));
   // measured on 64 requests over a pool of 2048 masks of 2048x2048: matrix
-  // mode with non-temporal loads (two workgroups per compute unit at once);
-  // its fallbacks there are best with 24 requests per pass and 4 workgroups
-  // per compute unit (shared), 1024-vector items in row order (persistent)
+  // mode with non-temporal loads (1.73 ms; two workgroups per compute unit
+  // run at once); the shared fallback is best there with the same load hint,
+  // 24 requests per pass and 4 workgroups per compute unit (2.74 ms).  The
+  // persistent fallback (repeated ids) prefers cached loads and 256-vector
+  // items, 2 per compute unit (4.86 ms against 6.26 ms with these values);
+  // the autotuner finds that
   t->mode = CMP_BATCH_MATRIX;
   t->tile_vecs = 1024;
   t->blocks_per_cu = 4;
