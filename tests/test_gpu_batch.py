@@ -255,6 +255,26 @@ def test_matrix_mode_falls_back():
             assert np.array_equal(_got(r), e), f"request {k}"
 
 
+def test_matrix_mode_large_pool_uses_more_than_64k_lds():
+    """8192 rasters, the limit: M of a request block takes 64 KiB of LDS,
+    which with the union bytes and chunk list (65.5 KiB in all) is above the
+    64 KiB a launch gets by default."""
+    P, H, W = 8192, 2, 9
+    stack = synth.random_members(78, P, H, W)
+    rng = np.random.default_rng(4)
+    reqs = [dict(ids=rng.choice(P, int(rng.integers(1, 3000)), replace=False).tolist(),
+                 x0=int(rng.integers(0, 5)), y0=int(rng.integers(0, 2)), w=4, h=1) for _ in range(70)]
+    reqs.append(dict(ids=list(range(P)), x0=0, y0=0, w=W, h=H))
+    exp = oracle.batch(stack, reqs)
+    buf = _pool_tensor(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        _outs(reqs)
+        pool.run(reqs, make_tune(CMP_BATCH_MATRIX, 256, 2, 1, CMP_ORDER_ROWS, 1))
+        assert pool.last()[2] == CMP_BATCH_MATRIX
+        for k, (r, e) in enumerate(zip(reqs, exp)):
+            assert np.array_equal(_got(r), e), f"request {k}"
+
+
 def test_matrix_mode_pool_above_limit_runs_shared():
     P, H, W = 8193, 2, 9
     stack = synth.random_members(77, P, H, W)
