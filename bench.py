@@ -250,10 +250,52 @@ def run_streamed(torch, ens, e, reps, variants):
     return res
 
 
-def run_batched(torch, reps, tuned=True):
+def matrix_unique_bytes(reqs, W, H, P, tile=512):
+    """HBM bytes the matrix batched mode must move: every (member, tile of
+    `tile` pixels of a row) that a request covering the tile holds, read once,
+    plus the outputs written once."""
+    masks = np.zeros((len(reqs), P), bool)
+    for k, q in enumerate(reqs):
+        masks[k, q["ids"]] = True
+    y0 = np.array([q["y0"] for q in reqs]); y1 = y0 + np.array([q["h"] for q in reqs])
+    x0 = np.array([q["x0"] for q in reqs]); x1 = x0 + np.array([q["w"] for q in reqs])
+    reads = 0
+    for xt in range(0, W, tile):
+        tw = min(tile, W - xt)
+        xcov = (x0 < xt + tw) & (x1 > xt)
+        for y in range(H):
+            cov = xcov & (y0 <= y) & (y1 > y)
+            if cov.any():
+                reads += int(masks[cov].any(0).sum()) * tw
+    return reads, 4 * sum(q["w"] * q["h"] for q in reqs)
+
+
+def batched_cpu_baseline(e, lv, reqs, seconds):
+    """The oracle on the smallest requests of the batch (members generated
+    untimed), until about `seconds` of oracle time."""
+    import oracle
+    from paper_2104_14667_amd import synth
+    done, pxm, t = 0, 0, 0.0
+    for r in sorted(reqs, key=lambda q: len(q["ids"]) * q["w"] * q["h"]):
+        ec = e[r["y0"]:r["y0"] + r["h"], r["x0"]:r["x0"] + r["w"]]
+        crops = [synth.mask(ec, int(lv[i])) for i in r["ids"]]
+        t0 = time.perf_counter()
+        oracle.accumulate(crops, shape=ec.shape, outputs=("count",))
+        t += time.perf_counter() - t0
+        done += 1
+        pxm += len(r["ids"]) * r["w"] * r["h"]
+        if t >= seconds:
+            break
+    return {"value": round(pxm / t / 1e9, 4), "unit": "Gpixel-members/s", "cores": 1, "kind": "oracle",
+            "requests_per_s": round(done / t, 2),
+            "sample": f"the {done} smallest of {len(reqs)} requests ({pxm / 1e9:.3f} G px-members, "
+                      f"{t:.1f} s), numpy single thread, members generated untimed"}
+
+
+def run_batched(torch, reps, tuned=True, cpu_seconds=3.0):
     """Batched crop requests: pool of 2048 masks of 2048x2048, 64 requests;
-    one autotuned launch (graph replay; shared or persistent mode) against the
-    best persistent launch and 64 plain launches."""
+    one autotuned launch (graph replay; matrix, shared or persistent mode)
+    against the best launch of each other mode and 64 plain launches."""
     from paper_2104_14667_amd import synth
     from paper_2104_14667_amd.composite import (CMP_BATCH_MATRIX, CMP_BATCH_PER_REQUEST,
                                                 CMP_BATCH_PERSISTENT, CMP_BATCH_SHARED, Pool,
@@ -339,12 +381,59 @@ def run_batched(torch, reps, tuned=True):
         # requests that want it, so this exceeds the HBM rate
         out["algorithmic_GBps_best"] = round((pxm + 4 * sum(r["w"] * r["h"] for r in reqs))
                                              / (p * 1e-3) / 1e9, 1)
+        if out["best_graph"]["mode"] == "matrix":
+            reads, writes = matrix_unique_bytes(reqs, wl.W, wl.H, wl.pool)
+            ach = (reads + writes) / (p * 1e-3) / 1e9
+            out["roofline"] = {"bound": "hbm", "kernel": "k_matrix", "unit": "GB/s", "peak": 8000.0,
+                               "achieved": round(ach, 1), "frac": round(ach / 8000.0, 4),
+                               "unique_bytes": reads + writes,
+                               "unique_bytes_note": "each (member, 512-pixel row tile) a covering "
+                                                    "request holds, read once, plus the outputs"}
+    if cpu_seconds > 0:
+        log("  batched cpu baseline")
+        out["cpu_baseline"] = batched_cpu_baseline(e, lv, reqs, cpu_seconds)
     del buf, reqs
     torch.cuda.empty_cache()
     return out
 
 
-def run_served(torch, duration_s, spill_duration_s):
+def served_cpu_baseline(e, lv, sched, seconds, max_members=320):
+    """The oracle replaying session 0's first requests in order (each
+    viewport recomputed from the members held), members generated untimed.
+    The number of requests doubles until the replay takes about `seconds`."""
+    import oracle
+    from paper_2104_14667_amd import synth
+    ops = [{"op": r["op"], "ids": [int(i) for i in r["ids"]], "vx0": int(r["vx0"]),
+            "vy0": int(r["vy0"]), "vw": int(r["vw"]), "vh": int(r["vh"])}
+           for r in sched if r["sid"] == 0]
+    cache = {}
+
+    class Members:  # the pool rasters the requests name, generated before the replay
+        shape = e.shape
+
+        def __getitem__(self, i):
+            return cache[i]
+
+    k = 1
+    while True:
+        for q in ops[:k]:
+            for i in q["ids"]:
+                if i not in cache:
+                    cache[i] = synth.depth(e, int(lv[i]))
+        t0 = time.perf_counter()
+        oracle.replay_session(Members(), ops[:k])
+        t = time.perf_counter() - t0
+        if t >= seconds or k >= len(ops) or len(cache) >= max_members:
+            break
+        k = min(len(ops), 2 * k)
+    view = f"{ops[0]['vw']}x{ops[0]['vh']}" if ops else "-"
+    return {"value": round(k / t, 2), "unit": "requests/s", "cores": 1, "kind": "oracle",
+            "sample": f"session 0's first {k} requests replayed in order ({t:.1f} s), each {view} "
+                      f"viewport recomputed from the members held; numpy single thread, members "
+                      f"generated untimed"}
+
+
+def run_served(torch, duration_s, spill_duration_s, cpu_seconds=3.0):
     """Served sessions: open-loop Poisson arrivals at 2000 req/s over 256
     sessions of 4096x4096 u32 count, pool of 1024 depth maps; each request adds
     or removes 1-32 members and reads a 1024x1024 viewport.  Continuous
@@ -396,7 +485,7 @@ def run_served(torch, duration_s, spill_duration_s):
             checked += 1
         return ok, checked
 
-    def one(name, sched, held=None, **opts):
+    def one(name, sched, held=None, roofline=False, **opts):
         """Replays sched; held: per-session member lists loaded untimed first."""
         log(f"  {name}")
         with Server(pool, **opts) as srv:
@@ -426,6 +515,19 @@ def run_served(torch, duration_s, spill_duration_s):
                      "device_ms_per_request": round(st["device_ms"] / max(1, st["requests"]), 4),
                      "gpx_member_per_s": round(pxm / wall / 1e9, 1),
                      "exact": exact, "sessions_checked": checked}
+        if roofline and st["device_ms"] > 0:
+            # HBM bytes the step kernels must move per request: its members
+            # read, the session composite read and written (only written by a
+            # session's first request, which sets it), the viewport staged
+            seen, byts = set(), 0
+            for r in sched:
+                first = r["sid"] not in seen
+                seen.add(r["sid"])
+                byts += len(r["ids"]) * plane + (4 if first else 8) * plane + 4 * r["vw"] * r["vh"]
+            ach = byts / (st["device_ms"] * 1e-3) / 1e9
+            out[name]["roofline"] = {"bound": "hbm", "kernel": "k_serve", "unit": "GB/s", "peak": 8000.0,
+                                     "achieved": round(ach, 1), "frac": round(ach / 8000.0, 4),
+                                     "bytes_per_request": round(byts / len(sched))}
 
 
     def window(start_s, dur_s):
@@ -445,7 +547,7 @@ def run_served(torch, duration_s, spill_duration_s):
         return [dict(r, t=r["t"] - t0) for r in full[k0:k1]], held
 
     with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
-        one("continuous_batching", sched, max_batch=64, overlap=1,
+        one("continuous_batching", sched, roofline=True, max_batch=64, overlap=1,
             hbm_budget_bytes=wl.sessions * plane * 4)
         one("unbatched_fifo", sched, max_batch=1, overlap=0,
             hbm_budget_bytes=wl.sessions * plane * 4)
@@ -464,6 +566,9 @@ def run_served(torch, duration_s, spill_duration_s):
                         remat_max_members=remat)
     del buf
     torch.cuda.empty_cache()
+    if cpu_seconds > 0:
+        log("  served cpu baseline")
+        out["cpu_baseline"] = served_cpu_baseline(e, lv, sched, cpu_seconds)
     return out
 
 
@@ -673,10 +778,12 @@ def main():
                 "dual_buffer_linear": dict(nbuf=2, chunk_depth=8)})}
     if not args.no_batched:
         log("batched", synth.BATCHED.name)
-        out["batched"] = run_batched(torch, args.stream_reps + 2, not args.no_autotune)
+        out["batched"] = run_batched(torch, args.stream_reps + 2, not args.no_autotune,
+                                     min(3.0, args.cpu_seconds))
     if args.served_seconds > 0:
         log("served", synth.SERVED.name)
-        out["served"] = run_served(torch, args.served_seconds, args.spill_seconds)
+        out["served"] = run_served(torch, args.served_seconds, args.spill_seconds,
+                                   min(3.0, args.cpu_seconds))
     log("plain small")
     out["plain_small"] = run_plain_small(torch)
     log("cpu baseline")
