@@ -122,7 +122,8 @@ def run_resident(torch, ens, e, steps, warmup):
         launches, kms = c.kernel_stats(reset=True)
         exact = verify(c, ens, e, steps + warmup)
         hist = overlap_histogram(c, ens, steps + warmup)
-    ceiling = same_traffic_ceiling(torch, dev)
+    n, H, W = dev.shape
+    ceiling = same_traffic_ceiling(torch, dev.data_ptr(), H * W, n, H * W)
     del dev, ptrs
     torch.cuda.empty_cache()
     return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact, ceiling=ceiling,
@@ -158,24 +159,24 @@ def cpu_model() -> str:
     return platform.processor() or platform.machine()
 
 
-def same_traffic_ceiling(torch, dev):
-    """Best time of the same-traffic reference kernel (libceiling.so) on the
-    resident members: read + composite read-modify-write, and read only."""
+def same_traffic_ceiling(torch, ptr, stride, n, npix, modes=((1, "rmw_ms"), (0, "read_only_ms"))):
+    """Best time of the same-traffic reference kernel (libceiling.so) over n
+    device rasters at ptr + i * stride of npix bytes: member reads plus, by
+    mode, the 9 B/px count+sum+max read-modify-write (1), a 4 B/px count
+    read-modify-write (2), or reads only (0)."""
     import ctypes as C
     lib = C.CDLL(os.path.join(ROOT, "paper_2104_14667_amd", "libceiling.so"))
     lib.traffic_ceiling.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_float)]
-    n, H, W = dev.shape
-    npix = H * W
     cnt = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
     sm = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
     mx = torch.zeros(npix, dtype=torch.uint8, device="cuda:0")
     torch.cuda.synchronize()
     out = {}
-    for rmw, name in ((1, "rmw_ms"), (0, "read_only_ms")):
+    for rmw, name in modes:
         ms = C.c_float()
-        rc = lib.traffic_ceiling(dev.data_ptr(), npix, n, npix, cnt.data_ptr(), sm.data_ptr(),
+        rc = lib.traffic_ceiling(ptr, stride, n, npix, cnt.data_ptr(), sm.data_ptr(),
                                  mx.data_ptr(), rmw, 6, torch.cuda.current_stream().cuda_stream,
                                  C.byref(ms))
         if rc != 0:
@@ -528,6 +529,16 @@ def run_served(torch, duration_s, spill_duration_s, cpu_seconds=3.0):
             out[name]["roofline"] = {"bound": "hbm", "kernel": "k_serve", "unit": "GB/s", "peak": 8000.0,
                                      "achieved": round(ach, 1), "frac": round(ach / 8000.0, 4),
                                      "bytes_per_request": round(byts / len(sched))}
+            # the same-traffic reference kernel on a request of the mean size:
+            # that many pool members read and one 4 B/px count composite
+            # read-modify-write over the raster
+            k = max(1, round(sum(len(r["ids"]) for r in sched) / len(sched)))
+            ref = same_traffic_ceiling(torch, buf.data_ptr(), plane, k, plane, ((2, "ms"),))["ms"]
+            att = (k + 8) * plane / (ref * 1e-3) / 1e9
+            out[name]["roofline"]["attainable"] = {
+                "kernel": f"same-traffic reference: {k} NT 16-byte member streams + 4 B/px count "
+                          f"read-modify-write over {wl.W}x{wl.H}, trivial arithmetic",
+                "GBps": round(att, 1), "frac": round(ach / att, 4)}
 
 
     def window(start_s, dur_s):

@@ -6,7 +6,8 @@
 // trivial arithmetic in place of the compositing: n member streams read with
 // non-temporal 16-byte loads, 16 pixels per thread, then (rmw = 1) 9 bytes per
 // pixel of composite read and written (uint32 count, uint32 sum, uint8 max),
-// or nothing (rmw = 0, the read-only rate).  Its rate is what the memory
+// (rmw = 2) 4 bytes per pixel (uint32 count only, the served sessions'
+// composite), or nothing (rmw = 0, the read-only rate).  Its rate is what the memory
 // system sustains for that access pattern, the attainable bound for the
 // compositing kernel on the same data.
 #include <hip/hip_runtime.h>
@@ -17,7 +18,7 @@ namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) u32x4 gu32x4;
 
-template <bool RMW>
+template <int RMW>
 __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem, int64_t stride, int n,
                                                  uint32_t *__restrict__ cnt, uint32_t *__restrict__ sum,
                                                  uint8_t *__restrict__ mx, uint32_t nvec, uint32_t never) {
@@ -47,7 +48,13 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
   uint4 *c = reinterpret_cast<uint4 *>(cnt + t * 16u);
   uint4 *s = reinterpret_cast<uint4 *>(sum + t * 16u);
   uint4 *x = reinterpret_cast<uint4 *>(mx + t * 16u);
-  if (RMW) {
+  if (RMW == 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 o = c[q];
+      c[q] = make_uint4(o.x + a0, o.y + a1, o.z + a2, o.w + a3);
+    }
+  } else if (RMW == 1) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint4 o = c[q], p = s[q];
@@ -69,11 +76,12 @@ extern "C" {
 // rasters at members + i * stride (npix bytes each, npix a multiple of 16,
 // 16-byte aligned) and composite buffers count, sum (npix uint32 each) and
 // max (npix bytes), and returns in *best_ms the fastest of the runs after the
-// first.  Returns 0 or a hipError_t.  The composite buffers are overwritten.
+// first.  rmw: 0, 1 or 2 as above.  Returns 0 or a hipError_t.  The
+// composite buffers are overwritten.
 int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t npix, void *count,
                     void *sum, void *max, int32_t rmw, int32_t reps, void *stream, float *best_ms) {
   if (!members || !count || !sum || !max || !best_ms || n < 1 || reps < 2 || npix < 16 ||
-      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix)
+      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 2)
     return (int)hipErrorInvalidValue;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint32_t nvec = (uint32_t)(npix / 16);
@@ -90,12 +98,15 @@ int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t n
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
     e = hipEventRecord(e0, s);
     if (e != hipSuccess) break;
-    if (rmw)
-      k_ceiling<true><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
-                                           (uint8_t *)max, nvec, 0x9e3779b9u);
+    if (rmw == 2)
+      k_ceiling<2><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
+                                        (uint8_t *)max, nvec, 0x9e3779b9u);
+    else if (rmw == 1)
+      k_ceiling<1><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
+                                        (uint8_t *)max, nvec, 0x9e3779b9u);
     else
-      k_ceiling<false><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
-                                            (uint8_t *)max, nvec, 0x9e3779b9u);
+      k_ceiling<0><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
+                                        (uint8_t *)max, nvec, 0x9e3779b9u);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);

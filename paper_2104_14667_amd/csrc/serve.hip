@@ -91,6 +91,19 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       const int row = v / nvr, j = v - row * nvr;
       const int y = I.row0 + row, x = 16 * j;
       const uint32_t off = (uint32_t)y * (uint32_t)W + (uint32_t)x;
+      // global-space pointers (the arena's are generic): global, not flat,
+      // loads and stores
+      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+      __attribute__((address_space(1))) v4u *c = (__attribute__((address_space(1))) v4u *)(R.comp + off);
+      // the old composite is requested first, so that its latency overlaps
+      // the member loads instead of trailing them
+      v4u o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = v4u{0u, 0u, 0u, 0u};
+      if (R.mode != kModeSet) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = c[q];
+      }
       uint32_t cnt[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) cnt[k] = 0u;
@@ -99,31 +112,25 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
         cmp::Acc<cmp::kCount> a;
         a.zero();
         int i = g0;
-        for (; i + 4 <= g1; i += 4) {
-          uint4 xs[4];
+        for (; i + 8 <= g1; i += 8) {
+          uint4 xs[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
+          for (int u = 0; u < 8; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) a.fold(xs[u]);
+          for (int u = 0; u < 8; ++u) a.fold(xs[u]);
         }
         for (; i < g1; ++i) a.fold(cmp::ld16(base + (int64_t)ids[i] * stride, off));
 #pragma unroll
         for (int k = 0; k < 16; ++k) cnt[k] += cmp::lane_px(a.c, k);
       }
-      // global-space pointers (the arena's are generic): global, not flat,
-      // loads and stores
-      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-      __attribute__((address_space(1))) v4u *c = (__attribute__((address_space(1))) v4u *)(R.comp + off);
       uint32_t nv[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        v4u o = {0u, 0u, 0u, 0u};
-        if (R.mode != kModeSet) o = c[q];
         const v4u d = {cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]};
-        if (R.mode == kModeSub) o -= d;
-        else o += d;
-        c[q] = o;
-        nv[4 * q] = o.x; nv[4 * q + 1] = o.y; nv[4 * q + 2] = o.z; nv[4 * q + 3] = o.w;
+        if (R.mode == kModeSub) o[q] -= d;
+        else o[q] += d;
+        c[q] = o[q];
+        nv[4 * q] = o[q].x; nv[4 * q + 1] = o[q].y; nv[4 * q + 2] = o[q].z; nv[4 * q + 3] = o[q].w;
       }
       if (y >= R.vy0 && y < R.vy0 + R.vh && x + 16 > R.vx0 && x < R.vx0 + R.vw) {
         const int64_t row_base = (int64_t)(y - R.vy0) * R.vw;
