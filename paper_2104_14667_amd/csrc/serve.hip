@@ -112,12 +112,19 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
         cmp::Acc<cmp::kCount> a;
         a.zero();
         int i = g0;
-        for (; i + 8 <= g1; i += 8) {
-          uint4 xs[8];
+        for (; i + 16 <= g1; i += 16) {
+          uint4 xs[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
+          for (int u = 0; u < 16; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
 #pragma unroll
-          for (int u = 0; u < 8; ++u) a.fold(xs[u]);
+          for (int u = 0; u < 16; ++u) a.fold(xs[u]);
+        }
+        for (; i + 4 <= g1; i += 4) {
+          uint4 xs[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a.fold(xs[u]);
         }
         for (; i < g1; ++i) a.fold(cmp::ld16(base + (int64_t)ids[i] * stride, off));
 #pragma unroll
