@@ -77,8 +77,11 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
   const int32_t *ids_all = reinterpret_cast<const int32_t *>(arena + hd->ids_off);
   const int nvr = W >> 4;
   __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+  for (int pass = 0;; ++pass) {
+    // persistent grid: items from the queue; otherwise (queue NULL) one item
+    // per workgroup
+    if (threadIdx.x == 0)
+      s_item = queue ? (int)atomicAdd(queue, 1u) : pass == 0 ? (int)blockIdx.x : nitems;
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
@@ -419,13 +422,15 @@ void worker_body(cmp_server *s) {
       const std::vector<int32_t> &v = rd[k].mode == kModeSet ? rebuilt[k] : step[k].ids;
       if (!v.empty()) std::memcpy(h + hd.ids_off + 4 * (int64_t)rd[k].ids_off, v.data(), 4 * v.size());
     }
-    const int grid = s->pool->cus * s->o.blocks_per_cu;
+    // blocks_per_cu 0: one workgroup per item, no queue
+    const bool persistent = s->o.blocks_per_cu > 0;
+    const int grid = persistent ? s->pool->cus * s->o.blocks_per_cu : (int)items.size();
     e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
-    if (e == hipSuccess) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
+    if (e == hipSuccess && persistent) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
     if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);
-    if (e == hipSuccess) {
+    if (e == hipSuccess && grid > 0) {
       k_serve<<<grid, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half],
-                                          s->d_queue);
+                                          persistent ? s->d_queue : nullptr);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(s->ev_k1[half], s->comp);
@@ -509,7 +514,7 @@ void composite_default_server_opts(cmp_server_opts *o) {
   // items with 2 workgroups per CU take 0.091 ms of device time per request,
   // 1024 with 8 take 0.140 ms
   o->tile_vecs = 256;
-  o->blocks_per_cu = 2;
+  o->blocks_per_cu = 0;
   o->overlap = 1;
   o->remat_max_members = 2048;
 }
@@ -526,7 +531,7 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
   if (pool->W % 16) return CMP_EUNSUPPORTED;
   const int64_t comp_bytes = (int64_t)pool->W * pool->H * 4;
   if (o.max_batch < 1 || o.max_batch > 4096 || o.max_sessions < 1 || o.max_view_pixels < 1 ||
-      o.tile_vecs < 64 || o.tile_vecs > 65536 || o.blocks_per_cu < 1 || o.blocks_per_cu > 16 ||
+      o.tile_vecs < 64 || o.tile_vecs > 65536 || o.blocks_per_cu < 0 || o.blocks_per_cu > 16 ||
       (o.overlap != 0 && o.overlap != 1) || o.remat_max_members < 0 || o.remat_max_members > 65535)
     return CMP_EINVAL;
   // a step must fit in the slab: at least max_batch resident composites

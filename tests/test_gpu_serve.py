@@ -58,18 +58,19 @@ def _check_alone(wl, stack, sched, outs):
 
 # remat: 0 copies every evicted non-empty composite to host memory and back, 65535
 # drops and rebuilds every one, 4 drops sessions of at most 4 members only
-@pytest.mark.parametrize("max_batch,overlap,budget_slots,remat", [
-    (1, 0, 8, 0), (4, 1, 4, 0), (64, 1, 64, 512), (3, 0, 3, 65535), (8, 1, 10, 4),
-    (4, 1, 4, 512), (1, 0, 3, 4)])
-def test_mix_equals_alone(max_batch, overlap, budget_slots, remat):
+# bpc: persistent workgroups per CU, or 0 for one workgroup per work item
+@pytest.mark.parametrize("max_batch,overlap,budget_slots,remat,bpc", [
+    (1, 0, 8, 0, 2), (4, 1, 4, 0, 2), (64, 1, 64, 512, 2), (3, 0, 3, 65535, 2), (8, 1, 10, 4, 2),
+    (4, 1, 4, 512, 2), (1, 0, 3, 4, 2), (64, 1, 64, 512, 0), (4, 1, 4, 65535, 0)])
+def test_mix_equals_alone(max_batch, overlap, budget_slots, remat, bpc):
     wl, stack, sched = _small(seed=max_batch + 10 * overlap + remat % 7)
     P, H, W = stack.shape
-    say("serve mix", max_batch, overlap, budget_slots, remat)
+    say("serve mix", max_batch, overlap, budget_slots, remat, bpc)
     buf = _pool(stack)
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=max_batch, overlap=overlap,
                     hbm_budget_bytes=budget_slots * H * W * 4, max_view_pixels=16 * 16,
-                    tile_vecs=64, blocks_per_cu=2, remat_max_members=remat) as srv:
+                    tile_vecs=64, blocks_per_cu=bpc, remat_max_members=remat) as srv:
             sids, outs = _run_mix(srv, wl, sched)
             st = srv.stats()
             assert st["requests"] == len(sched)
