@@ -374,7 +374,9 @@ typedef struct cmp_server_opts {
   int32_t max_view_pixels;  /* largest viewport w*h accepted.  Default 2^20 */
   int32_t tile_vecs;        /* 16-pixel vectors per work item.  Default 256 */
   int32_t blocks_per_cu;    /* persistent workgroups per compute unit, 1 .. 16, or 0
-                               for one workgroup per work item (no queue).
+                               (automatic): one workgroup per work item (no
+                               queue) for steps whose requests average at most
+                               64 members, else 2 persistent per compute unit.
                                Default 0 */
   int32_t overlap;          /* 1: a step may launch while the previous step's
                                viewports are still being copied out; 0: each

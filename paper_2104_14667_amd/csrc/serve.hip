@@ -153,6 +153,9 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
   }
 }
 
+// Mean members per request above which an automatic step runs persistent.
+constexpr int64_t kServeHeavy = 64;
+
 struct Request {
   uint64_t ticket;
   int64_t sid;
@@ -422,9 +425,15 @@ void worker_body(cmp_server *s) {
       const std::vector<int32_t> &v = rd[k].mode == kModeSet ? rebuilt[k] : step[k].ids;
       if (!v.empty()) std::memcpy(h + hd.ids_off + 4 * (int64_t)rd[k].ids_off, v.data(), 4 * v.size());
     }
-    // blocks_per_cu 0: one workgroup per item, no queue
-    const bool persistent = s->o.blocks_per_cu > 0;
-    const int grid = persistent ? s->pool->cus * s->o.blocks_per_cu : (int)items.size();
+    // blocks_per_cu 0 (automatic): steps of small requests (16 members on
+    // average in the served workload) run one workgroup per item, with no
+    // queue, atomic or barrier per item; steps whose requests average more
+    // than kServeHeavy members (rebuilds of evicted sessions, ~300) run a
+    // persistent grid of 2 workgroups per compute unit, whose lower
+    // occupancy interleaves fewer member streams (both measured faster)
+    const bool persistent = s->o.blocks_per_cu > 0 || nids > kServeHeavy * (int64_t)step.size();
+    const int bpc = s->o.blocks_per_cu > 0 ? s->o.blocks_per_cu : 2;
+    const int grid = persistent ? s->pool->cus * bpc : (int)items.size();
     e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
     if (e == hipSuccess && persistent) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
     if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);

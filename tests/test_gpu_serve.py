@@ -119,6 +119,28 @@ def test_submit_validation():
             assert c not in (a, b)
 
 
+@pytest.mark.parametrize("bpc", [0, 3])
+def test_heavy_requests_automatic_launch(bpc):
+    """Requests of 70-120 members: with blocks_per_cu 0 their steps average
+    more than 64 members and run on the persistent grid; both launch forms
+    equal the oracle's replay of each session alone."""
+    wl = synth.ServeWorkload(sessions=3, pool=260, H=40, W=80, sigma=4.0, view=16,
+                             k_lo=70, k_hi=120, seed=21)
+    e = wl.elevation()
+    lv = wl.levels()
+    stack = np.stack([synth.depth(e, int(L)) for L in lv])
+    sched = wl.schedule(24)
+    P, H, W = stack.shape
+    say("serve heavy", bpc)
+    buf = _pool(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=2, overlap=1, hbm_budget_bytes=2 * H * W * 4,
+                    max_view_pixels=16 * 16, tile_vecs=64, blocks_per_cu=bpc) as srv:
+            sids, outs = _run_mix(srv, wl, sched)
+            assert srv.stats()["requests"] == len(sched)
+    _check_alone(wl, stack, sched, outs)
+
+
 def test_replay_small_open_loop():
     wl, stack, sched = _small(seed=5, n=300)
     P, H, W = stack.shape
