@@ -153,8 +153,11 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
   }
 }
 
-// Mean members per request above which an automatic step runs persistent.
+// Mean members per request above which an automatic step runs persistent,
+// and the most work items it launches one workgroup each (a larger step runs
+// persistent too, well inside the launch's grid limits).
 constexpr int64_t kServeHeavy = 64;
+constexpr size_t kServeMaxGrid = size_t(1) << 22;
 
 struct Request {
   uint64_t ticket;
@@ -431,7 +434,8 @@ void worker_body(cmp_server *s) {
     // than kServeHeavy members (rebuilds of evicted sessions, ~300) run a
     // persistent grid of 2 workgroups per compute unit, whose lower
     // occupancy interleaves fewer member streams (both measured faster)
-    const bool persistent = s->o.blocks_per_cu > 0 || nids > kServeHeavy * (int64_t)step.size();
+    const bool persistent = s->o.blocks_per_cu > 0 || nids > kServeHeavy * (int64_t)step.size() ||
+                            items.size() > kServeMaxGrid;
     const int bpc = s->o.blocks_per_cu > 0 ? s->o.blocks_per_cu : 2;
     const int grid = persistent ? s->pool->cus * bpc : (int)items.size();
     e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
@@ -519,9 +523,10 @@ void composite_default_server_opts(cmp_server_opts *o) {
   o->max_sessions = 1024;
   o->max_batch = 64;
   o->max_view_pixels = 1 << 20;
-  // measured on the served workload (256 sessions of 4096x4096): 256-vector
-  // items with 2 workgroups per CU take 0.091 ms of device time per request,
-  // 1024 with 8 take 0.140 ms
+  // measured on the served workload (256 sessions of 4096x4096): one
+  // workgroup per 256-vector item takes 0.082 ms of device time per request
+  // (persistent, 2 per CU: 0.086 ms; 1024-vector items: 0.087 ms); steps of
+  // rebuilds run persistent (automatic choice, blocks_per_cu 0)
   o->tile_vecs = 256;
   o->blocks_per_cu = 0;
   o->overlap = 1;
