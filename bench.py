@@ -124,10 +124,78 @@ def run_resident(torch, ens, e, steps, warmup):
         hist = overlap_histogram(c, ens, steps + warmup)
     n, H, W = dev.shape
     ceiling = same_traffic_ceiling(torch, dev.data_ptr(), H * W, n, H * W)
+    ops = run_context_ops(torch, ens, e, dev)
     del dev, ptrs
     torch.cuda.empty_cache()
     return dict(seconds=t1 - t0, launches=launches, kernel_ms=kms, exact=exact, ceiling=ceiling,
-                histogram=hist)
+                histogram=hist, context_ops=ops)
+
+
+def run_context_ops(torch, ens, e, dev, reps=3):
+    """The single-context operations besides add, on the resident depth
+    workload: clear (a1), removal of half the members with max rebuilt from
+    the retained rest (a6), and reads (a7): the whole count composite to
+    pinned host memory (PCIe), a 1024x1024 window to pinned host memory, and
+    the same window to device memory.  Best of `reps` each; every result is
+    checked against the closed form."""
+    from paper_2104_14667_amd.composite import Composite
+    log("  context operations (clear, remove, read)")
+    n, H, W = dev.shape
+    npix = H * W
+    ptrs = [dev[i] for i in range(n)]
+    ids = list(range(n))
+    half = n // 2
+    lv = np.asarray(ens.levels())
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    out = {"workload": f"depth N={n} x {W}x{H}, count+sum+max (u32, u32, u8), resident, "
+                       f"retained members"}
+    with Composite(W, H, ens.outputs, 32, retain_members=1) as c:
+        ms = min(timed(lambda: (c.clear(), c.sync())) for _ in range(reps))
+        byts = 9 * npix                                    # count, sum, max written
+        out["clear"] = {"ms": round(ms, 4), "bytes": byts, "GBps": round(byts / ms / 1e6, 1)}
+        rm = []
+        for _ in range(reps):
+            c.clear()
+            c.add_device(ptrs, ids)
+            c.sync()
+            rm.append(timed(lambda: (c.remove(None, ids[:half]), c.sync())))
+        # the removed members read with count+sum read-modify-written (16 B/px);
+        # then max cleared (1 B/px) and rebuilt from the retained members
+        # (their bytes, max read-modify-written: 2 B/px)
+        byts = half * npix + 16 * npix + npix + (n - half) * npix + 2 * npix
+        out["remove_half"] = {"ms": round(min(rm), 4), "members_removed": half, "bytes": byts,
+                              "GBps": round(byts / min(rm) / 1e6, 1)}
+        lut = closed_form(lv[half:], ens.kind)
+        exact = all(bool(np.array_equal(c.read(k).astype(np.int64), lut[k][e])) for k in ens.outputs)
+        full = torch.empty((H, W), dtype=torch.int32, pin_memory=True)
+        fn = full.numpy().view(np.uint32)
+        ms = min(timed(lambda: c.read("count", out=fn, pinned=True)) for _ in range(reps))
+        out["read_count_to_pinned_host"] = {"ms": round(ms, 4), "bytes": 4 * npix,
+                                            "GBps": round(4 * npix / ms / 1e6, 1), "bound": "pcie"}
+        exact = exact and bool(np.array_equal(fn.astype(np.int64), lut["count"][e]))
+        v = 1024
+        x0, y0 = (W - v) // 3, (H - v) // 5
+        win = torch.empty((v, v), dtype=torch.int32, pin_memory=True)
+        wn = win.numpy().view(np.uint32)
+        ms = min(timed(lambda: c.read("count", window=(x0, y0, v, v), out=wn, pinned=True))
+                 for _ in range(reps))
+        out["read_window_to_pinned_host"] = {"ms": round(ms, 4), "window": f"{v}x{v}"}
+        exact = exact and bool(np.array_equal(wn.astype(np.int64), lut["count"][e[y0:y0 + v, x0:x0 + v]]))
+        dwin = torch.empty((v, v), dtype=torch.int32, device="cuda:0")
+        ms = min(timed(lambda: c.read_device("count", dwin, window=(x0, y0, v, v))) for _ in range(reps))
+        out["read_window_to_device"] = {"ms": round(ms, 4), "window": f"{v}x{v}"}
+        exact = exact and bool(np.array_equal(dwin.cpu().numpy().view(np.uint32).astype(np.int64),
+                                              lut["count"][e[y0:y0 + v, x0:x0 + v]]))
+        out["exact"] = exact
+        del full, win, dwin
+    return out
 
 
 def overlap_histogram(c, ens, times, reps=10):
@@ -751,6 +819,7 @@ def main():
                    "members": ens.N, "W": ens.W, "H": ens.H, "seed": ens.seed},
         "bit_exact": r["exact"],
         "histogram": r["histogram"],
+        "context_ops": r["context_ops"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
