@@ -290,6 +290,35 @@ def test_full_depth_8192_n128(mode):
         check_closed_form_and_samples(c, ens, e, lv)
 
 
+def test_full_depth_remove_half_and_reads():
+    """The resident depth workload (128 x 8192x8192, count+sum+max) with
+    retained members: removing 64 of them (count and sum decremented, max
+    rebuilt from the 64 kept) leaves the composite of the rest, checked per
+    pixel against the closed form and at sampled pixels against the oracle;
+    windows read to pinned host and to device memory equal the full read."""
+    ens = synth.DEPTH
+    say("full depth remove", ens.name)
+    e = elevation_of(ens)
+    lv = ens.levels()
+    dev = device_members(ens, e, lv)
+    n = len(lv)
+    ids = list(range(n))
+    with Composite(ens.W, ens.H, ens.outputs, ens.count_bits, retain_members=1) as c:
+        c.add_device([dev[i] for i in range(n)], ids)
+        c.remove(None, ids[: n // 2])
+        assert c.members() == n - n // 2
+        check_closed_form_and_samples(c, ens, e, lv[n // 2:])
+        full = c.read("count")
+        x0, y0, v = ens.W - 1024 - 3, 777, 1024
+        win = torch.empty((v, v), dtype=torch.int32, pin_memory=True)
+        c.read("count", window=(x0, y0, v, v), out=win.numpy().view(np.uint32), pinned=True)
+        assert np.array_equal(win.numpy().view(np.uint32), full[y0:y0 + v, x0:x0 + v])
+        dwin = torch.empty((v, v + 5), dtype=torch.int32, device="cuda:0")
+        c.read_device("count", dwin, window=(x0, y0, v, v), pitch_bytes=4 * (v + 5))
+        got = dwin.cpu().numpy().view(np.uint32)[:, :v]
+        assert np.array_equal(got, full[y0:y0 + v, x0:x0 + v])
+
+
 def test_repeated_and_alternating_member_tables():
     """Calls that repeat the previous call's rasters reuse its device table;
     alternating and repeated tables give the oracle's composite."""
