@@ -209,6 +209,34 @@ def test_matrix_mode_small(P, H, W, nreq, graph, nt, bpc):
                 assert np.array_equal(_got(r), e), f"run {rep}, request {k}"
 
 
+def test_matrix_mode_tile_edges():
+    """Windows that start, end or sit exactly at the 512-pixel tile edges and
+    one pixel either side of them, single-row windows at the first and last
+    rows, and 65 requests, so that the second block of 64 holds one."""
+    P, H, W = 45, 6, 1536
+    stack = synth.random_members(31, P, H, W)
+    rng = np.random.default_rng(8)
+    edges = [(0, 512), (512, 512), (511, 2), (1023, 2), (1024, 512), (1535, 1), (0, W),
+             (510, 3), (1022, 4), (513, 510)]
+    reqs = []
+    for k in range(65):
+        x0, w = edges[k % len(edges)]
+        y0 = [0, H - 1, 2, 0][k % 4]
+        h = 1 if k % 4 < 2 else H - y0
+        reqs.append(dict(ids=rng.choice(P, int(rng.integers(0, P + 1)), replace=False).tolist(),
+                         x0=x0, y0=y0, w=w, h=h))
+    exp = oracle.batch(stack, reqs)
+    buf = _pool_tensor(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        for bpc, nt in ((1, 0), (2, 1)):
+            say("matrix tile edges", P, H, W, len(reqs), bpc, nt)
+            _outs(reqs, pad=bpc)
+            pool.run(reqs, make_tune(CMP_BATCH_MATRIX, 1024, bpc, 1, CMP_ORDER_ROWS, nt))
+            assert pool.last()[2] == CMP_BATCH_MATRIX
+            for k, (r, e) in enumerate(zip(reqs, exp)):
+                assert np.array_equal(_got(r), e), f"bpc {bpc}, request {k}"
+
+
 def test_matrix_mode_nonzero_values_and_dense_sets():
     """Members with every byte value (the nonzero test, not a mask), and
     requests holding every member of a pool of 96 (three full chunks)."""
