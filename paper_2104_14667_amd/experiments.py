@@ -28,9 +28,18 @@
 * ``h2d-sweep``: the host-to-device copy rate of a plain copy from pinned
   memory as a function of buffer size, 64 KiB to 64 MiB in steps of 64 KiB
   (the copy baseline of Section 6, its buffer-size figure).
+* ``subdivide``: spatial subdivision (Section 1) at the ~16k raster size the
+  paper could not run (14848x17664, 262 MB per mask): N masks, taken
+  round-robin from a ring of distinct pinned rasters, composited band by
+  band for several band heights, the whole raster (one band) first, into
+  pageable and then page-locked host outputs.  Each timing covers the whole
+  job: contexts, uploads, compositing and the read-back of every band's count
+  into host memory.  Every result is checked
+  against its closed form (a pixel's count is the number of members whose
+  level exceeds its elevation).
 
 Usage: python -m paper_2104_14667_amd.experiments
-           {repack-sweep,paper-table,kernel-table,h2d-sweep} [--out FILE]
+           {repack-sweep,paper-table,kernel-table,h2d-sweep,subdivide} [--out FILE]
 """
 
 from __future__ import annotations
@@ -230,6 +239,52 @@ def h2d_sweep(lo: int = 64 << 10, hi: int = 64 << 20, step: int = 64 << 10, reps
                         "max": round(float(r.max()), 2)}}
 
 
+def subdivide_table(N: int = 32, ring_size: int = 8, bands=(17664, 8192, 4096, 1024),
+                    W: int = 14848, H: int = 17664, reps: int = 3) -> dict:
+    """Rate of banded compositing (member bytes per second of the whole job)
+    by band height, next to a plain pinned copy of the same rasters."""
+    import torch
+
+    from . import synth
+    from .subdivide import composite_banded
+    t0 = time.perf_counter()
+    e = synth.elevation(16, H, W, 64.0)
+    lv = synth.levels(16, ring_size, 64, 192)
+    ring = [torch.from_numpy(synth.mask(e, int(L))).pin_memory() for L in lv]
+    print(json.dumps({"generated_s": round(time.perf_counter() - t0, 1)}), file=sys.stderr, flush=True)
+    maps = [ring[i % ring_size] for i in range(N)]
+    # closed form of the count: members whose level exceeds the elevation
+    used = np.sort(np.array([int(lv[i % ring_size]) for i in range(N)], dtype=np.int64))
+    below = np.searchsorted(used, np.arange(256), side="right")       # levels <= v
+    expect = (N - below).astype(np.uint32)[e]
+    del e
+    copy_rate = N * W * H / _copy_time(torch, ring, N) / 1e9
+    pinned_out = torch.empty((H, W), dtype=torch.int32, pin_memory=True).numpy().view(np.uint32)
+    rows = []
+    for dst in ("pageable", "pinned"):
+        for band in bands:
+            times = []
+            for r in range(reps):
+                if dst == "pinned":
+                    pinned_out.fill(0xFFFFFFFF)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                out = composite_banded(maps, W, H, band, out={"count": pinned_out} if dst == "pinned"
+                                       else None, pinned=dst == "pinned")
+                times.append(time.perf_counter() - t)
+                if not np.array_equal(out["count"], expect):
+                    raise RuntimeError(f"banded count differs from its closed form (band {band})")
+                del out
+            t = min(times[1:]) if reps > 1 else times[0]
+            rows.append({"output_memory": dst, "band_rows": band, "bands": -(-H // band),
+                         "time_ms": round(t * 1e3, 2), "rate_GBps": round(N * W * H / t / 1e9, 3),
+                         "copy_GBps": round(copy_rate, 3),
+                         "efficiency_pct": round(100 * N * W * H / t / 1e9 / copy_rate, 2),
+                         "exact": True})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"W": W, "H": H, "N": N, "ring": ring_size, "output": "count u32", "rows": rows}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -250,6 +305,10 @@ def main(argv=None):
     d = sub.add_parser("h2d-sweep")
     d.add_argument("--reps", type=int, default=10)
     d.add_argument("--out", default=None)
+    f = sub.add_parser("subdivide")
+    f.add_argument("--n", type=int, default=32)
+    f.add_argument("--bands", default="17664,8192,4096,1024")
+    f.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     if args.cmd == "repack-sweep":
         res = repack_sweep(args.lo, args.hi, args.step, args.reps)
@@ -261,6 +320,9 @@ def main(argv=None):
     elif args.cmd == "h2d-sweep":
         res = h2d_sweep(reps=args.reps)
         print(json.dumps(res["summary"]))
+    elif args.cmd == "subdivide":
+        res = subdivide_table(args.n, bands=tuple(int(x) for x in args.bands.split(",")))
+        print(json.dumps(res))
     else:
         res = paper_table(tuple(int(x) for x in args.ns.split(",")),
                           sizes=tuple(args.sizes.split(",")))
