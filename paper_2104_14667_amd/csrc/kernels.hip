@@ -383,19 +383,39 @@ __global__ __launch_bounds__(256) void k_histogram(const void *__restrict__ coun
     }
     put(cur, run);
   };
-  const uint32_t nv = npix / 8;
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+  // one vector of 8 counts: 16 bytes of u16 or 32 bytes of u32
+  typedef uint4 vec_t[C16 ? 1 : 2];
+  auto load = [&](uint32_t v, vec_t &x) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(count) + (C16 ? 1 : 2) * (size_t)v;
+#pragma unroll
+    for (int h = 0; h < (C16 ? 1 : 2); ++h) x[h] = p[h];
+  };
+  auto count8 = [&](const vec_t &x) {
     if constexpr (C16) {
-      const uint4 x = reinterpret_cast<const uint4 *>(count)[v];
-      const uint32_t c[8] = {x.x & 0xffffu, x.x >> 16, x.y & 0xffffu, x.y >> 16,
-                             x.z & 0xffffu, x.z >> 16, x.w & 0xffffu, x.w >> 16};
+      const uint32_t c[8] = {x[0].x & 0xffffu, x[0].x >> 16, x[0].y & 0xffffu, x[0].y >> 16,
+                             x[0].z & 0xffffu, x[0].z >> 16, x[0].w & 0xffffu, x[0].w >> 16};
       put8(c);
     } else {
-      const uint4 *p = reinterpret_cast<const uint4 *>(count) + 2 * (size_t)v;
-      const uint4 a = p[0], b = p[1];
-      const uint32_t c[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      const uint32_t c[8] = {x[0].x, x[0].y, x[0].z, x[0].w, x[1].x, x[1].y, x[1].z, x[1].w};
       put8(c);
     }
+  };
+  const uint32_t nv = npix / 8;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  // four grid-stride steps at a time, their loads issued before any atomic,
+  // so that each wave keeps several loads in flight (nv < 2^29: no overflow)
+  for (; v + 3 * stride < nv; v += 4 * stride) {
+    vec_t x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load(v + u * stride, x[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) count8(x[u]);
+  }
+  for (; v < nv; v += stride) {
+    vec_t x;
+    load(v, x);
+    count8(x);
   }
   // the last npix % 8 values
   if (blockIdx.x == 0 && threadIdx.x < npix - nv * 8) {
