@@ -409,7 +409,9 @@ void composite_server_free(cmp_server *srv);
  * CMP_ENOMEM when max_sessions are open. */
 int composite_session_open(cmp_server *srv, int64_t *sid_out);
 
-/* Closes a session; CMP_EBUSY while it has unfinished requests. */
+/* Closes a session; CMP_EBUSY while it has unfinished requests.  CMP_EDEVICE
+ * if the device fails while the session's spilled composite is released (the
+ * session is closed and the server is failed). */
 int composite_session_close(cmp_server *srv, int64_t sid);
 
 /* Queues one request: op (cmp_op) of n pool ids, then the viewport

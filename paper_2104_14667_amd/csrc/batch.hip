@@ -747,7 +747,7 @@ int64_t align64(int64_t x) { return (x + 63) / 64 * 64; }
 namespace {
 
 void drop_graphs(cmp_pool *p) {
-  for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
+  for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   p->graphs.clear();
 }
 
@@ -763,8 +763,8 @@ int ensure_arena(cmp_pool *p, int64_t bytes) {
   if (bytes <= p->arena_cap) return CMP_OK;
   if (hipStreamSynchronize(p->s) != hipSuccess) return CMP_EDEVICE;
   drop_graphs(p);
-  hipFree(p->d_arena);
-  if (p->h_arena) hipHostFree(p->h_arena);
+  (void)hipFree(p->d_arena);
+  if (p->h_arena) (void)hipHostFree(p->h_arena);
   p->d_arena = nullptr;
   p->h_arena = nullptr;
   p->arena_cap = 0;
@@ -922,15 +922,15 @@ int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count
 
 void composite_pool_free(cmp_pool *p) {
   if (!p) return;
-  hipSetDevice(p->dev);
-  if (p->s) hipStreamSynchronize(p->s);
+  (void)hipSetDevice(p->dev);
+  if (p->s) (void)hipStreamSynchronize(p->s);
   drop_graphs(p);
-  hipFree(p->d_arena);
-  if (p->h_arena) hipHostFree(p->h_arena);
-  hipFree(p->d_queue);
-  if (p->ev0) hipEventDestroy(p->ev0);
-  if (p->ev1) hipEventDestroy(p->ev1);
-  if (p->s) hipStreamDestroy(p->s);
+  (void)hipFree(p->d_arena);
+  if (p->h_arena) (void)hipHostFree(p->h_arena);
+  (void)hipFree(p->d_queue);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  if (p->s) (void)hipStreamDestroy(p->s);
   delete p;
 }
 
@@ -1107,12 +1107,12 @@ int composite_batch_run(cmp_pool *p, const cmp_request *reqs, int32_t nreq, cons
         const hipError_t le = launch();
         const hipError_t ce = hipStreamEndCapture(p->s, &g);
         if (le != hipSuccess || ce != hipSuccess) {
-          if (g) hipGraphDestroy(g);
+          if (g) (void)hipGraphDestroy(g);
           p->poisoned = true;
           return CMP_EDEVICE;
         }
         const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (ie != hipSuccess) {
           p->poisoned = true;
           return CMP_EDEVICE;

@@ -91,7 +91,7 @@ int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t n
   if (e != hipSuccess) return (int)e;
   e = hipEventCreate(&e1);
   if (e != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return (int)e;
   }
   float best = 0.f;
@@ -114,8 +114,8 @@ int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t n
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e == hipSuccess && r > 0 && (r == 1 || ms < best)) best = ms;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *best_ms = best;
   return (int)e;
 }

@@ -144,7 +144,7 @@ bool dalloc(cmp_ctx *ctx, void **p, size_t bytes) {
 void dfree(cmp_ctx *ctx, void *p) {
   if (!p) return;
   if (ctx->o.dev_free) ctx->o.dev_free(p, ctx->o.alloc_ctx);
-  else hipFree(p);
+  else (void)hipFree(p);
 }
 
 // Range guard: refuse any add that could overflow a stored value.
@@ -156,9 +156,9 @@ bool fits(const cmp_ctx *ctx, int64_t add) {
 }
 
 void free_all(cmp_ctx *ctx) {
-  hipSetDevice(ctx->dev);
-  if (ctx->comp_s) hipStreamSynchronize(ctx->comp_s);
-  if (ctx->copy_s) hipStreamSynchronize(ctx->copy_s);
+  (void)hipSetDevice(ctx->dev);
+  if (ctx->comp_s) (void)hipStreamSynchronize(ctx->comp_s);
+  if (ctx->copy_s) (void)hipStreamSynchronize(ctx->copy_s);
   dfree(ctx, ctx->d_count);
   dfree(ctx, ctx->d_sum);
   dfree(ctx, ctx->d_max);
@@ -170,25 +170,25 @@ void free_all(cmp_ctx *ctx) {
     dfree(ctx, ctx->d_tiled[i]);
     dfree(ctx, ctx->d_slot_tab[i]);
     dfree(ctx, ctx->d_tab[i]);
-    if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
-    if (ctx->h_bounce[i]) hipHostFree(ctx->h_bounce[i]);
-    if (ctx->h_read[i]) hipHostFree(ctx->h_read[i]);
-    if (ctx->ev_bounce[i]) hipEventDestroy(ctx->ev_bounce[i]);
-    if (ctx->ev_read[i]) hipEventDestroy(ctx->ev_read[i]);
-    if (ctx->ev_copied[i]) hipEventDestroy(ctx->ev_copied[i]);
-    if (ctx->ev_free[i]) hipEventDestroy(ctx->ev_free[i]);
-    if (ctx->ev_tab[i]) hipEventDestroy(ctx->ev_tab[i]);
+    if (ctx->h_tab[i]) (void)hipHostFree(ctx->h_tab[i]);
+    if (ctx->h_bounce[i]) (void)hipHostFree(ctx->h_bounce[i]);
+    if (ctx->h_read[i]) (void)hipHostFree(ctx->h_read[i]);
+    if (ctx->ev_bounce[i]) (void)hipEventDestroy(ctx->ev_bounce[i]);
+    if (ctx->ev_read[i]) (void)hipEventDestroy(ctx->ev_read[i]);
+    if (ctx->ev_copied[i]) (void)hipEventDestroy(ctx->ev_copied[i]);
+    if (ctx->ev_free[i]) (void)hipEventDestroy(ctx->ev_free[i]);
+    if (ctx->ev_tab[i]) (void)hipEventDestroy(ctx->ev_tab[i]);
   }
-  if (ctx->ev_host_done) hipEventDestroy(ctx->ev_host_done);
+  if (ctx->ev_host_done) (void)hipEventDestroy(ctx->ev_host_done);
   dfree(ctx, ctx->d_hist);
   dfree(ctx, ctx->d_fp);
-  if (ctx->h_fp) hipHostFree(ctx->h_fp);
+  if (ctx->h_fp) (void)hipHostFree(ctx->h_fp);
   for (auto &t : ctx->timed) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
-  if (ctx->own_copy && ctx->copy_s) hipStreamDestroy(ctx->copy_s);
-  if (ctx->own_comp && ctx->comp_s) hipStreamDestroy(ctx->comp_s);
+  if (ctx->own_copy && ctx->copy_s) (void)hipStreamDestroy(ctx->copy_s);
+  if (ctx->own_comp && ctx->comp_s) (void)hipStreamDestroy(ctx->comp_s);
 }
 
 hipError_t clear_outputs(cmp_ctx *ctx) {
@@ -334,7 +334,7 @@ int upload_table(cmp_ctx *ctx, const uint8_t *const *ptrs, int64_t n, const uint
     ctx->tab_last = -1;
     for (int i = 0; i < 2; ++i) {
       if (ctx->ev_tab[i] && hipEventSynchronize(ctx->ev_tab[i]) != hipSuccess) return CMP_EDEVICE;
-      if (ctx->h_tab[i]) hipHostFree(ctx->h_tab[i]);
+      if (ctx->h_tab[i]) (void)hipHostFree(ctx->h_tab[i]);
       dfree(ctx, ctx->d_tab[i]);
       ctx->h_tab[i] = nullptr;
       ctx->d_tab[i] = nullptr;
@@ -370,7 +370,7 @@ int ensure_bounce(cmp_ctx *ctx) {
   for (int i = 0; i < ctx->o.nbuf; ++i) {
     if (hipHostMalloc((void **)&ctx->h_bounce[i], bytes, hipHostMallocDefault) != hipSuccess) {
       for (int j = 0; j < 2; ++j) {
-        if (ctx->h_bounce[j]) hipHostFree(ctx->h_bounce[j]);
+        if (ctx->h_bounce[j]) (void)hipHostFree(ctx->h_bounce[j]);
         ctx->h_bounce[j] = nullptr;
       }
       return CMP_ENOMEM;
@@ -478,7 +478,7 @@ int begin_fingerprints(cmp_ctx *ctx, int64_t n) {
   if (n > ctx->fp_cap) {
     if (hipStreamSynchronize(ctx->comp_s) != hipSuccess) return CMP_EDEVICE;
     dfree(ctx, ctx->d_fp);
-    if (ctx->h_fp) hipHostFree(ctx->h_fp);
+    if (ctx->h_fp) (void)hipHostFree(ctx->h_fp);
     ctx->d_fp = nullptr;
     ctx->h_fp = nullptr;
     ctx->fp_cap = 0;
@@ -878,7 +878,7 @@ int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0, int32_t
   if (ctx->read_cap < want) {
     for (int i = 0; i < 2; ++i) {
       CMP_TRY(hipEventSynchronize(ctx->ev_read[i]));
-      if (ctx->h_read[i]) hipHostFree(ctx->h_read[i]);
+      if (ctx->h_read[i]) (void)hipHostFree(ctx->h_read[i]);
       ctx->h_read[i] = nullptr;
     }
     ctx->read_cap = 0;

@@ -318,8 +318,8 @@ hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
 void worker_body(cmp_server *s);
 
 void worker_loop(cmp_server *s) {
-  hipSetDevice(s->dev);
-  worker_body(s);
+  if (hipSetDevice(s->dev) != hipSuccess) fail(s, CMP_EDEVICE);
+  else worker_body(s);
   std::lock_guard<std::mutex> lk(s->mu);
   s->worker_done = true;
   s->cv_steps.notify_all();
@@ -477,7 +477,10 @@ void worker_body(cmp_server *s) {
 }
 
 void completer_loop(cmp_server *s) {
-  hipSetDevice(s->dev);
+  if (hipSetDevice(s->dev) != hipSuccess) {
+    fail(s, CMP_EDEVICE);
+    return;
+  }
   for (;;) {
     Step st;
     {
@@ -618,23 +621,23 @@ void composite_server_free(cmp_server *s) {
   else s->worker_done = true;
   s->cv_steps.notify_all();
   if (s->completer.joinable()) s->completer.join();
-  hipSetDevice(s->dev);
-  if (s->comp) hipStreamSynchronize(s->comp);
-  if (s->copy) hipStreamSynchronize(s->copy);
+  (void)hipSetDevice(s->dev);
+  if (s->comp) (void)hipStreamSynchronize(s->comp);
+  if (s->copy) (void)hipStreamSynchronize(s->copy);
   for (auto &kv : s->sessions)
-    if (kv.second.spill) hipHostFree(kv.second.spill);
-  hipFree(s->slab);
-  hipFree(s->d_queue);
+    if (kv.second.spill) (void)hipHostFree(kv.second.spill);
+  (void)hipFree(s->slab);
+  (void)hipFree(s->d_queue);
   for (int i = 0; i < 2; ++i) {
-    if (s->h_arena[i]) hipHostFree(s->h_arena[i]);
-    hipFree(s->d_arena[i]);
-    hipFree(s->stage[i]);
-    if (s->ev_k0[i]) hipEventDestroy(s->ev_k0[i]);
-    if (s->ev_k1[i]) hipEventDestroy(s->ev_k1[i]);
-    if (s->ev_copied[i]) hipEventDestroy(s->ev_copied[i]);
+    if (s->h_arena[i]) (void)hipHostFree(s->h_arena[i]);
+    (void)hipFree(s->d_arena[i]);
+    (void)hipFree(s->stage[i]);
+    if (s->ev_k0[i]) (void)hipEventDestroy(s->ev_k0[i]);
+    if (s->ev_k1[i]) (void)hipEventDestroy(s->ev_k1[i]);
+    if (s->ev_copied[i]) (void)hipEventDestroy(s->ev_copied[i]);
   }
-  if (s->comp) hipStreamDestroy(s->comp);
-  if (s->copy) hipStreamDestroy(s->copy);
+  if (s->comp) (void)hipStreamDestroy(s->comp);
+  if (s->copy) (void)hipStreamDestroy(s->copy);
   delete s;
 }
 
@@ -664,10 +667,14 @@ int composite_session_close(cmp_server *s, int64_t sid) {
   s->open_sessions -= 1;
   lk.unlock();
   if (spill) {
-    // a spill copy into it may still be queued on the compute stream
-    hipSetDevice(s->dev);
-    hipStreamSynchronize(s->comp);
-    hipHostFree(spill);
+    // a spill copy into it may still be queued on the compute stream: free it
+    // only once that stream has drained; if it cannot be drained the buffer
+    // is left allocated (a copy may still write it) and the server fails
+    if (hipSetDevice(s->dev) != hipSuccess || hipStreamSynchronize(s->comp) != hipSuccess) {
+      fail(s, CMP_EDEVICE);
+      return CMP_EDEVICE;
+    }
+    (void)hipHostFree(spill);
   }
   return CMP_OK;
 }
