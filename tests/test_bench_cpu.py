@@ -25,3 +25,24 @@ def test_matrix_unique_bytes_ragged_tile_and_uncovered_rows():
     reqs = [dict(ids=[3, 1], x0=590, y0=0, w=10, h=2)]
     reads, _ = bench.matrix_unique_bytes(reqs, W=600, H=3, P=4)
     assert reads == 2 * 2 * 88
+
+
+def test_traffic_is_reported_only_for_the_profiled_kernel_sources(monkeypatch, tmp_path):
+    """The committed counter summary carries the hash of the kernel sources it
+    was taken on: its traffic figure is used while they are unchanged, and
+    dropped (None) once they differ or the summary is malformed."""
+    kv = {}
+    for line in open(bench.TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.split("#")[0].strip()
+    assert kv["kernel_sources_sha256"] == bench.kernel_source_hash(), "counters are stale"
+    assert bench.measured_traffic() == int(kv["traffic_bytes"])
+    assert int(kv["traffic_bytes"]) == int(kv["traffic_read_bytes"]) + int(kv["traffic_write_bytes"])
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
+    assert bench.measured_traffic() is None
+    monkeypatch.undo()
+    bad = tmp_path / "traffic.txt"
+    bad.write_text(f"kernel_sources_sha256 = {bench.kernel_source_hash()}\n")   # no traffic_bytes
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(bad))
+    assert bench.measured_traffic() is None
