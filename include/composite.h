@@ -48,8 +48,9 @@ enum cmp_status {
   CMP_ENOTMEMBER = -4,   /* remove of an id the working set does not hold    */
   CMP_EUNSUPPORTED = -5, /* valid request this configuration cannot serve    */
   CMP_EDEVICE = -6,      /* no usable GPU, or a HIP call failed (poisoned)   */
-  CMP_EBUSY = -7,        /* resource is in use                               */
-  CMP_ETIMEDOUT = -8     /* a bounded wait expired                           */
+  CMP_EBUSY = -7,        /* resource is in use, or a queue is full           */
+  CMP_ETIMEDOUT = -8,    /* a bounded wait expired                           */
+  CMP_ECANCELED = -9     /* not attempted: an earlier failure ended the call */
 };
 
 /* Output selection bits (composite_init `outputs`, composite_read `which`). */
@@ -118,12 +119,12 @@ typedef struct cmp_opts {
                              each chunk into a pinned bounce buffer of the
                              library (one per staging slot).  Default 0 */
   int32_t host_paced;     /* 0: the copy stream waits on the event of the
-                             kernel that last read a slot (device-side
-                             ordering only).  1: the host waits for that
-                             kernel before queueing the slot's next upload;
-                             the previous chunk's upload is still in flight
-                             then, so the copy engine never idles on a
-                             cross-stream wait.  Default 1 */
+                             kernel that last read a slot: ordering by events
+                             only, no host synchronisation inside the loop
+                             (Section 4, Figure 4).  1: the host waits for that
+                             kernel before queueing the slot's next upload
+                             (the previous chunk's upload is still in flight
+                             then).  Default 0 */
   int32_t verify_members; /* 1: keep a 64-bit fingerprint of every member with
                              its id, so that composite_remove can refuse a
                              raster that is not one that was added under that
@@ -344,8 +345,9 @@ int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items, int32
  * Each session is one user's working set (Figure 1: surfaces are added and
  * removed in real time, and the composite follows) over the rasters of a
  * pool, with its own device-resident uint32 count composite of the pool's
- * W x H.  A request adds or removes pool members and asks for a viewport of
- * the updated composite.  One server thread batches continuously: every step
+ * W x H (uint32, or uint16 with count_bits = 16).  A request adds or removes
+ * pool members and asks for a viewport of the updated composite; the viewport
+ * is always returned as uint32 counts.  One server thread batches continuously: every step
  * takes the oldest queued request of each session (at most max_batch), runs
  * one launch that updates all their composites and writes their viewports to
  * device staging, and queues the copies of the viewports to host memory on a
@@ -360,6 +362,18 @@ int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items, int32
  * composite is dropped and later rebuilt from the session's members (the
  * cost: its member count) or copied to pinned host memory and back (the
  * cost: remat_max_members), see cmp_server_opts.remat_max_members.
+ *
+ * Admission and backpressure.  The budget holds hbm_budget_bytes / (W*H*
+ * count_bits/8) composites resident (the slots).  composite_session_open
+ * admits a session only while the open sessions number fewer than the slots
+ * plus oversubscribe_pct percent of them (and fewer than max_sessions), and
+ * refuses with CMP_ENOMEM otherwise: with the default oversubscribe_pct = 0
+ * every admitted session keeps its composite resident and nothing is ever
+ * evicted; above 0 the sessions beyond the slots live by eviction.
+ * composite_session_submit refuses with CMP_EBUSY while max_queue requests
+ * wait for a step, so a server that cannot keep up sheds load instead of
+ * letting the queue, and the latency, grow without bound.  A refused call
+ * changes nothing.
  */
 typedef struct cmp_server cmp_server;
 
@@ -390,7 +404,17 @@ typedef struct cmp_server_opts {
                                is copied to pinned host memory and back (2 *
                                W*H*4 bytes over PCIe).  0 copies all but empty
                                sessions; at most 65535.  Default 2048 */
-  int32_t reserved[5];      /* must be zero */
+  int32_t count_bits;       /* width of the session composites: 32, or 16
+                               (half the HBM and half the read-modify-write
+                               per request; a request that would take a
+                               session past 65535 members is refused with
+                               CMP_ERANGE).  Default 32 */
+  int32_t oversubscribe_pct; /* sessions admitted beyond the resident slots,
+                               in percent of the slots, >= 0.  Default 0 */
+  int32_t max_queue;        /* requests waiting for a step at most, >= 1;
+                               submit refuses beyond it (CMP_EBUSY).
+                               Default 1024 */
+  int32_t reserved[2];      /* must be zero */
 } cmp_server_opts;
 
 void composite_default_server_opts(cmp_server_opts *opts);
@@ -405,8 +429,10 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
  * ignored. */
 void composite_server_free(cmp_server *srv);
 
-/* Opens a session with an empty working set (all-zero composite).
- * CMP_ENOMEM when max_sessions are open. */
+/* Opens a session with an empty working set (all-zero composite): the
+ * interactive user of Figure 1, whose composite is kept on the device.
+ * CMP_ENOMEM when the HBM budget admits no more sessions (see "Admission and
+ * backpressure" above) or max_sessions are open; nothing changes then. */
 int composite_session_open(cmp_server *srv, int64_t *sid_out);
 
 /* Closes a session; CMP_EBUSY while it has unfinished requests.  CMP_EDEVICE
@@ -419,9 +445,12 @@ int composite_session_close(cmp_server *srv, int64_t sid);
  * memory allocated page-locked, vh rows of vw uint32 with dst_pitch elements
  * between rows).  The request is validated against the session's working set
  * as it will be after all its earlier requests: removing an id it will not
- * hold gives CMP_ENOTMEMBER.  Thread-safe; returns without waiting.  *ticket
- * identifies the request to composite_session_wait.  dst must stay valid and
- * untouched until the request completes. */
+ * hold gives CMP_ENOTMEMBER, and with count_bits = 16 an add that would take
+ * it past 65535 members gives CMP_ERANGE.  CMP_EBUSY when max_queue requests
+ * are waiting.  A refused request changes nothing.  Thread-safe; returns
+ * without waiting: the real-time add and remove of surfaces of Figure 1.
+ * *ticket identifies the request to composite_session_wait.  dst must stay
+ * valid and untouched until the request completes. */
 int composite_session_submit(cmp_server *srv, int64_t sid, int32_t op, const int32_t *ids,
                              int32_t n, int32_t vx0, int32_t vy0, int32_t vw, int32_t vh,
                              uint32_t *dst, int64_t dst_pitch, uint64_t *ticket);
@@ -440,9 +469,19 @@ typedef struct cmp_server_stats {
   double device_ms;          /* summed device time of the update launches */
   int64_t drops, rebuilds;   /* evictions without a copy, and composites
                                 rebuilt from their members */
+  int64_t refused_sessions;  /* session opens refused by admission */
+  int64_t refused_busy;      /* submits refused because the queue was full */
+  int64_t queue_peak;        /* most requests waiting for a step at once */
 } cmp_server_stats;
 
+/* Counters since the server was created. */
 int composite_server_stats(cmp_server *srv, cmp_server_stats *st);
+
+/* paused = 1: the server launches no new step (steps already launched
+ * finish); submitted requests wait in the queue, up to max_queue.  paused = 0
+ * resumes.  For maintenance windows and for tests of the queue bound.
+ * composite_server_free still drains everything. */
+int composite_server_pause(cmp_server *srv, int32_t paused);
 
 /* One request of an open-loop replay: t_ns is its arrival time after the
  * replay starts; its ids are ids[ids_off .. ids_off + n). */
@@ -458,10 +497,16 @@ typedef struct cmp_replay_req {
  * open-loop Poisson schedule does not wait for completions), then waits for
  * all of them.  Request i copies its viewport to dst_ring[i % ring] (pinned
  * host buffers of at least vh * dst_pitch uint32).  latency_ns[i] = completion
- * time - scheduled arrival time.  Returns the first failing status. */
+ * time - scheduled arrival time, or -1 for a request that did not complete.
+ * status: NULL, or nreq entries that receive each request's status.  With
+ * status, a request refused by submit with CMP_EBUSY, CMP_ENOTMEMBER (it
+ * removes ids that only a refused request would have added) or CMP_ERANGE is
+ * recorded and the replay goes on; any other failure, and any refusal when
+ * status is NULL, ends the replay (requests after it get CMP_ECANCELED).
+ * Returns the first status that ended it, else CMP_OK. */
 int composite_server_replay(cmp_server *srv, const cmp_replay_req *reqs, int64_t nreq,
                             const int32_t *ids, uint32_t *const *dst_ring, int32_t ring,
-                            int64_t dst_pitch, int64_t *latency_ns);
+                            int64_t dst_pitch, int64_t *latency_ns, int32_t *status);
 
 /* Histogram of overlap classes (Figure 1, lower-left panel: the frequency of
  * each overlap class of the composite): bins[k] = number of pixels whose count

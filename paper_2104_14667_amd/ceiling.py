@@ -1,0 +1,41 @@
+"""Binding of libceiling.so, the same-traffic reference kernel used by the
+benchmark and the experiments (measurement only; the compositing library
+never loads it).
+
+Modes (`rmw`): 0 member reads only; 1 plus a 9 B/px read-modify-write of
+uint32 count, uint32 sum and uint8 max; 2 plus a 4 B/px uint32 count
+read-modify-write; 3 plus a 2 B/px uint16 count read-modify-write; 4 plus the
+9 B/px written without being read; 5 plus the 9 B/px read without being
+written."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libceiling.so")
+
+
+def same_traffic_ceiling(torch, ptr, stride, n, npix, modes=((1, "rmw_ms"), (0, "read_only_ms")),
+                         reps=6):
+    """Best time in ms, per mode, of the reference kernel over n device rasters
+    at ptr + i * stride of npix bytes each."""
+    lib = C.CDLL(LIB_PATH)
+    lib.traffic_ceiling.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.POINTER(C.c_float)]
+    cnt = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
+    sm = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
+    mx = torch.zeros(npix, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    out = {}
+    for rmw, name in modes:
+        ms = C.c_float()
+        rc = lib.traffic_ceiling(ptr, stride, n, npix, cnt.data_ptr(), sm.data_ptr(),
+                                 mx.data_ptr(), rmw, reps, torch.cuda.current_stream().cuda_stream,
+                                 C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"traffic_ceiling failed: hip error {rc}")
+        out[name] = ms.value
+    del cnt, sm, mx
+    return out

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcomposite.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "composite.h")
 
 CMP_OK, CMP_EINVAL, CMP_ENOMEM, CMP_ERANGE, CMP_ENOTMEMBER = 0, -1, -2, -3, -4
-CMP_EUNSUPPORTED, CMP_EDEVICE, CMP_EBUSY, CMP_ETIMEDOUT = -5, -6, -7, -8
+CMP_EUNSUPPORTED, CMP_EDEVICE, CMP_EBUSY, CMP_ETIMEDOUT, CMP_ECANCELED = -5, -6, -7, -8, -9
 CMP_COUNT, CMP_SUM, CMP_MAX = 1, 2, 4
 CMP_LINEAR, CMP_TILED = 0, 1
 CMP_DST_HOST, CMP_DST_DEVICE, CMP_DST_PINNED = 0, 1, 2
@@ -66,13 +66,17 @@ class cmp_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_sessions", C.c_int32),
                 ("max_batch", C.c_int32), ("max_view_pixels", C.c_int32),
                 ("tile_vecs", C.c_int32), ("blocks_per_cu", C.c_int32), ("overlap", C.c_int32),
-                ("remat_max_members", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("remat_max_members", C.c_int32), ("count_bits", C.c_int32),
+                ("oversubscribe_pct", C.c_int32), ("max_queue", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class cmp_server_stats(C.Structure):
     _fields_ = [("requests", C.c_int64), ("steps", C.c_int64), ("max_step", C.c_int64),
                 ("spills", C.c_int64), ("restores", C.c_int64), ("resident_slots", C.c_int64),
-                ("device_ms", C.c_double), ("drops", C.c_int64), ("rebuilds", C.c_int64)]
+                ("device_ms", C.c_double), ("drops", C.c_int64), ("rebuilds", C.c_int64),
+                ("refused_sessions", C.c_int64), ("refused_busy", C.c_int64),
+                ("queue_peak", C.c_int64)]
 
 
 class cmp_replay_req(C.Structure):
@@ -125,7 +129,8 @@ _SIGS = {
     "composite_session_wait": (C.c_int, [_vp, C.c_uint64, _i64, _P(_i64), _P(_i64)]),
     "composite_server_stats": (C.c_int, [_vp, _P(cmp_server_stats)]),
     "composite_server_replay": (C.c_int, [_vp, _P(cmp_replay_req), _i64, _P(_i32), _P(_vp),
-                                          _i32, _i64, _P(_i64)]),
+                                          _i32, _i64, _P(_i64), _P(_i32)]),
+    "composite_server_pause": (C.c_int, [_vp, _i32]),
     "composite_histogram": (C.c_int, [_vp, _P(_i64), _i32, _P(_i64)]),
     "composite_repack_tiled": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _i32, _i32, _vp]),
     "composite_tiled_bytes": (C.c_int64, [_i32, _i32, _i32, _i32]),
@@ -519,6 +524,18 @@ class Server:
         _check(lib.composite_session_open(self.handle, C.byref(sid)), "composite_session_open")
         return sid.value
 
+    def try_open(self) -> Optional[int]:
+        """A session id, or None when admission refuses it (CMP_ENOMEM)."""
+        sid = C.c_int64()
+        rc = lib.composite_session_open(self.handle, C.byref(sid))
+        if rc == CMP_ENOMEM:
+            return None
+        _check(rc, "composite_session_open")
+        return sid.value
+
+    def pause(self, paused: bool = True) -> None:
+        _check(lib.composite_server_pause(self.handle, int(bool(paused))), "composite_server_pause")
+
     def close_session(self, sid: int) -> None:
         _check(lib.composite_session_close(self.handle, int(sid)), "composite_session_close")
 
@@ -545,11 +562,13 @@ class Server:
         _check(lib.composite_server_stats(self.handle, C.byref(st)), "composite_server_stats")
         return {k: getattr(st, k) for k, _ in cmp_server_stats._fields_}
 
-    def replay(self, schedule, sid_of, dst_ring, pitch: int) -> np.ndarray:
+    def replay(self, schedule, sid_of, dst_ring, pitch: int, with_status: bool = False):
         """Open-loop replay of requests (dicts t, sid, op, ids, vx0, vy0, vw, vh,
         as made by synth.ServeWorkload.schedule); sid_of maps the schedule's
         session index to a server session id.  Returns latency in ns per
-        request (completion time minus scheduled arrival)."""
+        request (completion time minus scheduled arrival, -1 if it did not
+        complete); with_status, also each request's status (refused requests
+        are recorded and the replay goes on)."""
         n = len(schedule)
         reqs = (cmp_replay_req * n)()
         ids_all = []
@@ -567,11 +586,14 @@ class Server:
         ids = np.ascontiguousarray(np.concatenate(ids_all) if ids_all else np.zeros(1, np.int32))
         ring = (C.c_void_p * len(dst_ring))(*[_ptr(d) for d in dst_ring])
         lat = np.zeros(n, dtype=np.int64)
+        status = np.zeros(n, dtype=np.int32)
         rc = lib.composite_server_replay(self.handle, reqs, n, ids.ctypes.data_as(C.POINTER(C.c_int32)),
                                          ring, len(dst_ring), int(pitch),
-                                         lat.ctypes.data_as(C.POINTER(C.c_int64)))
+                                         lat.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         status.ctypes.data_as(C.POINTER(C.c_int32))
+                                         if with_status else None)
         _check(rc, "composite_server_replay")
-        return lat
+        return (lat, status) if with_status else lat
 
     def close(self):
         if self.handle:

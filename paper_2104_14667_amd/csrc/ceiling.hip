@@ -4,12 +4,19 @@
 //
 // It issues the loads and stores of the compositing kernel's linear path with
 // trivial arithmetic in place of the compositing: n member streams read with
-// non-temporal 16-byte loads, 16 pixels per thread, then (rmw = 1) 9 bytes per
-// pixel of composite read and written (uint32 count, uint32 sum, uint8 max),
-// (rmw = 2) 4 bytes per pixel (uint32 count only, the served sessions'
-// composite), or nothing (rmw = 0, the read-only rate).  Its rate is what the memory
-// system sustains for that access pattern, the attainable bound for the
-// compositing kernel on the same data.
+// non-temporal 16-byte loads, 16 pixels per thread, then, by mode,
+//   0: nothing more (the read-only rate),
+//   1: 9 bytes per pixel of composite read and written (uint32 count, uint32
+//      sum, uint8 max),
+//   2: 4 bytes per pixel read and written (uint32 count, the served sessions'
+//      composite),
+//   3: 2 bytes per pixel read and written (uint16 count),
+//   4: the 9 bytes per pixel written without being read (a composite set from
+//      cleared accumulators),
+//   5: the 9 bytes per pixel read without being written.
+// Its rate is what the memory system sustains for that access pattern, the
+// attainable bound for the compositing kernel on the same data; modes 0, 4, 5
+// and 1 side by side split the cost of the composite's read and write.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,7 +55,31 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
   uint4 *c = reinterpret_cast<uint4 *>(cnt + t * 16u);
   uint4 *s = reinterpret_cast<uint4 *>(sum + t * 16u);
   uint4 *x = reinterpret_cast<uint4 *>(mx + t * 16u);
-  if (RMW == 2) {
+  if (RMW == 3) {
+    uint4 *c16 = reinterpret_cast<uint4 *>(reinterpret_cast<uint16_t *>(cnt) + t * 16u);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint4 o = c16[q];
+      c16[q] = make_uint4(o.x + a0, o.y + a1, o.z + a2, o.w + a3);
+    }
+  } else if (RMW == 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c[q] = make_uint4(a0 + q, a1, a2, a3);
+      s[q] = make_uint4(a0 ^ q, a1, a2, a3);
+    }
+    x[0] = make_uint4(a0 | 1u, a1, a2, a3);
+  } else if (RMW == 5) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 o = c[q], p = s[q];
+      r += o.x ^ o.y ^ o.z ^ o.w ^ p.x ^ p.y ^ p.z ^ p.w;
+    }
+    const uint4 o = x[0];
+    r += o.x ^ o.y ^ o.z ^ o.w;
+    if (r == never && a0 == never) c[0] = make_uint4(a0, a1, a2, a3);  // keeps the loads live; not taken
+  } else if (RMW == 2) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint4 o = c[q];
@@ -76,12 +107,12 @@ extern "C" {
 // rasters at members + i * stride (npix bytes each, npix a multiple of 16,
 // 16-byte aligned) and composite buffers count, sum (npix uint32 each) and
 // max (npix bytes), and returns in *best_ms the fastest of the runs after the
-// first.  rmw: 0, 1 or 2 as above.  Returns 0 or a hipError_t.  The
+// first.  rmw: the mode, 0 .. 5 as above.  Returns 0 or a hipError_t.  The
 // composite buffers are overwritten.
 int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t npix, void *count,
                     void *sum, void *max, int32_t rmw, int32_t reps, void *stream, float *best_ms) {
   if (!members || !count || !sum || !max || !best_ms || n < 1 || reps < 2 || npix < 16 ||
-      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 2)
+      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 5)
     return (int)hipErrorInvalidValue;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint32_t nvec = (uint32_t)(npix / 16);
@@ -98,15 +129,18 @@ int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t n
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
     e = hipEventRecord(e0, s);
     if (e != hipSuccess) break;
-    if (rmw == 2)
-      k_ceiling<2><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
-                                        (uint8_t *)max, nvec, 0x9e3779b9u);
-    else if (rmw == 1)
-      k_ceiling<1><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
-                                        (uint8_t *)max, nvec, 0x9e3779b9u);
-    else
-      k_ceiling<0><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum,
-                                        (uint8_t *)max, nvec, 0x9e3779b9u);
+#define CMP_CEIL(M)                                                                       \
+  k_ceiling<M><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, \
+                                    (uint8_t *)max, nvec, 0x9e3779b9u)
+    switch (rmw) {
+      case 5: CMP_CEIL(5); break;
+      case 4: CMP_CEIL(4); break;
+      case 3: CMP_CEIL(3); break;
+      case 2: CMP_CEIL(2); break;
+      case 1: CMP_CEIL(1); break;
+      default: CMP_CEIL(0); break;
+    }
+#undef CMP_CEIL
     e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);

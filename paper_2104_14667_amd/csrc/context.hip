@@ -9,13 +9,12 @@
 //   copy stream:    [wait slot_free[k % nbuf]]; H2D chunk k; record copied[k % nbuf]
 //   compute stream: wait copied[k % nbuf]; [repack to tiles]; composite;
 //                   record slot_free[k % nbuf]
-// The copy stream's wait on slot_free is replaced, by default, by a host wait
-// on the same event: a cross-stream wait in front of a copy costs about
-// 0.1 ms of copy-engine idle time per chunk on this runtime, while the host
-// wait happens when the kernel has long finished and the previous chunk is
-// still uploading, so the copy queue never runs dry.  nbuf = 1 gives the
-// single-buffer control (Figure 2): every upload waits for the kernel that
-// read the previous one.
+// Ordering is by events only: no host synchronisation inside the loop.  As an
+// option (host_paced) the copy stream's wait on slot_free is replaced by a host
+// wait on the same event, which happens when the kernel has long finished and
+// the previous chunk is still uploading.  nbuf = 1 gives the single-buffer
+// control (Figure 2): every upload waits for the kernel that read the previous
+// one.
 
 #include <hip/hip_runtime.h>
 
@@ -55,6 +54,11 @@ struct cmp_ctx {
   void *d_count = nullptr;
   uint32_t *d_sum = nullptr;
   uint8_t *d_max = nullptr;
+  // Outputs whose accumulators are logically zero but not written yet (after
+  // init, clear, or the start of a max rebuild): the next add writes them
+  // without reading (a set pass); anything else that needs their memory
+  // fills them first (materialize).
+  uint32_t zero_pending = 0;
   // With pingpong: the other accumulator of each output; a pass reads the
   // current one (above), writes this one, and the two are swapped.
   void *d_count_alt = nullptr;
@@ -102,8 +106,10 @@ struct cmp_ctx {
   unsigned long long *h_fp = nullptr;
   int64_t fp_cap = 0;
 
-  // Histogram counters (grown on demand).
+  // Histogram counters on the device and their pinned host copy (grown on
+  // demand, together).
   unsigned long long *d_hist = nullptr;
+  unsigned long long *h_hist = nullptr;
   int64_t hist_cap = 0;
 
   // Profiling of compositing kernels.
@@ -181,6 +187,7 @@ void free_all(cmp_ctx *ctx) {
   }
   if (ctx->ev_host_done) (void)hipEventDestroy(ctx->ev_host_done);
   dfree(ctx, ctx->d_hist);
+  if (ctx->h_hist) (void)hipHostFree(ctx->h_hist);
   dfree(ctx, ctx->d_fp);
   if (ctx->h_fp) (void)hipHostFree(ctx->h_fp);
   for (auto &t : ctx->timed) {
@@ -191,12 +198,15 @@ void free_all(cmp_ctx *ctx) {
   if (ctx->own_comp && ctx->comp_s) (void)hipStreamDestroy(ctx->comp_s);
 }
 
-hipError_t clear_outputs(cmp_ctx *ctx) {
+// Writes the zeros of the pending outputs among `which` (on the compute stream).
+hipError_t materialize(cmp_ctx *ctx, uint32_t which) {
+  const uint32_t w = ctx->zero_pending & which;
   hipError_t e = hipSuccess;
-  if (ctx->d_count && e == hipSuccess)
+  if ((w & CMP_COUNT) && e == hipSuccess)
     e = cmp::launch_fill(ctx->d_count, 0, ctx->npix * (ctx->count_bits / 8), ctx->comp_s);
-  if (ctx->d_sum && e == hipSuccess) e = cmp::launch_fill(ctx->d_sum, 0, ctx->npix * 4, ctx->comp_s);
-  if (ctx->d_max && e == hipSuccess) e = cmp::launch_fill(ctx->d_max, 0, ctx->npix, ctx->comp_s);
+  if ((w & CMP_SUM) && e == hipSuccess) e = cmp::launch_fill(ctx->d_sum, 0, ctx->npix * 4, ctx->comp_s);
+  if ((w & CMP_MAX) && e == hipSuccess) e = cmp::launch_fill(ctx->d_max, 0, ctx->npix, ctx->comp_s);
+  if (e == hipSuccess) ctx->zero_pending &= ~w;
   return e;
 }
 
@@ -239,6 +249,15 @@ hipError_t composite_pass(cmp_ctx *ctx, const uint8_t *const *d_tab, int n, bool
   if (sub) outs &= ~(uint32_t)CMP_MAX;  // max has no inverse: never subtracted
   cmp::Outputs o;
   o.count16 = ctx->count_bits == 16;
+  // an add over outputs that are all still zero writes them without reading
+  // them (a set pass); any other mix writes the pending zeros first
+  const uint32_t pend = ctx->zero_pending & outs;
+  if (pend && !sub && pend == outs) {
+    o.set = true;
+  } else if (pend) {
+    const hipError_t e = materialize(ctx, pend);
+    if (e != hipSuccess) return e;
+  }
   const bool pp = ctx->o.pingpong != 0;
   if (outs & CMP_COUNT) {
     o.count = pp ? ctx->d_count_alt : ctx->d_count;
@@ -262,6 +281,7 @@ hipError_t composite_pass(cmp_ctx *ctx, const uint8_t *const *d_tab, int n, bool
     e = cmp::launch_composite_linear(d_tab, n, ctx->npix, o, outs, sub, ctx->comp_s);
   }
   if (e != hipSuccess) return e;
+  ctx->zero_pending &= ~outs;
   if (pp) {
     if (outs & CMP_COUNT) std::swap(ctx->d_count, ctx->d_count_alt);
     if (outs & CMP_SUM) std::swap(ctx->d_sum, ctx->d_sum_alt);
@@ -543,7 +563,7 @@ void composite_default_opts(cmp_opts *o) {
   o->tile_w = 64;
   o->tile_h = 64;
   o->device = 0;
-  o->host_paced = 1;
+  o->host_paced = 0;
 }
 
 int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_t count_bits,
@@ -628,9 +648,8 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
       if (!dalloc(ctx, (void **)&ctx->d_max, ctx->npix + 64)) break;
       if (pp && !dalloc(ctx, (void **)&ctx->d_max_alt, ctx->npix + 64)) break;
     }
-    rc = CMP_EDEVICE;
-    if (clear_outputs(ctx) != hipSuccess) break;
-    if (hipStreamSynchronize(ctx->comp_s) != hipSuccess) break;
+    // the accumulators start logically cleared: the first add writes them
+    ctx->zero_pending = outputs;
     rc = CMP_OK;
   } while (false);
   if (rc != CMP_OK) {
@@ -648,7 +667,9 @@ int composite_clear(cmp_ctx *ctx) {
   CMP_TRY(set_device(ctx));
   // the clear must not overtake uploads still feeding the compute stream
   CMP_TRY(hipStreamSynchronize(ctx->copy_s));
-  CMP_TRY(clear_outputs(ctx));
+  // nothing is written now: the next add writes the accumulators without
+  // reading them, and a read before any add writes the zeros first
+  ctx->zero_pending = ctx->outs;
   ctx->members = 0;
   ctx->host_members = 0;
   ctx->held.clear();
@@ -818,8 +839,9 @@ int composite_remove(cmp_ctx *ctx, const uint8_t *const *maps, const int64_t *id
     }
   }
   if (need_max) {
-    // max has no inverse: rebuild it from the members that remain
-    CMP_TRY(cmp::launch_fill(ctx->d_max, 0, ctx->npix, ctx->comp_s));
+    // max has no inverse: rebuild it from the members that remain, the first
+    // pass writing it from scratch (it is zero if none remain)
+    ctx->zero_pending |= CMP_MAX;
     for (size_t k0 = 0; k0 < keep.size(); k0 += 65536) {
       const int cnt = (int)std::min<size_t>(65536, keep.size() - k0);
       const uint8_t **d_tab = nullptr;
@@ -859,6 +881,7 @@ int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0, int32_t
                                        : (const void *)ctx->d_max;
   CMP_TRY(set_device(ctx));
   CMP_TRY(hipStreamSynchronize(ctx->copy_s));
+  CMP_TRY(materialize(ctx, which));
   if (dst_kind == CMP_DST_DEVICE) {
     CMP_TRY(cmp::launch_pack_window(src, eb, ctx->W, x0, y0, w, h, dst, dst_pitch_bytes, ctx->comp_s));
     CMP_TRY(hipStreamSynchronize(ctx->comp_s));
@@ -938,6 +961,10 @@ int composite_device_buffer(cmp_ctx *ctx, uint32_t which, void **dev_ptr) {
   if (!ctx || !dev_ptr) return CMP_EINVAL;
   if (which != CMP_COUNT && which != CMP_SUM && which != CMP_MAX) return CMP_EINVAL;
   if (!(ctx->outs & which)) return CMP_EINVAL;
+  if (ctx->poisoned) return CMP_EDEVICE;
+  // the caller reads the memory itself: pending zeros are written first
+  CMP_TRY(set_device(ctx));
+  CMP_TRY(materialize(ctx, which));
   *dev_ptr = which == CMP_COUNT ? ctx->d_count
              : which == CMP_SUM ? (void *)ctx->d_sum
                                 : (void *)ctx->d_max;
@@ -967,12 +994,20 @@ int composite_histogram(cmp_ctx *ctx, int64_t *bins, int32_t nbins, int64_t *ove
   if (ctx->hist_cap < nbins + 1) {
     CMP_TRY(hipStreamSynchronize(ctx->comp_s));
     dfree(ctx, ctx->d_hist);
+    if (ctx->h_hist) (void)hipHostFree(ctx->h_hist);
     ctx->d_hist = nullptr;
+    ctx->h_hist = nullptr;
     ctx->hist_cap = 0;
     if (!dalloc(ctx, (void **)&ctx->d_hist, sizeof(unsigned long long) * (nbins + 1)))
       return CMP_ENOMEM;
+    // the bins come back through page-locked memory of the context, never
+    // through the runtime's handling of pageable memory
+    if (hipHostMalloc((void **)&ctx->h_hist, sizeof(unsigned long long) * (nbins + 1),
+                      hipHostMallocDefault) != hipSuccess)
+      return CMP_ENOMEM;
     ctx->hist_cap = nbins + 1;
   }
+  CMP_TRY(materialize(ctx, CMP_COUNT));
   unsigned long long *d_bins = ctx->d_hist;
   int cus = 256;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->dev);
@@ -980,9 +1015,9 @@ int composite_histogram(cmp_ctx *ctx, int64_t *bins, int32_t nbins, int64_t *ove
   if (e == hipSuccess)
     e = cmp::launch_histogram(ctx->d_count, ctx->count_bits == 16, ctx->npix, nbins, d_bins, cus,
                               ctx->comp_s);
-  std::vector<unsigned long long> h(nbins + 1);
+  const unsigned long long *h = ctx->h_hist;
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h.data(), d_bins, sizeof(unsigned long long) * (nbins + 1),
+    e = hipMemcpyAsync(ctx->h_hist, d_bins, sizeof(unsigned long long) * (nbins + 1),
                        hipMemcpyDeviceToHost, ctx->comp_s);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->comp_s);
   if (e != hipSuccess) {
@@ -1026,6 +1061,7 @@ const char *composite_strerror(int status) {
     case CMP_EDEVICE: return "GPU unavailable or HIP failure";
     case CMP_EBUSY: return "busy";
     case CMP_ETIMEDOUT: return "timed out";
+    case CMP_ECANCELED: return "not attempted: an earlier failure ended the call";
     default: return "unknown status";
   }
 }

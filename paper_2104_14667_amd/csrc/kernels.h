@@ -15,12 +15,15 @@ enum : uint32_t { kCount = 1, kSum = 2, kMax = 4 };
 // Where a launch writes the composite and, when the *_in pointers are set,
 // where it reads the previous values from (two accumulators used in turn);
 // otherwise the update is in place.  A launch that writes an output reads it
-// from its *_in pointer if any *_in pointer is set.
+// from its *_in pointer if any *_in pointer is set.  With set, the previous
+// values are all zero (cleared accumulators): nothing is read, the new values
+// are written (an add only; the *_in pointers are ignored).
 struct Outputs {
   void *count = nullptr;     // uint16_t* or uint32_t*
   uint32_t *sum = nullptr;
   uint8_t *max = nullptr;
   bool count16 = false;
+  bool set = false;
   const void *count_in = nullptr;
   const uint32_t *sum_in = nullptr;
   const uint8_t *max_in = nullptr;

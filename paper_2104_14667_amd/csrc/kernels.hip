@@ -14,8 +14,10 @@
 // kernel, while the paper's image kernels needed two accumulators used in turn
 // (image objects are read-only or write-only inside a kernel, Section 5.3).
 // That ping-pong form is kept as an option (PP: read one accumulator, write the
-// other) to measure the paper's kernel variants.  No matrix cores: nothing here
-// is a contraction.
+// other) to measure the paper's kernel variants.  A pass over accumulators that
+// were just cleared (SET) writes the new values without reading the old ones,
+// so a composite built from scratch moves member bytes plus one write of the
+// composite.  No matrix cores: nothing here is a contraction.
 
 #include "lanes.h"
 
@@ -128,7 +130,7 @@ struct TiledMap {
   }
 };
 
-template <uint32_t OUTS, bool SUB, bool C16, bool MULTI, class Map, bool PP>
+template <uint32_t OUTS, bool SUB, bool C16, bool MULTI, class Map, bool PP, bool SET>
 __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restrict__ tab,
                                                    int n, uint32_t nvec, Map map,
                                                    void *__restrict__ count,
@@ -147,6 +149,13 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
   Acc<OUTS> a;
   a.zero();
   Old<C16> old;
+  if constexpr (SET) {  // cleared accumulators: nothing to read
+#pragma unroll
+    for (int q = 0; q < (C16 ? 2 : 4); ++q) old.c[q] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) old.s[q] = make_uint4(0u, 0u, 0u, 0u);
+    old.m = make_uint4(0u, 0u, 0u, 0u);
+  }
   uint32_t cnt[16], sm[16], mx8[4];
   if constexpr (MULTI) {
 #pragma unroll
@@ -162,8 +171,12 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 #pragma unroll
       for (int k = 0; k < 8; ++k) a.c[k] = a.s[k] = 0u;
     }
-    if constexpr (PP) load_old<OUTS, SUB, C16>(old, p, count_in, sum_in, mx_in);
-    else load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
+    if constexpr (SET) {
+    } else if constexpr (PP) {
+      load_old<OUTS, SUB, C16>(old, p, count_in, sum_in, mx_in);
+    } else {
+      load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
+    }
   } else {
     // The old composite is requested before the last members are read, so
     // its latency overlaps them instead of trailing the wave (+1-2%).
@@ -175,8 +188,12 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) a.fold(x[u]);
     }
-    if constexpr (PP) load_old<OUTS, SUB, C16>(old, p, count_in, sum_in, mx_in);
-    else load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
+    if constexpr (SET) {
+    } else if constexpr (PP) {
+      load_old<OUTS, SUB, C16>(old, p, count_in, sum_in, mx_in);
+    } else {
+      load_old<OUTS, SUB, C16>(old, p, count, sum, mx);
+    }
     {  // the last 1..UNROLL members (n >= 1)
       uint4 x[UNROLL];
 #pragma unroll
@@ -200,7 +217,7 @@ __global__ __launch_bounds__(256) void k_composite(const uint8_t *const *__restr
 }
 
 // Pixels [p0, npix) that do not fill a 16-pixel vector: one thread per pixel.
-template <uint32_t OUTS, bool SUB, bool C16, bool PP>
+template <uint32_t OUTS, bool SUB, bool C16, bool PP, bool SET>
 __global__ __launch_bounds__(64) void k_composite_tail(const uint8_t *const *__restrict__ tab,
                                                        int n, int64_t p0, int64_t npix,
                                                        void *__restrict__ count,
@@ -220,19 +237,19 @@ __global__ __launch_bounds__(64) void k_composite_tail(const uint8_t *const *__r
   }
   if constexpr (OUTS & kCount) {
     if constexpr (C16) {
-      const uint16_t o = static_cast<const uint16_t *>(PP ? count_in : count)[p];
+      const uint16_t o = SET ? 0 : static_cast<const uint16_t *>(PP ? count_in : count)[p];
       static_cast<uint16_t *>(count)[p] = (uint16_t)(SUB ? o - c : o + c);
     } else {
-      const uint32_t o = static_cast<const uint32_t *>(PP ? count_in : count)[p];
+      const uint32_t o = SET ? 0u : static_cast<const uint32_t *>(PP ? count_in : count)[p];
       static_cast<uint32_t *>(count)[p] = SUB ? o - c : o + c;
     }
   }
   if constexpr (OUTS & kSum) {
-    const uint32_t o = (PP ? sum_in : sum)[p];
+    const uint32_t o = SET ? 0u : (PP ? sum_in : sum)[p];
     sum[p] = SUB ? o - s : o + s;
   }
   if constexpr ((OUTS & kMax) && !SUB) {
-    const uint32_t o = (PP ? mx_in : mx)[p];
+    const uint32_t o = SET ? 0u : (PP ? mx_in : mx)[p];
     mx[p] = (uint8_t)(m > o ? m : o);
   }
 }
@@ -244,15 +261,20 @@ hipError_t go(const uint8_t *const *tab, int n, int64_t nvec, const Map &map,
   if (nvec >= (int64_t(1) << 28)) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((nvec + 255) / 256);
   const bool pp = o.count_in || o.sum_in || o.max_in;
-#define CMP_GO(MULTI, PP)                                                                        \
-  k_composite<OUTS, SUB, C16, MULTI, Map, PP><<<blocks, 256, 0, s>>>(                            \
+#define CMP_GO(MULTI, PP, SET)                                                                   \
+  k_composite<OUTS, SUB, C16, MULTI, Map, PP, SET><<<blocks, 256, 0, s>>>(                       \
       tab, n, (uint32_t)nvec, map, o.count, o.sum, o.max, o.count_in, o.sum_in, o.max_in)
-  if (n > kGroup) {
-    if (pp) CMP_GO(true, true);
-    else CMP_GO(true, false);
+  if (o.set) {
+    // cleared accumulators are written, never read (and never subtracted from)
+    if constexpr (SUB) return hipErrorInvalidValue;
+    else if (n > kGroup) CMP_GO(true, false, true);
+    else CMP_GO(false, false, true);
+  } else if (n > kGroup) {
+    if (pp) CMP_GO(true, true, false);
+    else CMP_GO(true, false, false);
   } else {
-    if (pp) CMP_GO(false, true);
-    else CMP_GO(false, false);
+    if (pp) CMP_GO(false, true, false);
+    else CMP_GO(false, false, false);
   }
 #undef CMP_GO
   return hipGetLastError();
@@ -262,12 +284,18 @@ template <uint32_t OUTS, bool SUB, bool C16>
 hipError_t go_tail(const uint8_t *const *tab, int n, int64_t p0, int64_t npix,
                    const Outputs &o, hipStream_t s) {
   if (npix <= p0) return hipSuccess;
-  if (o.count_in || o.sum_in || o.max_in)
-    k_composite_tail<OUTS, SUB, C16, true><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum, o.max,
-                                                            o.count_in, o.sum_in, o.max_in);
-  else
-    k_composite_tail<OUTS, SUB, C16, false><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum, o.max,
-                                                             o.count_in, o.sum_in, o.max_in);
+  if (o.set) {
+    if constexpr (SUB) return hipErrorInvalidValue;
+    else
+      k_composite_tail<OUTS, SUB, C16, false, true><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum,
+                                                                     o.max, o.count_in, o.sum_in, o.max_in);
+  } else if (o.count_in || o.sum_in || o.max_in) {
+    k_composite_tail<OUTS, SUB, C16, true, false><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum, o.max,
+                                                                   o.count_in, o.sum_in, o.max_in);
+  } else {
+    k_composite_tail<OUTS, SUB, C16, false, false><<<1, 64, 0, s>>>(tab, n, p0, npix, o.count, o.sum,
+                                                                    o.max, o.count_in, o.sum_in, o.max_in);
+  }
   return hipGetLastError();
 }
 
@@ -307,28 +335,69 @@ hipError_t run_tiled(const uint8_t *const *tab, int n, int64_t nvec, const Tiled
       return c16 ? FN<O, true, true>(__VA_ARGS__) : FN<O, true, false>(__VA_ARGS__); \
     return c16 ? FN<O, false, true>(__VA_ARGS__) : FN<O, false, false>(__VA_ARGS__);
 
+// Linear -> tiled repack, staged through LDS.  A workgroup takes R rows of a
+// 1024-byte-wide block of one raster: the rows r0 .. r0 + R - 1 of the tiles
+// tx0 .. tx0 + 1024 / tw - 1 of tile row ty.  Every wave reads whole 1 KiB row
+// segments of the source into LDS, then writes each tile's R rows, which are
+// contiguous in the tiled layout (R * tw bytes per tile), so that both the
+// reads and the writes are long contiguous runs.  Bytes outside the raster
+// (right and bottom edge tiles) are written as zero.
+constexpr uint32_t kRepackBlockW = 1024;        // bytes of a row per workgroup
+constexpr uint32_t kRepackPitch = kRepackBlockW + 16;  // LDS row pitch: rows start on different banks
+
+struct RepackGeom {
+  uint32_t W, H, tw, th, ntx;
+  uint32_t R;     // rows per workgroup (<= th)
+  uint32_t nsb;   // row groups per tile row: ceil(th / R)
+  uint32_t ncb;   // 1024-byte column blocks: ceil(ntx * tw / 1024)
+};
+
 __global__ __launch_bounds__(256) void k_repack(const uint8_t *__restrict__ src, int64_t src_stride,
                                                 uint8_t *__restrict__ dst, int64_t dst_stride,
-                                                uint32_t nvec, TiledMap map) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nvec) return;
-  const int64_t i = blockIdx.y;
-  uint32_t p;
-  uint4 x = make_uint4(0u, 0u, 0u, 0u);
-  if (map.pixel(v, p)) {
-    const uint32_t col = p % map.W;
-    if (col + 16u <= map.W) {
-      x = ld16(src + i * src_stride, p);
-    } else {
-      // the vector crosses the raster's right edge: the bytes past it are
-      // padding (zero) and must not be read
-      uint32_t w[4] = {0u, 0u, 0u, 0u};
-      const uint8_t *row = src + i * src_stride + p;
-      for (uint32_t b = 0; b < map.W - col; ++b) w[b >> 2] |= (uint32_t)row[b] << (8 * (b & 3));
-      x = make_uint4(w[0], w[1], w[2], w[3]);
+                                                RepackGeom g) {
+  extern __shared__ uint4 lds[];
+  uint8_t *l8 = reinterpret_cast<uint8_t *>(lds);
+  const uint32_t b = blockIdx.x;
+  const uint32_t cb = b % g.ncb, t2 = b / g.ncb;
+  const uint32_t sb = t2 % g.nsb, ty = t2 / g.nsb;
+  const uint32_t r0 = sb * g.R;
+  const uint32_t rows = min(g.R, g.th - r0);
+  const uint32_t y0 = ty * g.th + r0, x0 = cb * kRepackBlockW;
+  const uint8_t *s = src + (int64_t)blockIdx.y * src_stride;
+  // rows x 64 vectors of 16 bytes in
+  for (uint32_t v = threadIdx.x; v < rows * 64u; v += blockDim.x) {
+    const uint32_t r = v >> 6, j = v & 63u;
+    const uint32_t y = y0 + r, x = x0 + 16u * j;
+    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+    if (y < g.H && x < g.W) {
+      const uint32_t off = y * g.W + x;  // < W * H < 2^32
+      if (x + 16u <= g.W) {
+        val = ld16(s, off);
+      } else {
+        // the vector crosses the raster's right edge: bytes past it are
+        // padding (zero) and must not be read
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        for (uint32_t k = 0; k < g.W - x; ++k) w[k >> 2] |= (uint32_t)s[off + k] << (8 * (k & 3));
+        val = make_uint4(w[0], w[1], w[2], w[3]);
+      }
     }
+    *reinterpret_cast<uint4 *>(l8 + r * kRepackPitch + 16u * j) = val;
   }
-  *reinterpret_cast<uint4 *>(dst + i * dst_stride + (int64_t)v * 16) = x;
+  __syncthreads();
+  // each tile's rows r0 .. r0 + rows - 1 out, contiguous in the tiled layout
+  const uint32_t K = kRepackBlockW / g.tw, vpr = g.tw >> 4;
+  const uint32_t tx0 = cb * K;
+  const uint32_t ktiles = min(K, g.ntx - tx0);
+  const uint32_t per_tile = rows * vpr;
+  uint8_t *d = dst + (int64_t)blockIdx.y * dst_stride;
+  const int64_t tile_bytes = (int64_t)g.tw * g.th;
+  for (uint32_t v = threadIdx.x; v < ktiles * per_tile; v += blockDim.x) {
+    const uint32_t k = v / per_tile, in = v - k * per_tile;
+    const uint32_t r = in / vpr, c = in - r * vpr;
+    const uint4 val = *reinterpret_cast<const uint4 *>(l8 + r * kRepackPitch + k * g.tw + 16u * c);
+    const int64_t o = ((int64_t)ty * g.ntx + tx0 + k) * tile_bytes + (int64_t)(r0 + r) * g.tw + 16u * c;
+    *reinterpret_cast<uint4 *>(d + o) = val;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fill(uint8_t *__restrict__ p, uint32_t word,
@@ -467,12 +536,25 @@ hipError_t launch_composite_tiled(const uint8_t *const *d_tab, int n, const Tili
 hipError_t launch_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
                                int64_t dst_stride, int n, const Tiling &t, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (t.tw % 16 || n > 65535) return hipErrorInvalidValue;
-  const TiledMap map{(uint32_t)t.W, (uint32_t)t.H, (uint32_t)t.tw, (uint32_t)t.th, (uint32_t)t.ntx()};
-  const int64_t nvec = t.plane() / 16;
-  if (nvec >= (int64_t(1) << 28)) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((nvec + 255) / 256), (unsigned)n);
-  k_repack<<<grid, 256, 0, s>>>(src, src_stride, dst, dst_stride, (uint32_t)nvec, map);
+  if (t.tw < 16 || t.tw > (int)kRepackBlockW || kRepackBlockW % t.tw || t.tw % 16 || t.th < 1 ||
+      n > 65535)
+    return hipErrorInvalidValue;
+  if ((int64_t)t.W * t.H >= (int64_t(1) << 32) || t.plane() / 16 >= (int64_t(1) << 28))
+    return hipErrorInvalidValue;
+  RepackGeom g;
+  g.W = (uint32_t)t.W;
+  g.H = (uint32_t)t.H;
+  g.tw = (uint32_t)t.tw;
+  g.th = (uint32_t)t.th;
+  g.ntx = (uint32_t)t.ntx();
+  // rows per workgroup: enough that each tile's part is a 1 KiB run, at most 32
+  g.R = std::min<uint32_t>(g.th, std::min<uint32_t>(32u, kRepackBlockW / g.tw));
+  g.nsb = (g.th + g.R - 1) / g.R;
+  g.ncb = (uint32_t)(((int64_t)g.ntx * g.tw + kRepackBlockW - 1) / kRepackBlockW);
+  const int64_t blocks = (int64_t)t.nty() * g.nsb * g.ncb;
+  if (blocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)blocks, (unsigned)n);
+  k_repack<<<grid, 256, (size_t)g.R * kRepackPitch, s>>>(src, src_stride, dst, dst_stride, g);
   return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ int64_t now_ns() {
 enum : int32_t { kModeAdd = 0, kModeSub = 1, kModeSet = 2 };
 
 struct SReq {
-  uint32_t *comp;     // session composite (device)
+  void *comp;         // session composite (device): uint16 or uint32 counts
   uint32_t *stage;    // viewport staging (device), vh rows of vw
   int32_t mode, ids_off, n;  // kMode*: composite += / -= / = count of ids
   int32_t vx0, vy0, vw, vh;
@@ -66,7 +66,10 @@ static_assert(sizeof(SHeader) == 64, "arena header is 64 bytes");
 // One work item: rows [row0, row0 + nrows) of a session composite.  Each thread
 // updates 16 pixels (count +/- the nonzero members, or count set to that of
 // the whole working set when the composite is rebuilt) and copies the pixels
-// that fall in the request's viewport to staging.
+// that fall in the request's viewport to staging (always uint32).  C16: the
+// session composites are uint16 (the server refuses a request that would take
+// a session past 65535 members, so no lane carries into its neighbour).
+template <bool C16>
 __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base, int64_t stride,
                                                int32_t W, const char *__restrict__ arena,
                                                uint32_t *__restrict__ queue) {
@@ -76,15 +79,20 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
   const SItem *items = reinterpret_cast<const SItem *>(arena + hd->items_off);
   const int32_t *ids_all = reinterpret_cast<const int32_t *>(arena + hd->ids_off);
   const int nvr = W >> 4;
+  constexpr int NQ = C16 ? 2 : 4;  // 16-byte words of composite per 16 pixels
   __shared__ int s_item;
   for (int pass = 0;; ++pass) {
-    // persistent grid: items from the queue; otherwise (queue NULL) one item
-    // per workgroup
-    if (threadIdx.x == 0)
-      s_item = queue ? (int)atomicAdd(queue, 1u) : pass == 0 ? (int)blockIdx.x : nitems;
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
+    int it;
+    if (queue) {
+      // persistent grid: items from the queue
+      if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();
+    } else {
+      // one item per workgroup: no queue, no barrier
+      it = pass == 0 ? (int)blockIdx.x : nitems;
+    }
     if (it >= nitems) break;  // the queue counter only grows: every wave exits
     const SItem I = items[it];
     const SReq R = reqs[I.req];
@@ -97,15 +105,17 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       // global-space pointers (the arena's are generic): global, not flat,
       // loads and stores
       typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-      __attribute__((address_space(1))) v4u *c = (__attribute__((address_space(1))) v4u *)(R.comp + off);
+      __attribute__((address_space(1))) v4u *c =
+          C16 ? (__attribute__((address_space(1))) v4u *)(static_cast<uint16_t *>(R.comp) + off)
+              : (__attribute__((address_space(1))) v4u *)(static_cast<uint32_t *>(R.comp) + off);
       // the old composite is requested first, so that its latency overlaps
       // the member loads instead of trailing them
-      v4u o[4];
+      v4u o[NQ];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = v4u{0u, 0u, 0u, 0u};
+      for (int q = 0; q < NQ; ++q) o[q] = v4u{0u, 0u, 0u, 0u};
       if (R.mode != kModeSet) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o[q] = c[q];
+        for (int q = 0; q < NQ; ++q) o[q] = c[q];
       }
       uint32_t cnt[16];
 #pragma unroll
@@ -134,13 +144,29 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
         for (int k = 0; k < 16; ++k) cnt[k] += cmp::lane_px(a.c, k);
       }
       uint32_t nv[16];
+      if constexpr (C16) {
+        // pixels 2m and 2m+1 share dword m of the composite (low half first)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const v4u d = {cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]};
-        if (R.mode == kModeSub) o[q] -= d;
-        else o[q] += d;
-        c[q] = o[q];
-        nv[4 * q] = o[q].x; nv[4 * q + 1] = o[q].y; nv[4 * q + 2] = o[q].z; nv[4 * q + 3] = o[q].w;
+        for (int q = 0; q < 2; ++q) {
+          uint32_t w[4] = {o[q].x, o[q].y, o[q].z, o[q].w};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t d = cnt[8 * q + 2 * k] | (cnt[8 * q + 2 * k + 1] << 16);
+            w[k] = R.mode == kModeSub ? cmp::psub(w[k], d) : cmp::padd(w[k], d);
+            nv[8 * q + 2 * k] = w[k] & 0xffffu;
+            nv[8 * q + 2 * k + 1] = w[k] >> 16;
+          }
+          c[q] = v4u{w[0], w[1], w[2], w[3]};
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const v4u d = {cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]};
+          if (R.mode == kModeSub) o[q] -= d;
+          else o[q] += d;
+          c[q] = o[q];
+          nv[4 * q] = o[q].x; nv[4 * q + 1] = o[q].y; nv[4 * q + 2] = o[q].z; nv[4 * q + 3] = o[q].w;
+        }
       }
       if (y >= R.vy0 && y < R.vy0 + R.vh && x + 16 > R.vx0 && x < R.vx0 + R.vw) {
         const int64_t row_base = (int64_t)(y - R.vy0) * R.vw;
@@ -175,9 +201,10 @@ struct Session {
   int slot = -1;            // resident slot or -1
   bool has_data = false;    // false: all zero (new); true: data in slot, spill, or dropped
   bool dropped = false;     // evicted without a copy: rebuilt from `applied` when next used
-  uint32_t *spill = nullptr;  // pinned host copy while spilled
+  uint8_t *spill = nullptr;  // pinned host copy while spilled
   std::unordered_map<int32_t, int64_t> projected;  // working set after queued requests
   std::unordered_map<int32_t, int64_t> applied;    // working set after launched requests
+  int64_t projected_n = 0;
   int64_t applied_n = 0;
   int64_t inflight = 0;     // requests submitted and not completed
   // Eviction priority (GreedyDual): the floor at the last use plus the cost
@@ -204,9 +231,10 @@ struct cmp_server {
   cmp_server_opts o{};
   int dev = 0;
   int32_t W = 0, H = 0;
-  int64_t comp_bytes = 0;
+  int64_t comp_bytes = 0;         // one session composite: W*H*count_bits/8
+  int64_t admit_limit = 0;        // sessions admitted at most (HBM budget)
   hipStream_t comp = nullptr, copy = nullptr;
-  uint32_t *slab = nullptr;
+  uint8_t *slab = nullptr;
   std::vector<int64_t> slot_owner;  // session id per slot, or -1
   uint32_t *d_queue = nullptr;
   // per half: descriptor arena (pinned + device), viewport staging, events
@@ -231,6 +259,7 @@ struct cmp_server {
   uint64_t use_clock = 0;
   double gd_floor = 0.0;         // priority of the last evicted session
   bool stop = false;
+  bool paused = false;
   bool worker_done = false;
   int failed = CMP_OK;           // sticky device failure
   cmp_server_stats st{};
@@ -289,7 +318,7 @@ hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
         if (e != hipSuccess) return e;
       }
       // ordered after every kernel that wrote the slot (same stream)
-      hipError_t e = hipMemcpyAsync(vs.spill, s->slab + (int64_t)slot * (s->comp_bytes / 4),
+      hipError_t e = hipMemcpyAsync(vs.spill, s->slab + (int64_t)slot * s->comp_bytes,
                                     s->comp_bytes, hipMemcpyDeviceToHost, s->comp);
       if (e != hipSuccess) return e;
       vs.dropped = false;
@@ -298,7 +327,7 @@ hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
     vs.slot = -1;
     s->slot_owner[slot] = -1;
   }
-  uint32_t *dst = s->slab + (int64_t)slot * (s->comp_bytes / 4);
+  uint8_t *dst = s->slab + (int64_t)slot * s->comp_bytes;
   if (ss.has_data && !ss.dropped) {
     hipError_t e = hipMemcpyAsync(dst, ss.spill, s->comp_bytes, hipMemcpyHostToDevice, s->comp);
     if (e != hipSuccess) return e;
@@ -333,7 +362,8 @@ void worker_body(cmp_server *s) {
     uint64_t index;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_queue.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      // a paused server forms no step (free stops it anyway, after draining)
+      s->cv_queue.wait(lk, [&] { return s->stop || (!s->queue.empty() && !s->paused); });
       if (s->queue.empty() && s->stop) return;
       if (s->failed != CMP_OK) return;
       index = s->steps_launched;
@@ -384,7 +414,7 @@ void worker_body(cmp_server *s) {
       ss->gd_h = s->gd_floor + 1.0 + (double)std::min<int64_t>(ss->applied_n, s->o.remat_max_members);
       ss->last_use = ++s->use_clock;
       SReq &d = rd[k];
-      d.comp = s->slab + (int64_t)ss->slot * (s->comp_bytes / 4);
+      d.comp = s->slab + (int64_t)ss->slot * s->comp_bytes;
       d.stage = s->stage[half] + (int64_t)k * view_stride;
       d.mode = rebuild ? kModeSet : r.op == CMP_OP_REMOVE ? kModeSub : kModeAdd;
       if (rebuild) {
@@ -442,8 +472,11 @@ void worker_body(cmp_server *s) {
     if (e == hipSuccess && persistent) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
     if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);
     if (e == hipSuccess && grid > 0) {
-      k_serve<<<grid, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half],
-                                          persistent ? s->d_queue : nullptr);
+      uint32_t *q = persistent ? s->d_queue : nullptr;
+      if (s->o.count_bits == 16)
+        k_serve<true><<<grid, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q);
+      else
+        k_serve<false><<<grid, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(s->ev_k1[half], s->comp);
@@ -534,6 +567,9 @@ void composite_default_server_opts(cmp_server_opts *o) {
   o->blocks_per_cu = 0;
   o->overlap = 1;
   o->remat_max_members = 2048;
+  o->count_bits = 32;
+  o->oversubscribe_pct = 0;
+  o->max_queue = 1024;
 }
 
 int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_opts *opts) {
@@ -545,12 +581,14 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
   if (opts) o = *opts;
   for (int r : o.reserved)
     if (r) return CMP_EINVAL;
-  if (pool->W % 16) return CMP_EUNSUPPORTED;
-  const int64_t comp_bytes = (int64_t)pool->W * pool->H * 4;
   if (o.max_batch < 1 || o.max_batch > 4096 || o.max_sessions < 1 || o.max_view_pixels < 1 ||
       o.tile_vecs < 64 || o.tile_vecs > 65536 || o.blocks_per_cu < 0 || o.blocks_per_cu > 16 ||
-      (o.overlap != 0 && o.overlap != 1) || o.remat_max_members < 0 || o.remat_max_members > 65535)
+      (o.overlap != 0 && o.overlap != 1) || o.remat_max_members < 0 || o.remat_max_members > 65535 ||
+      (o.count_bits != 16 && o.count_bits != 32) || o.oversubscribe_pct < 0 || o.max_queue < 1 ||
+      o.hbm_budget_bytes < 1)
     return CMP_EINVAL;
+  if (pool->W % 16) return CMP_EUNSUPPORTED;
+  const int64_t comp_bytes = (int64_t)pool->W * pool->H * (o.count_bits / 8);
   // a step must fit in the slab: at least max_batch resident composites
   if (o.hbm_budget_bytes / comp_bytes < o.max_batch) return CMP_EINVAL;
   cmp_server *s = new (std::nothrow) cmp_server();
@@ -562,6 +600,9 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
   s->H = pool->H;
   s->comp_bytes = comp_bytes;
   const int64_t nslots = std::min<int64_t>(o.hbm_budget_bytes / comp_bytes, o.max_sessions);
+  // admission: the sessions the slab holds resident, plus oversubscribe_pct
+  // percent of them that live by eviction
+  s->admit_limit = std::min<int64_t>(o.max_sessions, nslots + nslots * (int64_t)o.oversubscribe_pct / 100);
   int rc = CMP_EDEVICE;
   do {
     if (hipSetDevice(s->dev) != hipSuccess) break;
@@ -645,7 +686,11 @@ int composite_session_open(cmp_server *s, int64_t *sid_out) {
   if (!s || !sid_out) return CMP_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->failed != CMP_OK) return s->failed;
-  if (s->open_sessions >= s->o.max_sessions) return CMP_ENOMEM;
+  if (s->open_sessions >= s->admit_limit) {
+    // refused by the HBM budget (or max_sessions); nothing else changes
+    s->st.refused_sessions += 1;
+    return CMP_ENOMEM;
+  }
   const int64_t sid = s->next_sid++;
   Session &ss = s->sessions[sid];
   ss.open = true;
@@ -662,7 +707,7 @@ int composite_session_close(cmp_server *s, int64_t sid) {
   if (it->second.inflight > 0) return CMP_EBUSY;
   // the slot is released; the worker never touches it again for this id
   if (it->second.slot >= 0) s->slot_owner[it->second.slot] = -1;
-  uint32_t *spill = it->second.spill;
+  uint8_t *spill = it->second.spill;
   s->sessions.erase(it);
   s->open_sessions -= 1;
   lk.unlock();
@@ -696,6 +741,11 @@ int composite_session_submit(cmp_server *s, int64_t sid, int32_t op, const int32
   auto it = s->sessions.find(sid);
   if (it == s->sessions.end() || !it->second.open) return CMP_EINVAL;
   Session &ss = it->second;
+  // every refusal below leaves the server as it was
+  if ((int64_t)s->queue.size() >= s->o.max_queue) {
+    s->st.refused_busy += 1;
+    return CMP_EBUSY;
+  }
   if (op == CMP_OP_REMOVE) {
     std::unordered_map<int32_t, int64_t> need;
     for (int32_t i = 0; i < n; ++i) need[ids[i]] += 1;
@@ -705,8 +755,14 @@ int composite_session_submit(cmp_server *s, int64_t sid, int32_t op, const int32
     }
     for (auto &kv : need)
       if ((ss.projected[kv.first] -= kv.second) == 0) ss.projected.erase(kv.first);
+    ss.projected_n -= n;
   } else {
+    // a uint16 composite holds counts up to 65535 (a uint32 one 2^32 - 1,
+    // beyond what a pool can be asked for here)
+    const int64_t cap = s->o.count_bits == 16 ? 65535 : (int64_t(1) << 32) - 1;
+    if (ss.projected_n + n > cap) return CMP_ERANGE;
     for (int32_t i = 0; i < n; ++i) ss.projected[ids[i]] += 1;
+    ss.projected_n += n;
   }
   Request r;
   r.ticket = s->next_ticket++;
@@ -725,7 +781,19 @@ int composite_session_submit(cmp_server *s, int64_t sid, int32_t op, const int32
   s->pending.insert(r.ticket);
   *ticket = r.ticket;
   s->queue.push_back(std::move(r));
+  s->st.queue_peak = std::max<int64_t>(s->st.queue_peak, (int64_t)s->queue.size());
   s->cv_queue.notify_one();
+  return CMP_OK;
+}
+
+int composite_server_pause(cmp_server *s, int32_t paused) {
+  if (!s || (paused != 0 && paused != 1)) return CMP_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed != CMP_OK) return s->failed;
+    s->paused = paused != 0;
+  }
+  s->cv_queue.notify_all();
   return CMP_OK;
 }
 
@@ -756,12 +824,14 @@ int composite_server_stats(cmp_server *s, cmp_server_stats *st) {
 
 int composite_server_replay(cmp_server *s, const cmp_replay_req *reqs, int64_t nreq, const int32_t *ids,
                             uint32_t *const *dst_ring, int32_t ring, int64_t dst_pitch,
-                            int64_t *latency_ns) {
+                            int64_t *latency_ns, int32_t *status) {
   if (!s || nreq < 0 || (nreq > 0 && (!reqs || !dst_ring || ring < 1 || !latency_ns))) return CMP_EINVAL;
   std::vector<uint64_t> tickets(nreq, 0);
   std::vector<int64_t> arrival(nreq, 0);
+  std::vector<int32_t> st(nreq, CMP_OK);
   const int64_t t0 = now_ns();
   int rc = CMP_OK;
+  int64_t last = nreq;  // requests [last, nreq) were never submitted
   for (int64_t i = 0; i < nreq; ++i) {
     const cmp_replay_req &q = reqs[i];
     const int64_t target = t0 + q.t_ns;
@@ -772,23 +842,35 @@ int composite_server_replay(cmp_server *s, const cmp_replay_req *reqs, int64_t n
       else std::this_thread::yield();
     }
     arrival[i] = target;
-    rc = composite_session_submit(s, q.sid, q.op, q.n ? ids + q.ids_off : nullptr, q.n, q.vx0, q.vy0,
-                                  q.vw, q.vh, dst_ring[i % ring], dst_pitch, &tickets[i]);
-    if (rc != CMP_OK) break;
+    const int r = composite_session_submit(s, q.sid, q.op, q.n ? ids + q.ids_off : nullptr, q.n, q.vx0,
+                                           q.vy0, q.vw, q.vh, dst_ring[i % ring], dst_pitch, &tickets[i]);
+    st[i] = r;
+    if (r == CMP_OK) continue;
+    // a refusal (full queue; a remove of ids that only a refused add would have
+    // brought; a uint16 session at its limit) is recorded and the replay goes
+    // on; any other failure ends it
+    if (status && (r == CMP_EBUSY || r == CMP_ENOTMEMBER || r == CMP_ERANGE)) continue;
+    rc = r;
+    last = i + 1;
+    break;
   }
-  const int64_t submitted = rc == CMP_OK ? nreq : std::count_if(tickets.begin(), tickets.end(),
-                                                                [](uint64_t t) { return t != 0; });
-  for (int64_t i = 0; i < submitted; ++i) {
+  for (int64_t i = 0; i < last; ++i) {
+    latency_ns[i] = -1;
+    if (st[i] != CMP_OK) continue;
     int64_t ts = 0, td = 0;
     const int w = composite_session_wait(s, tickets[i], -1, &ts, &td);
     if (w != CMP_OK) {
       if (rc == CMP_OK) rc = w;
-      latency_ns[i] = -1;
+      st[i] = w;
       continue;
     }
     latency_ns[i] = td - arrival[i];
   }
-  for (int64_t i = submitted; i < nreq; ++i) latency_ns[i] = -1;
+  for (int64_t i = last; i < nreq; ++i) {
+    latency_ns[i] = -1;
+    st[i] = CMP_ECANCELED;
+  }
+  if (status) std::copy(st.begin(), st.end(), status);
   return rc;
 }
 

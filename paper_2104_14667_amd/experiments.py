@@ -38,8 +38,21 @@
   against its closed form (a pixel's count is the number of members whose
   level exceeds its elevation).
 
+* ``member-layout``: the resident depth workload (N = 128 members of
+  8192x8192, count + sum + max) with the members placed in one allocation at a
+  stride of 8192^2 + pad bytes, for several pads: the compositing kernel's
+  average launch time (HIP events) and the same-traffic reference kernel's
+  best time on the same placement.  With pad 0 the same pixel of every member
+  lies exactly 64 MiB apart.
+* ``write-mix``: what the composite's read and write cost next to n member
+  streams: the same-traffic reference kernel over n members of 8192x8192 with
+  member reads only, plus the 9 B/px composite read, plus its write, plus both
+  (read-modify-write), for several n; and a plain fill and copy of the same
+  composite bytes (torch) for scale.
+
 Usage: python -m paper_2104_14667_amd.experiments
-           {repack-sweep,paper-table,kernel-table,h2d-sweep,subdivide} [--out FILE]
+           {repack-sweep,paper-table,kernel-table,h2d-sweep,subdivide,member-layout,write-mix}
+           [--out FILE]
 """
 
 from __future__ import annotations
@@ -285,6 +298,113 @@ def subdivide_table(N: int = 32, ring_size: int = 8, bands=(17664, 8192, 4096, 1
     return {"W": W, "H": H, "N": N, "ring": ring_size, "output": "count u32", "rows": rows}
 
 
+def _depth_inputs(n, side, seed=2):
+    """Elevation and levels of the depth workload's recipe (sigma 64, levels
+    96..224)."""
+    from . import synth
+    return synth.elevation(seed, side, side, 64.0), synth.levels(seed, n, 96, 224)
+
+
+def _depth_members(torch, buf, e, lv, stride):
+    """The depth members of (e, lv) written at buf + i * stride."""
+    from . import synth
+    side = e.shape[0]
+    et = torch.from_numpy(e).to("cuda:0")
+    for i, L in enumerate(lv):
+        synth.member_torch(et, int(L), "depth", out=buf[i * stride:i * stride + side * side].view(side, side))
+    torch.cuda.synchronize()
+
+
+def _depth_closed_form(e, lv, times):
+    """count, sum and max of `times` passes over members clamp(L - e, 0, 255)."""
+    lv = np.asarray(lv, np.int64)
+    d = np.clip(lv[None, :] - np.arange(256)[:, None], 0, 255)
+    lut = {"count": (d > 0).sum(1) * times, "sum": d.sum(1) * times, "max": d.max(1)}
+    return {k: v[e] for k, v in lut.items()}
+
+
+def member_layout(pads=(0, 4096, 65536, 2 << 20, (2 << 20) + 4096, 64 << 20), n=128, side=8192,
+                  reps=10) -> dict:
+    import torch
+
+    from .ceiling import same_traffic_ceiling
+    from .composite import Composite
+    plane = side * side
+    buf = torch.empty(n * (plane + max(pads)) + 64, dtype=torch.uint8, device="cuda:0")
+    algo = n * plane + 2 * plane * 9
+    e, lv = _depth_inputs(n, side)
+    rows = []
+    for pad in pads:
+        stride = plane + pad
+        _depth_members(torch, buf, e, lv, stride)
+        ptrs = [buf.data_ptr() + i * stride for i in range(n)]
+        with Composite(side, side, ("count", "sum", "max"), 32, profile=1) as c:
+            for _ in range(2):
+                c.add_device(ptrs)
+            c.sync()
+            c.kernel_stats(reset=True)
+            for _ in range(reps):
+                c.add_device(ptrs)
+            c.sync()
+            launches, ms = c.kernel_stats(reset=True)
+            exp = _depth_closed_form(e, lv, reps + 2)
+            exact = all(np.array_equal(c.read(k).astype(np.int64), exp[k]) for k in exp)
+        ceil = same_traffic_ceiling(torch, buf.data_ptr(), stride, n, plane)
+        avg = ms / launches
+        rows.append({"pad_bytes": pad, "stride_bytes": stride, "kernel_avg_ms": round(avg, 4),
+                     "kernel_GBps": round(algo / (avg * 1e-3) / 1e9, 1),
+                     "kernel_frac_of_8TBps": round(algo / (avg * 1e-3) / 8e12, 4),
+                     "reference_rmw_ms": round(ceil["rmw_ms"], 4),
+                     "reference_read_only_ms": round(ceil["read_only_ms"], 4),
+                     "reference_read_only_GBps": round(n * plane / (ceil["read_only_ms"] * 1e-3) / 1e9, 1),
+                     "exact": exact})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"n": n, "side": side, "reps": reps, "algorithmic_bytes_per_launch": algo, "rows": rows}
+
+
+def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
+    import torch
+
+    from .ceiling import same_traffic_ceiling
+    plane = side * side
+    stride = plane + pad
+    buf = torch.empty(max(ns) * stride + 64, dtype=torch.uint8, device="cuda:0")
+    e, lv = _depth_inputs(max(ns), side)
+    _depth_members(torch, buf, e, lv, stride)
+    comp = 9 * plane
+    rows = []
+    for n in ns:
+        t = same_traffic_ceiling(torch, buf.data_ptr(), stride, n, plane,
+                                 ((0, "reads"), (5, "reads+composite_read"),
+                                  (4, "reads+composite_write"), (1, "reads+rmw")))
+        row = {"members": n, "member_GB": round(n * plane / 1e9, 3), "composite_GB": round(comp / 1e9, 3)}
+        row.update({k + "_ms": round(v, 4) for k, v in t.items()})
+        row["read_cost_ms_per_GB"] = round((t["reads+composite_read"] - t["reads"]) / (comp / 1e9), 3)
+        row["write_cost_ms_per_GB"] = round((t["reads+composite_write"] - t["reads"]) / (comp / 1e9), 3)
+        row["rmw_cost_ms_per_GB_moved"] = round((t["reads+rmw"] - t["reads"]) / (2 * comp / 1e9), 3)
+        row["member_read_GBps"] = round(n * plane / (t["reads"] * 1e-3) / 1e9, 1)
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    # plain fill and copy of the composite's bytes, for scale
+    a = torch.empty(comp, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty(comp, dtype=torch.uint8, device="cuda:0")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    plain = {}
+    for name, fn in (("fill", lambda: a.fill_(3)), ("copy", lambda: b.copy_(a))):
+        best = None
+        for _ in range(6):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            ev[1].synchronize()
+            ms = ev[0].elapsed_time(ev[1])
+            best = ms if best is None else min(best, ms)
+        plain[name + "_ms"] = round(best, 4)
+    plain["fill_GBps"] = round(comp / (plain["fill_ms"] * 1e-3) / 1e9, 1)
+    plain["copy_GBps"] = round(2 * comp / (plain["copy_ms"] * 1e-3) / 1e9, 1)
+    return {"side": side, "stride_bytes": stride, "rows": rows, "plain": plain}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -309,6 +429,14 @@ def main(argv=None):
     f.add_argument("--n", type=int, default=32)
     f.add_argument("--bands", default="17664,8192,4096,1024")
     f.add_argument("--out", default=None)
+    g = sub.add_parser("member-layout")
+    g.add_argument("--pads", default=None, help="comma-separated pads in bytes")
+    g.add_argument("--reps", type=int, default=10)
+    g.add_argument("--out", default=None)
+    w = sub.add_parser("write-mix")
+    w.add_argument("--ns", default="16,64,128")
+    w.add_argument("--pad", type=int, default=0)
+    w.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     if args.cmd == "repack-sweep":
         res = repack_sweep(args.lo, args.hi, args.step, args.reps)
@@ -322,6 +450,15 @@ def main(argv=None):
         print(json.dumps(res["summary"]))
     elif args.cmd == "subdivide":
         res = subdivide_table(args.n, bands=tuple(int(x) for x in args.bands.split(",")))
+        print(json.dumps(res))
+    elif args.cmd == "member-layout":
+        kw = {"reps": args.reps}
+        if args.pads:
+            kw["pads"] = tuple(int(x) for x in args.pads.split(","))
+        res = member_layout(**kw)
+        print(json.dumps(res))
+    elif args.cmd == "write-mix":
+        res = write_mix(tuple(int(x) for x in args.ns.split(",")), pad=args.pad)
         print(json.dumps(res))
     else:
         res = paper_table(tuple(int(x) for x in args.ns.split(",")),

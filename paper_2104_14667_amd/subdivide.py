@@ -23,6 +23,18 @@ import numpy as np
 from .composite import Composite
 
 
+def _page_locked(m) -> bool:
+    """True for a torch tensor in page-locked host memory; False for anything
+    else (a numpy array may be pageable, so it is treated as such)."""
+    f = getattr(m, "is_pinned", None)
+    if f is None:
+        return False
+    try:
+        return bool(f())
+    except (RuntimeError, TypeError):
+        return False
+
+
 def composite_banded(host_maps: Sequence, W: int, H: int, band_rows: int,
                      outputs=("count",), count_bits: int = 32, out: Optional[Dict] = None,
                      pinned: bool = False, **opts) -> Dict[str, np.ndarray]:
@@ -30,9 +42,16 @@ def composite_banded(host_maps: Sequence, W: int, H: int, band_rows: int,
     tensors, row-major), computed band by band.  Returns host arrays: those of
     `out` (name -> C-contiguous H x W array of the output's dtype) when given,
     which the copy engine fills directly when `pinned` says they are
-    page-locked, else new pageable ones."""
+    page-locked, else new pageable ones.  Members that are not page-locked
+    torch tensors are uploaded through the library's pinned bounce buffers
+    (opts pageable_host = 1, set here); asking for pageable_host = 0 with such
+    members is an error."""
     if band_rows < 1:
         raise ValueError("band_rows must be >= 1")
+    if not all(_page_locked(m) for m in host_maps):
+        if opts.get("pageable_host", 1) == 0:
+            raise ValueError("pageable_host=0 needs page-locked members (pinned torch tensors)")
+        opts = dict(opts, pageable_host=1)
     for m in host_maps:
         if int(np.prod(m.shape)) != W * H:
             raise ValueError("every member must hold W * H bytes")

@@ -37,7 +37,7 @@ def test_default_opts():
     assert (o.nbuf, o.chunk_depth, o.layout, o.tile_w, o.tile_h) == (2, 8, cb.CMP_LINEAR, 64, 64)
     assert o.copy_stream is None and o.compute_stream is None
     assert C.sizeof(cb.cmp_opts) == 96
-    assert o.host_paced == 1 and o.pageable_host == 0 and o.verify_members == 0 and o.pingpong == 0
+    assert o.host_paced == 0 and o.pageable_host == 0 and o.verify_members == 0 and o.pingpong == 0
 
 
 def test_argument_checks_before_any_device_call():
@@ -115,12 +115,45 @@ def test_tiled_bytes_and_repack_argument_checks():
 
 def test_server_opts_and_stats_layout():
     o = cb.composite_default_server_opts()
-    assert C.sizeof(cb.cmp_server_opts) == 56 and C.sizeof(cb.cmp_server_stats) == 72
+    assert C.sizeof(cb.cmp_server_opts) == 56 and C.sizeof(cb.cmp_server_stats) == 96
     assert (o.max_batch, o.tile_vecs, o.blocks_per_cu, o.overlap) == (64, 256, 0, 1)
     assert o.remat_max_members == 2048 and o.hbm_budget_bytes == 16 << 30
+    assert (o.count_bits, o.oversubscribe_pct, o.max_queue) == (32, 0, 1024)
     assert cb.lib.composite_server_create(None, None, None) == cb.CMP_EINVAL
     h = C.c_void_p()
     assert cb.lib.composite_server_create(C.byref(h), None, C.byref(o)) == cb.CMP_EINVAL
+
+
+def test_server_argument_checks_before_any_device_call():
+    """Options are checked before the pool is touched, and every served call
+    refuses a NULL server or bad arguments without side effects."""
+    h = C.c_void_p(1234)
+    fake_pool = C.c_void_p(8)          # never dereferenced: the options fail first
+    for field, bad in (("count_bits", 24), ("count_bits", 0), ("oversubscribe_pct", -1),
+                       ("max_queue", 0), ("max_batch", 0), ("max_batch", 4097),
+                       ("hbm_budget_bytes", 0), ("overlap", 2), ("remat_max_members", 65536),
+                       ("tile_vecs", 63), ("blocks_per_cu", 17)):
+        o = cb.composite_default_server_opts()
+        setattr(o, field, bad)
+        assert cb.lib.composite_server_create(C.byref(h), fake_pool, C.byref(o)) == cb.CMP_EINVAL, field
+        assert h.value is None
+        h = C.c_void_p(1234)
+    o = cb.composite_default_server_opts()
+    o.reserved[1] = 1
+    assert cb.lib.composite_server_create(C.byref(h), fake_pool, C.byref(o)) == cb.CMP_EINVAL
+    sid = C.c_int64()
+    t = C.c_uint64()
+    assert cb.lib.composite_session_open(None, C.byref(sid)) == cb.CMP_EINVAL
+    assert cb.lib.composite_session_close(None, 1) == cb.CMP_EINVAL
+    assert cb.lib.composite_session_submit(None, 1, 0, None, 0, 0, 0, 1, 1, None, 1,
+                                           C.byref(t)) == cb.CMP_EINVAL
+    assert cb.lib.composite_session_wait(None, 1, 0, None, None) == cb.CMP_EINVAL
+    assert cb.lib.composite_server_pause(None, 1) == cb.CMP_EINVAL
+    assert cb.lib.composite_server_stats(None, None) == cb.CMP_EINVAL
+    lat = (C.c_int64 * 1)()
+    assert cb.lib.composite_server_replay(None, None, 1, None, None, 1, 16, lat, None) == cb.CMP_EINVAL
+    cb.lib.composite_server_free(None)
+    assert cb.composite_strerror(cb.CMP_ECANCELED).startswith("not attempted")
 
 
 def test_ceiling_library_checks_arguments():
@@ -134,7 +167,7 @@ def test_ceiling_library_checks_arguments():
     ms = C.c_float()
     ok = dict(members=16, stride=64, n=2, npix=64, count=16, sum=16, max=16, rmw=1, reps=3)
     bads = [dict(members=None), dict(n=0), dict(npix=40), dict(stride=32), dict(reps=1),
-            dict(count=None), dict(npix=1 << 33, stride=1 << 33), dict(rmw=3), dict(rmw=-1)]
+            dict(count=None), dict(npix=1 << 33, stride=1 << 33), dict(rmw=6), dict(rmw=-1)]
     for bad in bads:
         a = dict(ok, **bad)
         rc = f(a["members"], a["stride"], a["n"], a["npix"], a["count"], a["sum"], a["max"],

@@ -8,8 +8,9 @@ import torch
 
 import oracle
 from paper_2104_14667_amd import synth
-from paper_2104_14667_amd.composite import (CMP_EINVAL, CMP_ENOTMEMBER, CMP_OP_ADD,
-                                            CMP_OP_REMOVE, CompositeError, Pool, Server)
+from paper_2104_14667_amd.composite import (CMP_EBUSY, CMP_EINVAL, CMP_ENOMEM, CMP_ENOTMEMBER,
+                                            CMP_ERANGE, CMP_OP_ADD, CMP_OP_REMOVE, CompositeError,
+                                            Pool, Server)
 
 from gpu_common import say
 
@@ -58,19 +59,24 @@ def _check_alone(wl, stack, sched, outs):
 
 # remat: 0 copies every evicted non-empty composite to host memory and back, 65535
 # drops and rebuilds every one, 4 drops sessions of at most 4 members only
-# bpc: persistent workgroups per CU, or 0 for one workgroup per work item
-@pytest.mark.parametrize("max_batch,overlap,budget_slots,remat,bpc", [
-    (1, 0, 8, 0, 2), (4, 1, 4, 0, 2), (64, 1, 64, 512, 2), (3, 0, 3, 65535, 2), (8, 1, 10, 4, 2),
-    (4, 1, 4, 512, 2), (1, 0, 3, 4, 2), (64, 1, 64, 512, 0), (4, 1, 4, 65535, 0)])
-def test_mix_equals_alone(max_batch, overlap, budget_slots, remat, bpc):
-    wl, stack, sched = _small(seed=max_batch + 10 * overlap + remat % 7)
+# bpc: persistent workgroups per CU, or 0 for one workgroup per work item;
+# cb: bits of the session composites.  Budgets below the 5 sessions admit
+# them by oversubscription (they live by eviction)
+@pytest.mark.parametrize("max_batch,overlap,budget_slots,remat,bpc,cb", [
+    (1, 0, 8, 0, 2, 32), (4, 1, 4, 0, 2, 32), (64, 1, 64, 512, 2, 32), (3, 0, 3, 65535, 2, 32),
+    (8, 1, 10, 4, 2, 32), (4, 1, 4, 512, 2, 32), (1, 0, 3, 4, 2, 32), (64, 1, 64, 512, 0, 32),
+    (4, 1, 4, 65535, 0, 32), (4, 1, 4, 0, 2, 16), (3, 0, 3, 65535, 2, 16), (64, 1, 64, 512, 0, 16),
+    (8, 1, 10, 4, 2, 16)])
+def test_mix_equals_alone(max_batch, overlap, budget_slots, remat, bpc, cb):
+    wl, stack, sched = _small(seed=max_batch + 10 * overlap + remat % 7 + cb)
     P, H, W = stack.shape
-    say("serve mix", max_batch, overlap, budget_slots, remat, bpc)
+    say("serve mix", max_batch, overlap, budget_slots, remat, bpc, cb)
     buf = _pool(stack)
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=max_batch, overlap=overlap,
-                    hbm_budget_bytes=budget_slots * H * W * 4, max_view_pixels=16 * 16,
-                    tile_vecs=64, blocks_per_cu=bpc, remat_max_members=remat) as srv:
+                    hbm_budget_bytes=budget_slots * H * W * cb // 8, max_view_pixels=16 * 16,
+                    tile_vecs=64, blocks_per_cu=bpc, remat_max_members=remat, count_bits=cb,
+                    oversubscribe_pct=100) as srv:
             sids, outs = _run_mix(srv, wl, sched)
             st = srv.stats()
             assert st["requests"] == len(sched)
@@ -135,7 +141,8 @@ def test_heavy_requests_automatic_launch(bpc):
     buf = _pool(stack)
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=2, overlap=1, hbm_budget_bytes=2 * H * W * 4,
-                    max_view_pixels=16 * 16, tile_vecs=64, blocks_per_cu=bpc) as srv:
+                    max_view_pixels=16 * 16, tile_vecs=64, blocks_per_cu=bpc,
+                    oversubscribe_pct=100) as srv:
             sids, outs = _run_mix(srv, wl, sched)
             assert srv.stats()["requests"] == len(sched)
     _check_alone(wl, stack, sched, outs)
@@ -156,14 +163,15 @@ def test_replay_small_open_loop():
             assert srv.stats()["requests"] == len(sched)
 
 
-@pytest.mark.parametrize("remat", [2048, 0])
-def test_full_served_shape_bursts(remat):
+@pytest.mark.parametrize("remat,cb", [(2048, 32), (0, 32), (0, 16)])
+def test_full_served_shape_bursts(remat, cb):
     """Sessions of 4096x4096 over a pool of 1024 depth maps, half of them
-    resident; bursts of 64 requests are checked against the closed form of
-    each session's ids.  Evicted composites are rebuilt from their members
-    (remat 2048) or copied to host memory and back (remat 0)."""
+    resident (admitted by oversubscription); bursts of 64 requests are checked
+    against the closed form of each session's ids.  Evicted composites are
+    rebuilt from their members (remat 2048) or copied to host memory and back
+    (remat 0); uint32 or uint16 composites."""
     wl = synth.SERVED
-    say("full served", wl.name, remat)
+    say("full served", wl.name, remat, cb)
     e = wl.elevation()
     lv = wl.levels()
     et = torch.from_numpy(e).cuda()
@@ -175,8 +183,8 @@ def test_full_served_shape_bursts(remat):
     sched = wl.schedule(256)
     held = [[] for _ in range(wl.sessions)]
     with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
-        with Server(pool, max_batch=64, hbm_budget_bytes=128 * plane * 4,
-                    remat_max_members=remat) as srv:
+        with Server(pool, max_batch=64, hbm_budget_bytes=128 * plane * cb // 8,
+                    remat_max_members=remat, count_bits=cb, oversubscribe_pct=100) as srv:
             sids = [srv.open() for _ in range(wl.sessions)]
             for b0 in range(0, len(sched), 64):
                 burst = sched[b0:b0 + 64]
@@ -254,3 +262,167 @@ def test_threaded_submitters_and_close_semantics():
         srv.close()                          # drains every submitted request
         assert closed in (True, False)
     _check_alone(wl, stack, sched, outs)
+
+
+def _expect_view(stack, held, r):
+    """The oracle's count over the window of the members held (id -> multiplicity)."""
+    x0, y0, w, h = r["vx0"], r["vy0"], r["vw"], r["vh"]
+    crops = (oracle.window(stack[i], x0, y0, w, h) for i, k in held.items() for _ in range(k))
+    return oracle.accumulate(crops, shape=(h, w), outputs=("count",))["count"]
+
+
+@pytest.mark.parametrize("cb,pct", [(32, 0), (16, 0), (32, 100)])
+def test_admission_refuses_with_state_unchanged(cb, pct):
+    """The HBM budget holds 3 composites: sessions beyond 3 (plus pct percent
+    by oversubscription) are refused with CMP_ENOMEM, nothing changes, the
+    admitted sessions still serve exact viewports, and a close makes room."""
+    wl, stack, sched = _small(seed=31, sessions=3, n=40)
+    P, H, W = stack.shape
+    say("serve admission", cb, pct)
+    buf = _pool(stack)
+    limit = 3 + 3 * pct // 100
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=2, hbm_budget_bytes=3 * H * W * cb // 8 + H * W * cb // 16,
+                    max_view_pixels=256, tile_vecs=64, count_bits=cb, oversubscribe_pct=pct) as srv:
+            sids = [srv.open() for _ in range(limit)]
+            st0 = srv.stats()
+            for k in range(2):
+                with pytest.raises(CompositeError) as ei:
+                    srv.open()
+                assert ei.value.status == CMP_ENOMEM
+                assert srv.try_open() is None
+            st1 = srv.stats()
+            assert st1["refused_sessions"] == st0["refused_sessions"] + 4
+            assert {k: v for k, v in st1.items() if k != "refused_sessions"} == \
+                   {k: v for k, v in st0.items() if k != "refused_sessions"}
+            # every admitted session serves, in the mix, what it serves alone
+            outs = []
+            for r in sched:
+                dst = torch.full((r["vh"], r["vw"]), -1, dtype=torch.int32, pin_memory=True)
+                op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
+                outs.append((srv.submit(sids[r["sid"]], op, r["ids"],
+                                        (r["vx0"], r["vy0"], r["vw"], r["vh"]), dst), dst))
+            for t, _ in outs:
+                srv.wait(t)
+            _check_alone(wl, stack, sched, [d for _, d in outs])
+            srv.close_session(sids[0])
+            sid = srv.open()                                   # room again
+            assert sid not in sids
+            with pytest.raises(CompositeError) as ei:
+                srv.open()
+            assert ei.value.status == CMP_ENOMEM
+            dst = torch.full((16, 16), -1, dtype=torch.int32, pin_memory=True)
+            srv.wait(srv.submit(sid, CMP_OP_ADD, [0, 1], (0, 0, 16, 16), dst))
+            held = {0: 1, 1: 1}
+            exp = _expect_view(stack, held, dict(vx0=0, vy0=0, vw=16, vh=16))
+            assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64), exp)
+
+
+def test_queue_bound_refuses_busy_with_state_unchanged():
+    """With the server paused, max_queue requests wait; the next submit is
+    refused with CMP_EBUSY and changes nothing (its ids are not held
+    afterwards); after resuming every accepted request completes exactly."""
+    wl, stack, sched = _small(seed=41, sessions=2, n=4)
+    P, H, W = stack.shape
+    say("serve queue bound")
+    buf = _pool(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=2, hbm_budget_bytes=4 * H * W * 4, max_view_pixels=256,
+                    tile_vecs=64, max_queue=4) as srv:
+            a, b = srv.open(), srv.open()
+            srv.pause(True)
+            plan = [(a, CMP_OP_ADD, [1, 2]), (b, CMP_OP_ADD, [3]), (a, CMP_OP_ADD, [4]),
+                    (b, CMP_OP_REMOVE, [3])]
+            views, tickets = [], []
+            for sid, op, ids in plan:
+                dst = torch.full((16, 16), -1, dtype=torch.int32, pin_memory=True)
+                tickets.append(srv.submit(sid, op, ids, (0, 0, 16, 16), dst))
+                views.append(dst)
+            spare = torch.full((16, 16), -7, dtype=torch.int32, pin_memory=True)
+            with pytest.raises(CompositeError) as ei:
+                srv.submit(a, CMP_OP_ADD, [5], (0, 0, 16, 16), spare)
+            assert ei.value.status == CMP_EBUSY
+            st = srv.stats()
+            assert st["refused_busy"] == 1 and st["queue_peak"] == 4 and st["requests"] == 0
+            srv.pause(False)
+            for t in tickets:
+                srv.wait(t)
+            assert (spare.numpy() == -7).all()                 # never written
+            with pytest.raises(CompositeError) as ei:          # 5 was never added
+                srv.submit(a, CMP_OP_REMOVE, [5], (0, 0, 16, 16), spare)
+            assert ei.value.status == CMP_ENOTMEMBER
+            held = {a: {}, b: {}}
+            for (sid, op, ids), dst in zip(plan, views):
+                for i in ids:
+                    held[sid][i] = held[sid].get(i, 0) + (1 if op == CMP_OP_ADD else -1)
+                exp = _expect_view(stack, held[sid], dict(vx0=0, vy0=0, vw=16, vh=16))
+                assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64), exp)
+            assert srv.stats()["requests"] == len(plan)
+
+
+def test_uint16_sessions_at_their_limit():
+    """A uint16 session holds up to 65535 members: 65535 copies of one raster
+    give 65535 where it is nonzero; one more member is refused with
+    CMP_ERANGE and changes nothing; after a remove it is accepted."""
+    rng = np.random.default_rng(5)
+    P, H, W = 3, 2, 32
+    stack = rng.integers(0, 3, size=(P, H, W), dtype=np.uint8)
+    say("serve u16 limit")
+    buf = _pool(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=1, hbm_budget_bytes=H * W * 2, max_view_pixels=H * W,
+                    tile_vecs=64, count_bits=16) as srv:
+            sid = srv.open()
+            dst = torch.full((H, W), -1, dtype=torch.int32, pin_memory=True)
+            vp = (0, 0, W, H)
+            srv.wait(srv.submit(sid, CMP_OP_ADD, [0] * 65535, vp, dst))
+            held = {0: 65535}
+            assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64),
+                                  _expect_view(stack, held, dict(vx0=0, vy0=0, vw=W, vh=H)))
+            with pytest.raises(CompositeError) as ei:
+                srv.submit(sid, CMP_OP_ADD, [1], vp, dst)
+            assert ei.value.status == CMP_ERANGE
+            srv.wait(srv.submit(sid, CMP_OP_REMOVE, [0], vp, dst))
+            srv.wait(srv.submit(sid, CMP_OP_ADD, [1], vp, dst))
+            held = {0: 65534, 1: 1}
+            assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64),
+                                  _expect_view(stack, held, dict(vx0=0, vy0=0, vw=W, vh=H)))
+            with pytest.raises(CompositeError) as ei:
+                srv.submit(sid, CMP_OP_ADD, [2], vp, dst)
+            assert ei.value.status == CMP_ERANGE
+
+
+def test_replay_records_refusals_and_goes_on():
+    """An open-loop replay into a server whose queue holds one request: some
+    submits are refused (CMP_EBUSY, or CMP_ENOTMEMBER for removes of ids only
+    a refused add would have held); the replay records them and goes on, and
+    the final composite of every session equals the members of its accepted
+    requests."""
+    wl, stack, sched = _small(seed=51, sessions=4, n=200)
+    P, H, W = stack.shape
+    say("serve replay refusals")
+    buf = _pool(stack)
+    ring = [torch.zeros((16, 16), dtype=torch.int32, pin_memory=True) for _ in range(8)]
+    sched = [dict(r, t=r["t"] * 0.01) for r in sched]          # a burst: 200 requests in ~1 ms
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=1, overlap=0, hbm_budget_bytes=4 * H * W * 4,
+                    max_view_pixels=H * W, tile_vecs=64, max_queue=1) as srv:
+            sids = [srv.open() for _ in range(wl.sessions)]
+            lat, status = srv.replay(sched, sids, ring, 16, with_status=True)
+            ok = status == 0
+            assert ok.any() and (~ok).any()
+            assert set(status[~ok].tolist()) <= {CMP_EBUSY, CMP_ENOTMEMBER}
+            assert (lat[ok] > 0).all() and (lat[~ok] == -1).all()
+            st = srv.stats()
+            assert st["requests"] == int(ok.sum())
+            assert st["refused_busy"] == int((status == CMP_EBUSY).sum())
+            dst = torch.full((H, W), -1, dtype=torch.int32, pin_memory=True)
+            for k, sid in enumerate(sids):
+                held = {}
+                for r, good in zip(sched, ok):
+                    if good and r["sid"] == k:
+                        for i in r["ids"]:
+                            held[int(i)] = held.get(int(i), 0) + (1 if r["op"] == "add" else -1)
+                srv.wait(srv.submit(sid, CMP_OP_ADD, [], (0, 0, W, H), dst))
+                exp = _expect_view(stack, held, dict(vx0=0, vy0=0, vw=W, vh=H))
+                assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64), exp), k

@@ -21,7 +21,8 @@ class FakeContext:
     def __init__(self, W, h, outputs, bits, **opts):
         FakeContext.count += 1
         self.id, self.h, self.busy, self.closed = FakeContext.count, h, False, False
-        self._log("new", h)
+        self.opts = opts
+        self._log("new", h, opts.get("pageable_host"))
 
     def _log(self, *what):
         with FakeContext.lock:
@@ -63,6 +64,7 @@ def test_two_contexts_per_height_in_turn(fake):
     out = sd.composite_banded([np.zeros(W * H, np.uint8)] * 2, W, H, 10, ("count", "max"))
     news = [e for e in fake.log if e[1] == "new"]
     assert [e[2] for e in news] == [10, 10, 3]      # two full-height contexts, one for the tail
+    assert [e[3] for e in news] == [1, 1, 1]        # numpy members: through pinned bounce buffers
     # band b is written by context 1 + (b % 2), the tail by the third
     assert [int(out["count"][y, 0]) for y in range(0, H, 10)] == [1, 2, 1, 2, 1, 3]
     assert np.array_equal(out["max"], out["count"].astype(np.uint8))
@@ -93,3 +95,13 @@ def test_argument_checks(fake):
         sd.composite_banded([np.zeros(16, np.uint8)], 4, 4, 2,
                             out={"count": np.zeros((4, 4), np.uint16)})  # wrong dtype
     assert fake.log == []
+
+
+def test_pageable_members_use_bounce_buffers(fake):
+    """numpy members are uploaded with pageable_host = 1; asking for direct
+    copies (pageable_host = 0) from them is refused before any context."""
+    with pytest.raises(ValueError, match="page-locked"):
+        sd.composite_banded([np.zeros(16, np.uint8)], 4, 4, 2, pageable_host=0)
+    assert fake.log == []
+    sd.composite_banded([np.zeros(16, np.uint8)], 4, 4, 4, pageable_host=1)
+    assert [e[3] for e in fake.log if e[1] == "new"] == [1]
