@@ -27,9 +27,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer: only the host
+# pass is instrumented (device code is compiled as usual).  The result is a
+# CPU test build of the same sources, loaded with the sanitizer runtime
+# preloaded; nothing on the device path uses it.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-g"]
+SAN_DIR = os.path.join(BUILD, "hostsan")
+
+
+def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
@@ -52,6 +62,37 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+def build_host_sanitized(verbose: bool = False) -> str:
+    """libcomposite.so with ASan and UBSan in its host code, under
+    _build/hostsan/ (run it with the clang ASan runtime preloaded)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(lambda s: _compile(s, SAN_DIR, SAN_FLAGS), SOURCES))
+    out = os.path.join(SAN_DIR, "libcomposite.so")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", out, *objs, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{r.stderr}")
+    if verbose:
+        print(f"built {out}")
+    return out
+
+
+def sanitizer_runtime() -> str:
+    """Path of the clang ASan runtime that matches hipcc's compiler."""
+    r = subprocess.run([os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin",
+                        "clang"), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isfile(path):
+        raise RuntimeError("clang ASan runtime not found")
+    return path
+
+
 if __name__ == "__main__":
+    if "--host-sanitize" in sys.argv:
+        build_host_sanitized(verbose=True)
+        sys.exit(0)
     build(verbose=True)
     sys.exit(0)

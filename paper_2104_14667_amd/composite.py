@@ -16,7 +16,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcomposite.so")
+# COMPOSITE_LIBRARY names another build of the same sources (the host-side
+# sanitizer build of the CPU tests); by default the in-tree library is loaded.
+LIB_PATH = os.environ.get("COMPOSITE_LIBRARY") or os.path.join(_HERE, "libcomposite.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "composite.h")
 
 CMP_OK, CMP_EINVAL, CMP_ENOMEM, CMP_ERANGE, CMP_ENOTMEMBER = 0, -1, -2, -3, -4

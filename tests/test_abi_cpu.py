@@ -159,8 +159,8 @@ def test_server_argument_checks_before_any_device_call():
 def test_ceiling_library_checks_arguments():
     """The benchmark's same-traffic reference kernel (libceiling.so) rejects
     bad arguments before any device call."""
-    import os
-    lib = C.CDLL(os.path.join(os.path.dirname(cb.LIB_PATH), "libceiling.so"))
+    from paper_2104_14667_amd import ceiling
+    lib = C.CDLL(ceiling.LIB_PATH)
     f = lib.traffic_ceiling
     f.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
                   C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_float)]
