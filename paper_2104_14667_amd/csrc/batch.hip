@@ -786,7 +786,7 @@ int64_t shared_lds_bytes(int64_t count, int S) {
 // Slots per pass the shared mode can use on this pool (0: not usable).
 int shared_slots(const cmp_pool *p) {
   if (p->count > 65536) return 0;
-  const int64_t room = (int64_t)p->max_lds - 512 - shared_lds_bytes(p->count, 0);
+  const int64_t room = (int64_t)p->max_lds - p->static_lds_shared - shared_lds_bytes(p->count, 0);
   const int64_t S = std::min<int64_t>(kShMaxSlots, room / (kShTpb * kShPx));
   return S >= 4 ? (int)S : 0;
 }
@@ -859,6 +859,15 @@ void composite_default_tune(cmp_tune *t) {
   t->slots = 24;
 }
 
+// The larger static LDS of two instances of a kernel, in bytes.
+static hipError_t static_lds(const void *f1, const void *f2, int *bytes) {
+  hipFuncAttributes a{}, b{};
+  hipError_t e = hipFuncGetAttributes(&a, f1);
+  if (e == hipSuccess) e = hipFuncGetAttributes(&b, f2);
+  if (e == hipSuccess) *bytes = (int)std::max(a.sharedSizeBytes, b.sharedSizeBytes);
+  return e;
+}
+
 int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count, int32_t W,
                           int32_t H, int64_t stride_bytes, int64_t pool_bytes, int32_t device) {
   if (!out) return CMP_EINVAL;
@@ -887,7 +896,16 @@ int composite_pool_create(cmp_pool **out, const uint8_t *dev_base, int64_t count
       break;
     if (hipDeviceGetAttribute(&p->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
       break;
-    p->max_lds_matrix = p->max_lds - 1024;  // the kernel's static LDS
+    // the dynamic LDS a mode may ask for is what a workgroup may use less the
+    // kernels' static LDS, as the compiler laid it out
+    int st_mx = 0, st_sh = 0;
+    if (static_lds((const void *)k_matrix<true, kMxWaves>, (const void *)k_matrix<false, kMxWaves>,
+                   &st_mx) != hipSuccess ||
+        static_lds((const void *)k_shared<true, kShTpb, kShPx>,
+                   (const void *)k_shared<false, kShTpb, kShPx>, &st_sh) != hipSuccess)
+      break;
+    p->max_lds_matrix = p->max_lds - st_mx;
+    p->static_lds_shared = st_sh;
     if (const int S = shared_slots(p)) {
       // allow k_shared its dynamic LDS (beyond the default per-launch limit)
       const int lds = (int)shared_lds_bytes(p->count, S);

@@ -14,6 +14,7 @@ struct cmp_pool {
   int cus = 0;
   int max_lds = 0;  // LDS bytes a workgroup may use (0: shared mode unavailable)
   int max_lds_matrix = 0;  // dynamic LDS k_matrix may use (0: matrix mode unavailable)
+  int static_lds_shared = 0;  // static LDS of the k_shared instances, as compiled
   bool poisoned = false;
   hipStream_t s = nullptr;
   char *d_arena = nullptr, *h_arena = nullptr;

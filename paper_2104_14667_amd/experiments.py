@@ -44,6 +44,11 @@
   average launch time (HIP events) and the same-traffic reference kernel's
   best time on the same placement.  With pad 0 the same pixel of every member
   lies exactly 64 MiB apart.
+* ``pool-layout``: the batched workload (64 crop requests over a pool of 2048
+  masks of 2048x2048) with the pool's rasters at a stride of 2048^2 + pad
+  bytes, for several pads: the median device time of the library's default
+  tune (matrix mode, graph replay), every output checked against its closed
+  form.  With pad 0 the same pixel of every raster lies exactly 4 MiB apart.
 * ``write-mix``: what the composite's read and write cost next to n member
   streams: the same-traffic reference kernel over n members of 8192x8192 with
   member reads only, plus the 9 B/px composite read, plus its write, plus both
@@ -51,7 +56,8 @@
   composite bytes (torch) for scale.
 
 Usage: python -m paper_2104_14667_amd.experiments
-           {repack-sweep,paper-table,kernel-table,h2d-sweep,subdivide,member-layout,write-mix}
+           {repack-sweep,paper-table,kernel-table,h2d-sweep,subdivide,member-layout,
+            pool-layout,write-mix}
            [--out FILE]
 """
 
@@ -362,6 +368,50 @@ def member_layout(pads=(0, 4096, 65536, 2 << 20, (2 << 20) + 4096, 64 << 20), n=
     return {"n": n, "side": side, "reps": reps, "algorithmic_bytes_per_launch": algo, "rows": rows}
 
 
+def pool_layout(pads=(0, 4096, 65536, 1 << 20, (1 << 20) + 4096, 4 << 20), reps=10) -> dict:
+    import torch
+
+    from . import synth
+    from .composite import CMP_BATCH_MATRIX, Pool
+    wl = synth.BATCHED
+    e = wl.elevation()
+    lv = wl.levels()
+    et = torch.from_numpy(e).to("cuda:0")
+    plane = wl.H * wl.W
+    buf = torch.empty(wl.pool * (plane + max(pads)) + 64, dtype=torch.uint8, device="cuda:0")
+    reqs = wl.requests()
+    for r in reqs:
+        r["out"] = torch.empty((r["h"], r["w"]), dtype=torch.int32, device="cuda:0")
+    exp = []
+    for r in reqs:
+        lvs = np.sort(lv[r["ids"]])
+        ec = e[r["y0"]:r["y0"] + r["h"], r["x0"]:r["x0"] + r["w"]]
+        exp.append(len(lvs) - np.searchsorted(lvs, ec, side="right"))
+    rows = []
+    for pad in pads:
+        stride = plane + pad
+        for i, L in enumerate(lv):
+            synth.member_torch(et, int(L), "mask", out=buf[i * stride:i * stride + plane].view(wl.H, wl.W))
+        torch.cuda.synchronize()
+        with Pool(buf, wl.pool, wl.W, wl.H, stride, buf.numel()) as pool:
+            ms = []
+            for _ in range(reps + 1):
+                for r in reqs:
+                    r["out"].fill_(-1)
+                pool.run(reqs)
+                ms.append(pool.last()[0])
+            mode = pool.last()[2]
+            exact = all(np.array_equal(r["out"].cpu().numpy().view(np.uint32), x)
+                        for r, x in zip(reqs, exp))
+        d = np.array(ms[1:])
+        rows.append({"pad_bytes": pad, "stride_bytes": stride, "matrix_mode": mode == CMP_BATCH_MATRIX,
+                     "device_ms_median": round(float(np.median(d)), 4),
+                     "device_ms_min": round(float(d.min()), 4), "device_ms_max": round(float(d.max()), 4),
+                     "exact": exact})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"pool": wl.pool, "W": wl.W, "H": wl.H, "requests": len(reqs), "reps": reps, "rows": rows}
+
+
 def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
     import torch
 
@@ -433,6 +483,10 @@ def main(argv=None):
     g.add_argument("--pads", default=None, help="comma-separated pads in bytes")
     g.add_argument("--reps", type=int, default=10)
     g.add_argument("--out", default=None)
+    pl = sub.add_parser("pool-layout")
+    pl.add_argument("--pads", default=None, help="comma-separated pads in bytes")
+    pl.add_argument("--reps", type=int, default=10)
+    pl.add_argument("--out", default=None)
     w = sub.add_parser("write-mix")
     w.add_argument("--ns", default="16,64,128")
     w.add_argument("--pad", type=int, default=0)
@@ -456,6 +510,12 @@ def main(argv=None):
         if args.pads:
             kw["pads"] = tuple(int(x) for x in args.pads.split(","))
         res = member_layout(**kw)
+        print(json.dumps(res))
+    elif args.cmd == "pool-layout":
+        kw = {"reps": args.reps}
+        if args.pads:
+            kw["pads"] = tuple(int(x) for x in args.pads.split(","))
+        res = pool_layout(**kw)
         print(json.dumps(res))
     elif args.cmd == "write-mix":
         res = write_mix(tuple(int(x) for x in args.ns.split(",")), pad=args.pad)
