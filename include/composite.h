@@ -183,14 +183,18 @@ int composite_add(cmp_ctx *ctx, const uint8_t *const *host_maps,
                   const int64_t *ids, int32_t n);
 
 /* Composites n members that are already in device memory (one kernel pass over
- * all of them, no staging).  dev_maps[i]: device pointers to W*H bytes, any
+ * all of them, no staging): the accumulation kernel step of the paper's two
+ * listings (Section 4) with the load from client memory left out, as for data
+ * already resident on the device.  dev_maps[i]: device pointers to W*H bytes, any
  * alignment (in a CMP_TILED context: to the tiled layout, see cmp_layout).  The rasters must stay valid until composite_sync returns, and,
  * with retain_members, for as long as they are members.  Returns without
  * waiting for the device. */
 int composite_add_device(cmp_ctx *ctx, const uint8_t *const *dev_maps,
                          const int64_t *ids, int32_t n);
 
-/* Removes n members: count and sum are decremented exactly; max, when
+/* Removes n members, the counterpart of adding one: surfaces are added and
+ * removed in real time and the composite follows (Figure 1 and its caption;
+ * the paper names no mechanism).  Count and sum are decremented exactly; max, when
  * selected, is recomputed from the retained members (retain_members = 1 and
  * every member added with composite_add_device), else CMP_EUNSUPPORTED.
  * maps: the rasters removed (host memory if maps_on_device == 0, else device
@@ -214,10 +218,13 @@ int composite_read(cmp_ctx *ctx, uint32_t which, int32_t x0, int32_t y0,
                    int32_t w, int32_t h, void *dst, int64_t dst_pitch_bytes,
                    int32_t dst_kind);
 
-/* Waits for all work enqueued on the context. */
+/* Waits for all work enqueued on the context: the end of the listings'
+ * loop (Section 4), after which the accumulators hold the composite of every
+ * member (the point where the paper's timing stops, Section 5.1). */
 int composite_sync(cmp_ctx *ctx);
 
-/* Number of members currently composited (with multiplicity). */
+/* Number of members currently composited (with multiplicity): the N of the
+ * composite, i.e. the length of the list of selected surfaces (Figure 1). */
 int composite_members(const cmp_ctx *ctx, int64_t *n_out);
 
 /* Device address of one output of the composite (row-major, pitch W elements),
@@ -533,8 +540,9 @@ int64_t composite_tiled_bytes(int32_t W, int32_t H, int32_t tile_w, int32_t tile
 /* Static description of a status code; never NULL. */
 const char *composite_strerror(int status);
 
-/* Waits for in-flight work, then releases everything the context owns.
- * NULL is ignored. */
+/* Waits for in-flight work, then releases everything the context owns: the
+ * accumulators and staging buffers of the listings (Section 4), which the
+ * paper keeps for the life of its program.  NULL is ignored. */
 void composite_free(cmp_ctx *ctx);
 
 #ifdef __cplusplus
