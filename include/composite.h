@@ -537,6 +537,31 @@ int composite_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
 /* Bytes of one raster in the tiled layout (edge tiles padded). */
 int64_t composite_tiled_bytes(int32_t W, int32_t H, int32_t tile_w, int32_t tile_h);
 
+/* For callers that cannot allocate memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): composite_add_device
+ * without a context and without any allocation.  It folds n device-resident
+ * members (dev_maps[i]: W*H bytes, row-major, any alignment) into
+ * caller-owned device accumulators: count (uint16 or uint32 per count_bits),
+ * sum (uint32) and max (uint8), each W*H elements, row-major, 16-byte
+ * aligned, for the outputs selected (non-empty OR of cmp_outputs; unselected
+ * pointers are ignored).  set = 1: the accumulators' previous contents are
+ * ignored and the composite of the n members is written, as after
+ * composite_clear (n == 0 writes zeros); set = 0: the members are added to
+ * what they hold.  The caller keeps the totals in range (at most 65535 or
+ * 2^32 - 1 members in a count, 16843009 in a sum).  Enqueued on `stream` (a
+ * hipStream_t, or NULL for the null stream) on the current device; returns
+ * without waiting, and dev_maps may be reused on return.
+ * The member table lives in one fixed device array per GPU of
+ * CMP_STATIC_MAX_MEMBERS pointers (64 KiB) that every call on that GPU
+ * shares: n above it gives CMP_ERANGE.  Calls on one GPU must therefore be
+ * ordered (the same stream, or ordered by the caller); calls that overlap race
+ * on the table.  Returns CMP_EINVAL for bad arguments, CMP_EDEVICE if a
+ * launch fails. */
+#define CMP_STATIC_MAX_MEMBERS 8192
+int composite_accumulate_static(const uint8_t *const *dev_maps, int32_t n, int32_t W, int32_t H,
+                                uint32_t outputs, int32_t count_bits, void *dev_count,
+                                uint32_t *dev_sum, uint8_t *dev_max, int32_t set, void *stream);
+
 /* Static description of a status code; never NULL. */
 const char *composite_strerror(int status);
 

@@ -136,6 +136,8 @@ _SIGS = {
     "composite_histogram": (C.c_int, [_vp, _P(_i64), _i32, _P(_i64)]),
     "composite_repack_tiled": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _i32, _i32, _vp]),
     "composite_tiled_bytes": (C.c_int64, [_i32, _i32, _i32, _i32]),
+    "composite_accumulate_static": (C.c_int, [_P(_vp), _i32, _i32, _i32, _u32, _i32, _vp, _vp, _vp,
+                                              _i32, _vp]),
     "composite_strerror": (C.c_char_p, [C.c_int]),
     "composite_free": (None, [_vp]),
 }
@@ -273,6 +275,22 @@ def composite_repack_tiled(src, src_stride: int, dst, dst_stride: int, n: int, W
     _check(lib.composite_repack_tiled(_ptr(src), int(src_stride), _ptr(dst), int(dst_stride),
                                       int(n), int(W), int(H), int(tile_w), int(tile_h), st),
            "composite_repack_tiled")
+
+
+CMP_STATIC_MAX_MEMBERS = 8192
+
+
+def composite_accumulate_static(dev_maps: Sequence, W: int, H: int, outputs: int, count_bits: int,
+                                dev_count=None, dev_sum=None, dev_max=None, set: bool = True,
+                                stream=None) -> int:
+    """Returns the status (no raise): callers check refusals by code."""
+    st = None if stream is None else (stream if isinstance(stream, int) else int(stream.cuda_stream))
+    n = len(dev_maps)
+    arr = _ptr_array(dev_maps) if n else None
+    return int(lib.composite_accumulate_static(
+        arr, n, int(W), int(H), int(outputs), int(count_bits),
+        None if dev_count is None else _ptr(dev_count), None if dev_sum is None else _ptr(dev_sum),
+        None if dev_max is None else _ptr(dev_max), 1 if set else 0, st))
 
 
 def composite_free(ctx: int) -> None:
