@@ -784,7 +784,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the compositing path "
-              "has no multi-GPU mode in this build.", file=sys.stderr)
+              "runs on a single GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch

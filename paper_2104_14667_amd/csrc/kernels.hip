@@ -335,71 +335,6 @@ hipError_t run_tiled(const uint8_t *const *tab, int n, int64_t nvec, const Tiled
       return c16 ? FN<O, true, true>(__VA_ARGS__) : FN<O, true, false>(__VA_ARGS__); \
     return c16 ? FN<O, false, true>(__VA_ARGS__) : FN<O, false, false>(__VA_ARGS__);
 
-// Linear -> tiled repack, staged through LDS.  A workgroup takes R rows of a
-// 1024-byte-wide block of one raster: the rows r0 .. r0 + R - 1 of the tiles
-// tx0 .. tx0 + 1024 / tw - 1 of tile row ty.  Every wave reads whole 1 KiB row
-// segments of the source into LDS, then writes each tile's R rows, which are
-// contiguous in the tiled layout (R * tw bytes per tile), so that both the
-// reads and the writes are long contiguous runs.  Bytes outside the raster
-// (right and bottom edge tiles) are written as zero.
-constexpr uint32_t kRepackBlockW = 1024;        // bytes of a row per workgroup
-constexpr uint32_t kRepackPitch = kRepackBlockW + 16;  // LDS row pitch: rows start on different banks
-
-struct RepackGeom {
-  uint32_t W, H, tw, th, ntx;
-  uint32_t R;     // rows per workgroup (<= th)
-  uint32_t nsb;   // row groups per tile row: ceil(th / R)
-  uint32_t ncb;   // 1024-byte column blocks: ceil(ntx * tw / 1024)
-};
-
-__global__ __launch_bounds__(256) void k_repack(const uint8_t *__restrict__ src, int64_t src_stride,
-                                                uint8_t *__restrict__ dst, int64_t dst_stride,
-                                                RepackGeom g) {
-  extern __shared__ uint4 lds[];
-  uint8_t *l8 = reinterpret_cast<uint8_t *>(lds);
-  const uint32_t b = blockIdx.x;
-  const uint32_t cb = b % g.ncb, t2 = b / g.ncb;
-  const uint32_t sb = t2 % g.nsb, ty = t2 / g.nsb;
-  const uint32_t r0 = sb * g.R;
-  const uint32_t rows = min(g.R, g.th - r0);
-  const uint32_t y0 = ty * g.th + r0, x0 = cb * kRepackBlockW;
-  const uint8_t *s = src + (int64_t)blockIdx.y * src_stride;
-  // rows x 64 vectors of 16 bytes in
-  for (uint32_t v = threadIdx.x; v < rows * 64u; v += blockDim.x) {
-    const uint32_t r = v >> 6, j = v & 63u;
-    const uint32_t y = y0 + r, x = x0 + 16u * j;
-    uint4 val = make_uint4(0u, 0u, 0u, 0u);
-    if (y < g.H && x < g.W) {
-      const uint32_t off = y * g.W + x;  // < W * H < 2^32
-      if (x + 16u <= g.W) {
-        val = ld16(s, off);
-      } else {
-        // the vector crosses the raster's right edge: bytes past it are
-        // padding (zero) and must not be read
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
-        for (uint32_t k = 0; k < g.W - x; ++k) w[k >> 2] |= (uint32_t)s[off + k] << (8 * (k & 3));
-        val = make_uint4(w[0], w[1], w[2], w[3]);
-      }
-    }
-    *reinterpret_cast<uint4 *>(l8 + r * kRepackPitch + 16u * j) = val;
-  }
-  __syncthreads();
-  // each tile's rows r0 .. r0 + rows - 1 out, contiguous in the tiled layout
-  const uint32_t K = kRepackBlockW / g.tw, vpr = g.tw >> 4;
-  const uint32_t tx0 = cb * K;
-  const uint32_t ktiles = min(K, g.ntx - tx0);
-  const uint32_t per_tile = rows * vpr;
-  uint8_t *d = dst + (int64_t)blockIdx.y * dst_stride;
-  const int64_t tile_bytes = (int64_t)g.tw * g.th;
-  for (uint32_t v = threadIdx.x; v < ktiles * per_tile; v += blockDim.x) {
-    const uint32_t k = v / per_tile, in = v - k * per_tile;
-    const uint32_t r = in / vpr, c = in - r * vpr;
-    const uint4 val = *reinterpret_cast<const uint4 *>(l8 + r * kRepackPitch + k * g.tw + 16u * c);
-    const int64_t o = ((int64_t)ty * g.ntx + tx0 + k) * tile_bytes + (int64_t)(r0 + r) * g.tw + 16u * c;
-    *reinterpret_cast<uint4 *>(d + o) = val;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_fill(uint8_t *__restrict__ p, uint32_t word,
                                               int64_t nvec, int64_t bytes) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -531,31 +466,6 @@ hipError_t launch_composite_tiled(const uint8_t *const *d_tab, int n, const Tili
   const TiledMap map{(uint32_t)t.W, (uint32_t)t.H, (uint32_t)t.tw, (uint32_t)t.th, (uint32_t)t.ntx()};
   const int64_t nvec = t.plane() / 16;
   CMP_DISPATCH(run_tiled, outs, sub, o.count16, d_tab, n, nvec, map, o, s);
-}
-
-hipError_t launch_repack_tiled(const uint8_t *src, int64_t src_stride, uint8_t *dst,
-                               int64_t dst_stride, int n, const Tiling &t, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (t.tw < 16 || t.tw > (int)kRepackBlockW || kRepackBlockW % t.tw || t.tw % 16 || t.th < 1 ||
-      n > 65535)
-    return hipErrorInvalidValue;
-  if ((int64_t)t.W * t.H >= (int64_t(1) << 32) || t.plane() / 16 >= (int64_t(1) << 28))
-    return hipErrorInvalidValue;
-  RepackGeom g;
-  g.W = (uint32_t)t.W;
-  g.H = (uint32_t)t.H;
-  g.tw = (uint32_t)t.tw;
-  g.th = (uint32_t)t.th;
-  g.ntx = (uint32_t)t.ntx();
-  // rows per workgroup: enough that each tile's part is a 1 KiB run, at most 32
-  g.R = std::min<uint32_t>(g.th, std::min<uint32_t>(32u, kRepackBlockW / g.tw));
-  g.nsb = (g.th + g.R - 1) / g.R;
-  g.ncb = (uint32_t)(((int64_t)g.ntx * g.tw + kRepackBlockW - 1) / kRepackBlockW);
-  const int64_t blocks = (int64_t)t.nty() * g.nsb * g.ncb;
-  if (blocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-  dim3 grid((unsigned)blocks, (unsigned)n);
-  k_repack<<<grid, 256, (size_t)g.R * kRepackPitch, s>>>(src, src_stride, dst, dst_stride, g);
-  return hipGetLastError();
 }
 
 hipError_t launch_fill(void *p, uint8_t value, int64_t bytes, hipStream_t s) {

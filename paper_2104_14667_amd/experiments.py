@@ -7,7 +7,9 @@
 * ``paper-table``: the dual- and single-buffer streaming runs of Section 5.1
   at the paper's raster sizes (~2k 1856x2208, ~4k 3712x4416, ~8k 7424x8832)
   and N = 10, 100, 1000, with the efficiency of Section 6.1 (rate over the
-  rate of a plain host-to-device copy of the same bytes in the same pieces).
+  rate of a plain host-to-device copy of the same bytes in the same pieces),
+  from the best of `reps` timed passes after one warm-up pass, with the
+  median and the slowest pass beside it.
   The paper's host kept a small set of images and sent them again (8 GB of
   host memory cannot hold 1000 ~8k images); here a ring of 16 distinct pinned
   rasters is sent round-robin.  Variants: "final" (pinned source, staged
@@ -25,6 +27,14 @@
   two used in turn (pingpong 1).  The paper's image-kernel 2 differs from
   image-kernel 1 only in taking the raster size as kernel arguments, which
   HIP kernels always do, so it is the same kernel here.
+* ``repack-rate``: the linear-to-tiled transform at fixed shapes: the
+  streamed path's chunk (8 rasters of 4096x4096), single rasters of
+  8192x8192, and widths that are and are not multiples of 1024 bytes, each
+  timed with HIP events over `reps` launches on the launch stream.  The rate
+  counts the bytes read (W*H per raster) plus the bytes written (the padded
+  tiled plane).  Every output is compared with the layout's definition (tile
+  (tx, ty) holds rows ty*th .. and bytes tx*tw .. of the raster, row-major,
+  zero past the edges) on sampled tiles.
 * ``h2d-sweep``: the host-to-device copy rate of a plain copy from pinned
   memory as a function of buffer size, 64 KiB to 64 MiB in steps of 64 KiB
   (the copy baseline of Section 6, its buffer-size figure).
@@ -56,8 +66,8 @@
   composite bytes (torch) for scale.
 
 Usage: python -m paper_2104_14667_amd.experiments
-           {repack-sweep,paper-table,kernel-table,h2d-sweep,subdivide,member-layout,
-            pool-layout,write-mix}
+           {repack-sweep,repack-rate,paper-table,kernel-table,h2d-sweep,subdivide,
+            member-layout,pool-layout,write-mix}
            [--out FILE]
 """
 
@@ -101,6 +111,62 @@ def repack_sweep(lo: int, hi: int, step: int, reps: int, tile=(64, 64)) -> dict:
             "seconds": time.perf_counter() - t0, "sides": sides, "rate_GBps": rate.tolist()}
 
 
+REPACK_SHAPES = ((4096, 4096, 8), (8192, 8192, 1), (8192, 8192, 8), (8320, 8192, 1), (8000, 8000, 1),
+                 (16384, 16384, 1), (16000, 16000, 1), (1856, 2208, 8), (7424, 8832, 1))
+
+
+def _tiled_reference(a: np.ndarray, tw: int, th: int, tx: int, ty: int) -> np.ndarray:
+    """Tile (tx, ty) of raster a as the tiled layout defines it."""
+    H, W = a.shape
+    t = np.zeros((th, tw), np.uint8)
+    blk = a[ty * th:(ty + 1) * th, tx * tw:(tx + 1) * tw]
+    t[:blk.shape[0], :blk.shape[1]] = blk
+    return t.reshape(-1)
+
+
+def repack_rate(shapes=REPACK_SHAPES, reps: int = 50, tile=(64, 64), seed: int = 5) -> dict:
+    import torch
+
+    from .composite import composite_repack_tiled, composite_tiled_bytes
+    tw, th = tile
+    rng = np.random.default_rng(seed)
+    s = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    rows = []
+    for W, H, n in shapes:
+        tb = composite_tiled_bytes(W, H, tw, th)
+        src = torch.randint(0, 256, (n, H * W), dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty((n, tb), dtype=torch.uint8, device="cuda:0")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            dst.fill_(0xA5)
+            composite_repack_tiled(src, W * H, dst, tb, n, W, H, tw, th, s)  # warm-up
+            ev[0].record(s)
+            for _ in range(reps):
+                composite_repack_tiled(src, W * H, dst, tb, n, W, H, tw, th, s)
+            ev[1].record(s)
+        ev[1].synchronize()
+        us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+        # sampled tiles of the first and last raster, edge tiles always included
+        ntx, nty = -(-W // tw), -(-H // th)
+        picks = {(ntx - 1, nty - 1), (0, 0), (ntx - 1, 0), (0, nty - 1)}
+        picks |= {(int(rng.integers(ntx)), int(rng.integers(nty))) for _ in range(12)}
+        exact = True
+        for i in sorted({0, n - 1}):
+            a = src[i].view(H, W).cpu().numpy()
+            d = dst[i].cpu().numpy()
+            for tx, ty in picks:
+                o = (ty * ntx + tx) * tw * th
+                exact &= bool(np.array_equal(d[o:o + tw * th], _tiled_reference(a, tw, th, tx, ty)))
+        moved = n * (W * H + tb)
+        rows.append({"W": W, "H": H, "rasters": n, "W_mod_1024": W % 1024, "launch_us": round(us, 2),
+                     "bytes_moved": moved, "GBps": round(moved / (us * 1e-6) / 1e9, 1),
+                     "frac_of_8TBps": round(moved / (us * 1e-6) / 8e12, 4), "exact": exact})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        del src, dst
+    return {"tile": [tw, th], "reps": reps, "rows": rows}
+
+
 def summarize_sweep(res: dict) -> dict:
     r = np.array(res["rate_GBps"])
     sides = np.array(res["sides"])
@@ -117,6 +183,7 @@ def summarize_sweep(res: dict) -> dict:
         for W, c in zip(sides[cols], big.T):
             classes.setdefault(int(W % m), []).append(float(c.mean()))
         out[f"by_W_mod_{m}"] = {k: round(float(np.mean(v)), 1) for k, v in sorted(classes.items())}
+        out[f"std_by_W_mod_{m}"] = {k: round(float(np.std(v)), 1) for k, v in sorted(classes.items())}
     return out
 
 
@@ -139,7 +206,8 @@ def _copy_time(torch, ring, n: int) -> float:
     return best
 
 
-def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k")) -> dict:
+def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"), only=None,
+                reps: int = 5) -> dict:
     import torch
 
     from . import synth
@@ -158,6 +226,8 @@ def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"
             "2b initial": dict(nbuf=2, chunk_depth=1, layout=CMP_TILED, src=pageable, pageable_host=1),
             "2b linear chunk 8": dict(nbuf=2, chunk_depth=8, layout=CMP_LINEAR, src=pinned),
         }
+        if only:
+            variants = {k: v for k, v in variants.items() if k in only}
         for N in Ns:
             copy_s = _copy_time(torch, pinned, N)
             copy_rate = N * W * H / copy_s / 1e9
@@ -167,7 +237,7 @@ def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"
                 maps = [src[i % ring_size] for i in range(N)]
                 times = []
                 with Composite(W, H, ("count",), 32, **kw) as c:
-                    for r in range(3):
+                    for r in range(reps + 1):      # the first pass warms up
                         c.clear()
                         c.sync()
                         t0 = time.perf_counter()
@@ -175,11 +245,13 @@ def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"
                         c.sync()
                         if r:
                             times.append(time.perf_counter() - t0)
-                t = min(times)
+                t, tmed, tmax = min(times), float(np.median(times)), max(times)
                 rate = N * W * H / t / 1e9
-                rows.append({"set": name, "N": N, "alg": vname, "time_us": round(t * 1e6, 1),
+                rows.append({"set": name, "N": N, "alg": vname, "reps": reps, "time_us": round(t * 1e6, 1),
+                             "median_us": round(tmed * 1e6, 1), "max_us": round(tmax * 1e6, 1),
                              "rate_GBps": round(rate, 3), "copy_GBps": round(copy_rate, 3),
-                             "efficiency_pct": round(100 * rate / copy_rate, 2)})
+                             "efficiency_pct": round(100 * rate / copy_rate, 2),
+                             "median_efficiency_pct": round(100 * N * W * H / tmed / 1e9 / copy_rate, 2)})
                 print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     return {"ring": ring_size, "rows": rows}
 
@@ -467,7 +539,12 @@ def main(argv=None):
     b = sub.add_parser("paper-table")
     b.add_argument("--ns", default="10,100,1000")
     b.add_argument("--sizes", default="2k,4k,8k")
+    b.add_argument("--variants", default=None, help="comma-separated variant names (default: all)")
+    b.add_argument("--reps", type=int, default=5)
     b.add_argument("--out", default=None)
+    rr = sub.add_parser("repack-rate")
+    rr.add_argument("--reps", type=int, default=50)
+    rr.add_argument("--out", default=None)
     c = sub.add_parser("kernel-table")
     c.add_argument("--size", default="4k", choices=sorted(PAPER_SIZES))
     c.add_argument("--launches", type=int, default=10000)
@@ -496,6 +573,9 @@ def main(argv=None):
         res = repack_sweep(args.lo, args.hi, args.step, args.reps)
         res["summary"] = summarize_sweep(res)
         print(json.dumps(res["summary"]))
+    elif args.cmd == "repack-rate":
+        res = repack_rate(reps=args.reps)
+        print(json.dumps(res))
     elif args.cmd == "kernel-table":
         res = kernel_table(args.size, args.launches)
         print(json.dumps(res))
@@ -522,7 +602,10 @@ def main(argv=None):
         print(json.dumps(res))
     else:
         res = paper_table(tuple(int(x) for x in args.ns.split(",")),
-                          sizes=tuple(args.sizes.split(",")))
+                          sizes=tuple(args.sizes.split(",")),
+                          only=tuple(args.variants.split(",")) if args.variants else None,
+                          reps=args.reps)
+        print(json.dumps(res))
     if args.out:
         json.dump(res, open(args.out, "w"))
 

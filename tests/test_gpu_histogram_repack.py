@@ -57,7 +57,10 @@ def tiled_reference(a, tw, th):
 
 @pytest.mark.parametrize("W,H,tw,th", [(64, 64, 64, 64), (48, 33, 16, 7), (4096, 9, 128, 4),
                                        (160, 100, 32, 128), (16, 1, 16, 1), (100, 100, 64, 64),
-                                       (1, 1, 16, 1), (4097, 3, 128, 2), (1856, 17, 64, 64)])
+                                       (1, 1, 16, 1), (4097, 3, 128, 2), (1856, 17, 64, 64),
+                                       # tiles taller than one workgroup's 32 rows, the last
+                                       # row group of each tile row partial
+                                       (1100, 70, 16, 40), (2100, 45, 64, 33)])
 def test_repack_matches_layout_definition(W, H, tw, th):
     n = 3
     stack = synth.random_members(W * H, n, H, W)
