@@ -49,9 +49,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(key="traffic_bytes"):
     """HBM bytes per launch of the resident kernel from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
+    summary (traffic_bytes: the one-shot set pass; incremental_traffic_bytes:
+    the read-modify-write pass), or None when the kernel sources changed since
+    it was taken."""
     try:
         kv = {}
         for line in open(TRAFFIC_FILE):
@@ -60,7 +62,7 @@ def measured_traffic():
                 kv[k.strip()] = v.split("#")[0].strip()
         if kv.get("kernel_sources_sha256") != kernel_source_hash():
             return None
-        return int(kv["traffic_bytes"])
+        return int(kv[key])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -869,6 +871,7 @@ def main():
             "algorithmic_bytes_per_launch": inc_bytes,
             "achieved_GBps": round(inc_bytes / inc_kavg_s / 1e9, 1),
             "frac": round(inc_bytes / inc_kavg_s / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("incremental_traffic_bytes"),
             "attainable_GBps": round(inc_bytes / (cl["rmw_ms"] * 1e-3) / 1e9, 1),
             "attainable_frac": round(cl["rmw_ms"] * 1e-3 / inc_kavg_s, 4),
             "exact": inc["exact"]},

@@ -9,7 +9,9 @@
   and N = 10, 100, 1000, with the efficiency of Section 6.1 (rate over the
   rate of a plain host-to-device copy of the same bytes in the same pieces),
   from the best of `reps` timed passes after one warm-up pass, with the
-  median and the slowest pass beside it.
+  median and the slowest pass beside it.  With ``--sample-clocks`` each pass
+  also reports the graphics and memory clock levels it ran at, as far as the
+  driver's sysfs tables are readable.
   The paper's host kept a small set of images and sent them again (8 GB of
   host memory cannot hold 1000 ~8k images); here a ring of 16 distinct pinned
   rasters is sent round-robin.  Variants: "final" (pinned source, staged
@@ -206,13 +208,70 @@ def _copy_time(torch, ring, n: int) -> float:
     return best
 
 
+class ClockSampler:
+    """Samples the current graphics and memory clock levels (the DPM tables
+    the kernel driver exposes in sysfs, where they are readable) every few
+    milliseconds on a thread, so that each timed pass can report the levels it
+    ran at."""
+
+    FILES = ("pp_dpm_sclk", "pp_dpm_mclk", "pp_dpm_fclk", "pp_dpm_socclk")
+
+    def __init__(self, period_s: float = 0.005):
+        import glob
+        import os
+        import threading
+        self.paths = {}
+        for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+            for f in self.FILES:
+                path = os.path.join(dev, f)
+                try:
+                    open(path).read()
+                except OSError:
+                    continue
+                self.paths.setdefault(f, path)
+        self.samples = []
+        self.period = period_s
+        self._stop = threading.Event()
+        self._t = threading.Thread(target=self._run, daemon=True)
+        if self.paths:
+            self._t.start()
+
+    def _run(self):
+        while not self._stop.is_set():
+            row = {"t": time.perf_counter()}
+            for f, path in self.paths.items():
+                try:
+                    cur = [ln for ln in open(path).read().splitlines() if ln.rstrip().endswith("*")]
+                except OSError:
+                    continue
+                if cur:  # "1: 2397Mhz *" -> 2397
+                    row[f] = int("".join(ch for ch in cur[0].split(":")[-1] if ch.isdigit()))
+            self.samples.append(row)
+            time.sleep(self.period)
+
+    def window(self, t0: float, t1: float) -> dict:
+        """min / median / max MHz of each clock over [t0, t1]."""
+        out = {}
+        for f in self.paths:
+            v = [r[f] for r in self.samples if t0 <= r["t"] <= t1 and f in r]
+            if v:
+                out[f] = {"samples": len(v), "min": min(v), "median": float(np.median(v)), "max": max(v)}
+        return out
+
+    def stop(self):
+        self._stop.set()
+        if self._t.is_alive():
+            self._t.join()
+
+
 def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"), only=None,
-                reps: int = 5) -> dict:
+                reps: int = 5, sample_clocks: bool = False) -> dict:
     import torch
 
     from . import synth
     from .composite import CMP_LINEAR, CMP_TILED, Composite
     rows = []
+    clocks = ClockSampler() if sample_clocks else None
     for name in sizes:
         W, H = PAPER_SIZES[name]
         e = synth.elevation(10 + len(name), H, W, 32.0)
@@ -235,7 +294,7 @@ def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"
                 kw = dict(kw)
                 src = kw.pop("src")
                 maps = [src[i % ring_size] for i in range(N)]
-                times = []
+                times, spans = [], []
                 with Composite(W, H, ("count",), 32, **kw) as c:
                     for r in range(reps + 1):      # the first pass warms up
                         c.clear()
@@ -245,6 +304,7 @@ def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"
                         c.sync()
                         if r:
                             times.append(time.perf_counter() - t0)
+                            spans.append((t0, t0 + times[-1]))
                 t, tmed, tmax = min(times), float(np.median(times)), max(times)
                 rate = N * W * H / t / 1e9
                 rows.append({"set": name, "N": N, "alg": vname, "reps": reps, "time_us": round(t * 1e6, 1),
@@ -252,8 +312,15 @@ def paper_table(Ns=(10, 100, 1000), ring_size: int = 16, sizes=("2k", "4k", "8k"
                              "rate_GBps": round(rate, 3), "copy_GBps": round(copy_rate, 3),
                              "efficiency_pct": round(100 * rate / copy_rate, 2),
                              "median_efficiency_pct": round(100 * N * W * H / tmed / 1e9 / copy_rate, 2)})
+                if clocks is not None:
+                    rows[-1]["passes"] = [{"ms": round(1e3 * (b - a), 2),
+                                           "efficiency_pct": round(100 * N * W * H / (b - a) / 1e9 / copy_rate, 2),
+                                           "clocks_MHz": clocks.window(a, b)} for a, b in spans]
                 print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
-    return {"ring": ring_size, "rows": rows}
+    if clocks is not None:
+        clocks.stop()
+    return {"ring": ring_size, "rows": rows,
+            "clock_files": sorted(clocks.paths) if clocks is not None else None}
 
 
 def kernel_table(size: str = "4k", launches: int = 10000, seed: int = 12) -> dict:
@@ -541,6 +608,8 @@ def main(argv=None):
     b.add_argument("--sizes", default="2k,4k,8k")
     b.add_argument("--variants", default=None, help="comma-separated variant names (default: all)")
     b.add_argument("--reps", type=int, default=5)
+    b.add_argument("--sample-clocks", action="store_true",
+                   help="report the clock levels (sysfs DPM tables) seen during each timed pass")
     b.add_argument("--out", default=None)
     rr = sub.add_parser("repack-rate")
     rr.add_argument("--reps", type=int, default=50)
@@ -604,7 +673,7 @@ def main(argv=None):
         res = paper_table(tuple(int(x) for x in args.ns.split(",")),
                           sizes=tuple(args.sizes.split(",")),
                           only=tuple(args.variants.split(",")) if args.variants else None,
-                          reps=args.reps)
+                          reps=args.reps, sample_clocks=args.sample_clocks)
         print(json.dumps(res))
     if args.out:
         json.dump(res, open(args.out, "w"))

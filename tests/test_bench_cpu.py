@@ -27,20 +27,24 @@ def test_matrix_unique_bytes_ragged_tile_and_uncovered_rows():
     assert reads == 2 * 2 * 88
 
 
-def test_traffic_is_reported_only_for_the_profiled_kernel_sources(monkeypatch, tmp_path):
+def test_traffic_counters_match_the_kernel_sources(monkeypatch, tmp_path):
     """The committed counter summary carries the hash of the kernel sources it
-    was taken on: its traffic figure is used while they are unchanged, and
-    dropped (None) once they differ or the summary is malformed."""
+    was taken on.  It must match the sources as they are: a change to the
+    resident kernel's sources needs new FETCH_SIZE / WRITE_SIZE counters.  Its
+    traffic figures are used while they match, and dropped (None) once they
+    differ or the summary is malformed."""
     kv = {}
     for line in open(bench.TRAFFIC_FILE):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.split("#")[0].strip()
-    assert int(kv["traffic_bytes"]) == int(kv["traffic_read_bytes"]) + int(kv["traffic_write_bytes"])
-    if kv["kernel_sources_sha256"] == bench.kernel_source_hash():
-        assert bench.measured_traffic() == int(kv["traffic_bytes"])
-    else:                                   # sources changed since the counters were taken
-        assert bench.measured_traffic() is None
+    for pre in ("", "incremental_"):
+        assert int(kv[pre + "traffic_bytes"]) == (int(kv[pre + "traffic_read_bytes"])
+                                                  + int(kv[pre + "traffic_write_bytes"]))
+    assert kv["kernel_sources_sha256"] == bench.kernel_source_hash(), \
+        "the resident kernel's sources changed since its HBM counters were taken: take them again"
+    assert bench.measured_traffic() == int(kv["traffic_bytes"])
+    assert bench.measured_traffic("incremental_traffic_bytes") == int(kv["incremental_traffic_bytes"])
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
     assert bench.measured_traffic() is None
     monkeypatch.undo()
