@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpixel-members/s composited (resident & streamed) at bit-exact; p50/p99 req latency"
 HBM_PEAK_GBS = 8000.0
+BATCHED_POOL_PAD = 4096
 
 
 def log(*a):
@@ -378,9 +379,13 @@ def run_batched(torch, reps, tuned=True, cpu_seconds=3.0):
     lv = wl.levels()
     et = torch.from_numpy(e).to("cuda:0")
     plane = wl.H * wl.W
-    buf = torch.empty(wl.pool * plane + 64, dtype=torch.uint8, device="cuda:0")
+    # rasters 4 KiB apart beyond their 4 MiB: at a power-of-two stride the
+    # 512-byte pieces a matrix-mode tile reads from ~1,900 rasters crowd onto
+    # fewer memory channels (measured 1.73 -> 1.66 ms per batch)
+    stride = plane + BATCHED_POOL_PAD
+    buf = torch.empty(wl.pool * stride + 64, dtype=torch.uint8, device="cuda:0")
     for i, L in enumerate(lv):
-        synth.member_torch(et, int(L), "mask", out=buf[i * plane:(i + 1) * plane].view(wl.H, wl.W))
+        synth.member_torch(et, int(L), "mask", out=buf[i * stride:i * stride + plane].view(wl.H, wl.W))
         if i % 256 == 255:
             log(f"  pool {i + 1}/{wl.pool}")
     reqs = wl.requests()
@@ -390,8 +395,8 @@ def run_batched(torch, reps, tuned=True, cpu_seconds=3.0):
     pxm = sum(len(r["ids"]) * r["w"] * r["h"] for r in reqs)
     out = {"workload": "batched: pool 2048 x 2048x2048 masks, 64 requests, N in [4,512], "
                        "square crops of side [512,2048] -> u32 count",
-           "px_members": pxm}
-    with Pool(buf, wl.pool, wl.W, wl.H, plane, buf.numel()) as pool:
+           "px_members": pxm, "pool_stride_bytes": stride}
+    with Pool(buf, wl.pool, wl.W, wl.H, stride, buf.numel()) as pool:
         keys = ("mode", "tile_vecs", "blocks_per_cu", "order", "stream_loads", "slots")
         if tuned:
             log("  autotune")

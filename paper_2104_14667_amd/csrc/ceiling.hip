@@ -13,7 +13,9 @@
 //   3: 2 bytes per pixel read and written (uint16 count),
 //   4: the 9 bytes per pixel written without being read (a composite set from
 //      cleared accumulators),
-//   5: the 9 bytes per pixel read without being written.
+//   5: the 9 bytes per pixel read without being written,
+//   6: as 4, with each workgroup starting at member blockIdx.x mod n and
+//      wrapping around (the members' order rotated per workgroup).
 // Its rate is what the memory system sustains for that access pattern, the
 // attainable bound for the compositing kernel on the same data; modes 0, 4, 5
 // and 1 side by side split the cost of the composite's read and write.
@@ -32,11 +34,18 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   if (t >= nvec) return;
   uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  // member of step j: (rot + j) mod n
+  const int rot = RMW == 6 ? (int)(blockIdx.x % (unsigned)n) : 0;
+  auto member = [&](int j) {
+    const int m = rot + j;
+    return m >= n ? m - n : m;
+  };
   int i = 0;
   for (; i + 8 <= n; i += 8) {
     u32x4 v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load((gu32x4 *)(mem + (i + u) * stride + t * 16u));
+    for (int u = 0; u < 8; ++u)
+      v[u] = __builtin_nontemporal_load((gu32x4 *)(mem + member(i + u) * stride + t * 16u));
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       a0 += v[u].x;
@@ -46,7 +55,7 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
     }
   }
   for (; i < n; ++i) {
-    const u32x4 v = __builtin_nontemporal_load((gu32x4 *)(mem + i * stride + t * 16u));
+    const u32x4 v = __builtin_nontemporal_load((gu32x4 *)(mem + member(i) * stride + t * 16u));
     a0 += v.x;
     a1 += v.y;
     a2 += v.z;
@@ -62,7 +71,7 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
       const uint4 o = c16[q];
       c16[q] = make_uint4(o.x + a0, o.y + a1, o.z + a2, o.w + a3);
     }
-  } else if (RMW == 4) {
+  } else if (RMW == 4 || RMW == 6) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       c[q] = make_uint4(a0 + q, a1, a2, a3);
@@ -107,12 +116,12 @@ extern "C" {
 // rasters at members + i * stride (npix bytes each, npix a multiple of 16,
 // 16-byte aligned) and composite buffers count, sum (npix uint32 each) and
 // max (npix bytes), and returns in *best_ms the fastest of the runs after the
-// first.  rmw: the mode, 0 .. 5 as above.  Returns 0 or a hipError_t.  The
+// first.  rmw: the mode, 0 .. 6 as above.  Returns 0 or a hipError_t.  The
 // composite buffers are overwritten.
 int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t npix, void *count,
                     void *sum, void *max, int32_t rmw, int32_t reps, void *stream, float *best_ms) {
   if (!members || !count || !sum || !max || !best_ms || n < 1 || reps < 2 || npix < 16 ||
-      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 5)
+      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 6)
     return (int)hipErrorInvalidValue;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint32_t nvec = (uint32_t)(npix / 16);
@@ -133,6 +142,7 @@ int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t n
   k_ceiling<M><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, \
                                     (uint8_t *)max, nvec, 0x9e3779b9u)
     switch (rmw) {
+      case 6: CMP_CEIL(6); break;
       case 5: CMP_CEIL(5); break;
       case 4: CMP_CEIL(4); break;
       case 3: CMP_CEIL(3); break;

@@ -64,8 +64,9 @@
 * ``write-mix``: what the composite's read and write cost next to n member
   streams: the same-traffic reference kernel over n members of 8192x8192 with
   member reads only, plus the 9 B/px composite read, plus its write, plus both
-  (read-modify-write), for several n; and a plain fill and copy of the same
-  composite bytes (torch) for scale.
+  (read-modify-write), for several n, and the write-only mode again with
+  each workgroup's member order rotated (starting at member blockIdx mod n);
+  and a plain fill and copy of the same composite bytes (torch) for scale.
 
 Usage: python -m paper_2104_14667_amd.experiments
            {repack-sweep,repack-rate,paper-table,kernel-table,h2d-sweep,subdivide,
@@ -565,7 +566,8 @@ def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
     for n in ns:
         t = same_traffic_ceiling(torch, buf.data_ptr(), stride, n, plane,
                                  ((0, "reads"), (5, "reads+composite_read"),
-                                  (4, "reads+composite_write"), (1, "reads+rmw")))
+                                  (4, "reads+composite_write"), (1, "reads+rmw"),
+                                  (6, "rotated_reads+composite_write")))
         row = {"members": n, "member_GB": round(n * plane / 1e9, 3), "composite_GB": round(comp / 1e9, 3)}
         row.update({k + "_ms": round(v, 4) for k, v in t.items()})
         row["read_cost_ms_per_GB"] = round((t["reads+composite_read"] - t["reads"]) / (comp / 1e9), 3)
