@@ -15,7 +15,10 @@
 //      cleared accumulators),
 //   5: the 9 bytes per pixel read without being written,
 //   6: as 4, with each workgroup starting at member blockIdx.x mod n and
-//      wrapping around (the members' order rotated per workgroup).
+//      wrapping around (the members' order rotated per workgroup),
+//   7 .. 12: as 4, phased (k_phased below): V = 2, 4, 8 vectors per thread per
+//      round, with 2 (modes 7 .. 9) or 4 (modes 10 .. 12) workgroups per
+//      compute unit.
 // Its rate is what the memory system sustains for that access pattern, the
 // attainable bound for the compositing kernel on the same data; modes 0, 4, 5
 // and 1 side by side split the cost of the composite's read and write.
@@ -108,6 +111,59 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
   }
 }
 
+// Phased variant of mode 4: a grid of `blocks` workgroups walks the pixels in
+// rounds of gridDim.x * 256 * V vectors.  In each round a thread first reads
+// all n members for its V vectors (vector base + u * nthreads + thread, two
+// members' loads in flight at a time), then writes the 9 bytes per pixel of
+// those V vectors.  Every thread has the same work, so the writes of a round
+// cluster in time instead of trickling out between the reads.
+template <int V>
+__global__ __launch_bounds__(256) void k_phased(const uint8_t *__restrict__ mem, int64_t stride, int n,
+                                                uint32_t *__restrict__ cnt, uint32_t *__restrict__ sum,
+                                                uint8_t *__restrict__ mx, uint32_t nvec) {
+  const uint32_t nthreads = gridDim.x * 256u;
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  for (uint32_t base = 0; base < nvec; base += nthreads * V) {
+    uint32_t a[V][4];
+#pragma unroll
+    for (int u = 0; u < V; ++u) a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0u;
+    for (int i = 0; i < n; i += 2) {
+      u32x4 x[2][V];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const uint32_t idx = base + u * nthreads + t;
+          x[m][u] = (idx < nvec && i + m < n)
+                        ? __builtin_nontemporal_load((gu32x4 *)(mem + (int64_t)(i + m) * stride + idx * 16u))
+                        : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          a[u][0] += x[m][u].x;
+          a[u][1] += x[m][u].y;
+          a[u][2] += x[m][u].z;
+          a[u][3] ^= x[m][u].w;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const uint32_t idx = base + u * nthreads + t;
+      if (idx >= nvec) continue;
+      uint4 *c = reinterpret_cast<uint4 *>(cnt + idx * 16u);
+      uint4 *s = reinterpret_cast<uint4 *>(sum + idx * 16u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = make_uint4(a[u][0] + q, a[u][1], a[u][2], a[u][3]);
+        s[q] = make_uint4(a[u][0] ^ q, a[u][1], a[u][2], a[u][3]);
+      }
+      reinterpret_cast<uint4 *>(mx + idx * 16u)[0] = make_uint4(a[u][0] | 1u, a[u][1], a[u][2], a[u][3]);
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -116,14 +172,19 @@ extern "C" {
 // rasters at members + i * stride (npix bytes each, npix a multiple of 16,
 // 16-byte aligned) and composite buffers count, sum (npix uint32 each) and
 // max (npix bytes), and returns in *best_ms the fastest of the runs after the
-// first.  rmw: the mode, 0 .. 6 as above.  Returns 0 or a hipError_t.  The
+// first.  rmw: the mode, 0 .. 12 as above.  Returns 0 or a hipError_t.  The
 // composite buffers are overwritten.
 int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t npix, void *count,
                     void *sum, void *max, int32_t rmw, int32_t reps, void *stream, float *best_ms) {
   if (!members || !count || !sum || !max || !best_ms || n < 1 || reps < 2 || npix < 16 ||
-      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 6)
+      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 12)
     return (int)hipErrorInvalidValue;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0, cus = 0;
+  hipError_t ea = hipGetDevice(&dev);
+  if (ea == hipSuccess) ea = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (ea != hipSuccess) return (int)ea;
+  const unsigned pgrid = (unsigned)cus * (rmw >= 10 ? 4u : 2u);
   const uint32_t nvec = (uint32_t)(npix / 16);
   const unsigned grid = (nvec + 255) / 256;
   hipEvent_t e0, e1;
@@ -142,6 +203,9 @@ int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t n
   k_ceiling<M><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, \
                                     (uint8_t *)max, nvec, 0x9e3779b9u)
     switch (rmw) {
+      case 7: case 10: k_phased<2><<<pgrid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, (uint8_t *)max, nvec); break;
+      case 8: case 11: k_phased<4><<<pgrid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, (uint8_t *)max, nvec); break;
+      case 9: case 12: k_phased<8><<<pgrid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, (uint8_t *)max, nvec); break;
       case 6: CMP_CEIL(6); break;
       case 5: CMP_CEIL(5); break;
       case 4: CMP_CEIL(4); break;

@@ -65,7 +65,10 @@
   streams: the same-traffic reference kernel over n members of 8192x8192 with
   member reads only, plus the 9 B/px composite read, plus its write, plus both
   (read-modify-write), for several n, and the write-only mode again with
-  each workgroup's member order rotated (starting at member blockIdx mod n);
+  each workgroup's member order rotated (starting at member blockIdx mod n),
+  and phased: a grid of 2 or 4 workgroups per compute unit whose threads
+  read all members for V = 2, 4 or 8 vectors before writing those vectors'
+  composite, round after round;
   and a plain fill and copy of the same composite bytes (torch) for scale.
 
 Usage: python -m paper_2104_14667_amd.experiments
@@ -567,7 +570,10 @@ def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
         t = same_traffic_ceiling(torch, buf.data_ptr(), stride, n, plane,
                                  ((0, "reads"), (5, "reads+composite_read"),
                                   (4, "reads+composite_write"), (1, "reads+rmw"),
-                                  (6, "rotated_reads+composite_write")))
+                                  (6, "rotated_reads+composite_write"),
+                                  (7, "phased_V2_2wg+composite_write"), (8, "phased_V4_2wg+composite_write"),
+                                  (9, "phased_V8_2wg+composite_write"), (10, "phased_V2_4wg+composite_write"),
+                                  (11, "phased_V4_4wg+composite_write"), (12, "phased_V8_4wg+composite_write")))
         row = {"members": n, "member_GB": round(n * plane / 1e9, 3), "composite_GB": round(comp / 1e9, 3)}
         row.update({k + "_ms": round(v, 4) for k, v in t.items()})
         row["read_cost_ms_per_GB"] = round((t["reads+composite_read"] - t["reads"]) / (comp / 1e9), 3)
