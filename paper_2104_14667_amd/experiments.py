@@ -61,6 +61,9 @@
   bytes, for several pads: the median device time of the library's default
   tune (matrix mode, graph replay), every output checked against its closed
   form.  With pad 0 the same pixel of every raster lies exactly 4 MiB apart.
+* ``serve-layout``: the served workload's continuous-batching run for a
+  few seconds of its schedule with the pool's depth maps at a stride of
+  4096^2 + pad bytes, for several pads: device time per request, p50, p99.
 * ``write-mix``: what the composite's read and write cost next to n member
   streams: the same-traffic reference kernel over n members of 8192x8192 with
   member reads only, plus the 9 B/px composite read, plus its write, plus both
@@ -73,7 +76,7 @@
 
 Usage: python -m paper_2104_14667_amd.experiments
            {repack-sweep,repack-rate,paper-table,kernel-table,h2d-sweep,subdivide,
-            member-layout,pool-layout,write-mix}
+            member-layout,pool-layout,serve-layout,write-mix}
            [--out FILE]
 """
 
@@ -555,6 +558,66 @@ def pool_layout(pads=(0, 4096, 65536, 1 << 20, (1 << 20) + 4096, 4 << 20), reps=
     return {"pool": wl.pool, "W": wl.W, "H": wl.H, "requests": len(reqs), "reps": reps, "rows": rows}
 
 
+def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: int = 8) -> dict:
+    """The served workload's continuous-batching run (uint16 composites, an
+    8 GiB budget, Poisson 2000 req/s) for `seconds` of its schedule, with the
+    pool's depth maps at a stride of 4096^2 + pad bytes: device time per
+    request, p50 and p99.  `check` sessions' final viewports are compared with
+    the closed form of their final members."""
+    import torch
+
+    from . import synth
+    from .composite import CMP_OP_ADD, Pool, Server
+    wl = synth.SERVED
+    e = wl.elevation()
+    lv = wl.levels()
+    et = torch.from_numpy(e).to("cuda:0")
+    plane = wl.H * wl.W
+    buf = torch.empty(wl.pool * (plane + max(pads)) + 64, dtype=torch.uint8, device="cuda:0")
+    sched = wl.schedule(int(wl.rate * seconds))
+    budget = wl.sessions // 2 * plane * 4
+    ring = [torch.empty((wl.view, wl.view), dtype=torch.int32, pin_memory=True) for _ in range(64)]
+    dst = torch.empty((wl.view, wl.view), dtype=torch.int32, pin_memory=True)
+    rows = []
+    for pad in pads:
+        stride = plane + pad
+        for i, L in enumerate(lv):
+            synth.member_torch(et, int(L), "depth", out=buf[i * stride:i * stride + plane].view(wl.H, wl.W))
+        torch.cuda.synchronize()
+        with Pool(buf, wl.pool, wl.W, wl.H, stride, buf.numel()) as pool:
+            with Server(pool, count_bits=16, max_batch=64, overlap=1, hbm_budget_bytes=budget) as srv:
+                sids = [srv.open() for _ in range(wl.sessions)]
+                st0 = srv.stats()
+                lat, status = srv.replay(sched, sids, ring, wl.view, with_status=True)
+                st = srv.stats()
+                # final members of a few sessions against their closed form
+                cur = [dict() for _ in range(wl.sessions)]
+                for r, g in zip(sched, status):
+                    if g != 0:
+                        continue
+                    c = cur[r["sid"]]
+                    for i in (int(x) for x in r["ids"]):
+                        c[i] = c.get(i, 0) + (1 if r["op"] == "add" else -1)
+                        if c[i] == 0:
+                            del c[i]
+                exact = True
+                for k in range(0, wl.sessions, wl.sessions // check):
+                    srv.wait(srv.submit(sids[k], CMP_OP_ADD, [], (0, 0, wl.view, wl.view), dst))
+                    c = cur[k]
+                    lvs = np.sort(np.repeat(lv[list(c)], list(c.values()))) if c else np.zeros(0, lv.dtype)
+                    exp = len(lvs) - np.searchsorted(lvs, e[:wl.view, :wl.view], side="right")
+                    exact &= bool(np.array_equal(dst.numpy().view(np.uint32), exp))
+        ok = status == 0
+        lat_ms = lat[ok] / 1e6
+        nreq = st["requests"] - st0["requests"]
+        rows.append({"pad_bytes": pad, "stride_bytes": stride, "requests": int(ok.sum()),
+                     "device_ms_per_request": round((st["device_ms"] - st0["device_ms"]) / max(1, nreq), 4),
+                     "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "exact": exact})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"seconds": seconds, "sessions": wl.sessions, "rows": rows}
+
+
 def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
     import torch
 
@@ -641,6 +704,10 @@ def main(argv=None):
     pl.add_argument("--pads", default=None, help="comma-separated pads in bytes")
     pl.add_argument("--reps", type=int, default=10)
     pl.add_argument("--out", default=None)
+    sl = sub.add_parser("serve-layout")
+    sl.add_argument("--pads", default=None, help="comma-separated pads in bytes")
+    sl.add_argument("--seconds", type=float, default=3.0)
+    sl.add_argument("--out", default=None)
     w = sub.add_parser("write-mix")
     w.add_argument("--ns", default="16,64,128")
     w.add_argument("--pad", type=int, default=0)
@@ -673,6 +740,12 @@ def main(argv=None):
         if args.pads:
             kw["pads"] = tuple(int(x) for x in args.pads.split(","))
         res = pool_layout(**kw)
+        print(json.dumps(res))
+    elif args.cmd == "serve-layout":
+        kw = {"seconds": args.seconds}
+        if args.pads:
+            kw["pads"] = tuple(int(x) for x in args.pads.split(","))
+        res = serve_layout(**kw)
         print(json.dumps(res))
     elif args.cmd == "write-mix":
         res = write_mix(tuple(int(x) for x in args.ns.split(",")), pad=args.pad)
