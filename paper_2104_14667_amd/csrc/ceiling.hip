@@ -18,7 +18,11 @@
 //      wrapping around (the members' order rotated per workgroup),
 //   7 .. 12: as 4, phased (k_phased below): V = 2, 4, 8 vectors per thread per
 //      round, with 2 (modes 7 .. 9) or 4 (modes 10 .. 12) workgroups per
-//      compute unit.
+//      compute unit,
+//   13: as 4, with the members interleaved in 1 KiB blocks (block b of member i
+//      at (b * n + i) * 1024): a wave's 64 vectors are one block, and its n
+//      member loads walk n KiB of contiguous memory (stride is ignored; the
+//      members take n * npix bytes).
 // Its rate is what the memory system sustains for that access pattern, the
 // attainable bound for the compositing kernel on the same data; modes 0, 4, 5
 // and 1 side by side split the cost of the composite's read and write.
@@ -29,6 +33,16 @@ namespace {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) u32x4 gu32x4;
+
+// Byte offset of vector t (16 bytes) of member i: member-major (i * stride +
+// 16 t), or interleaved in 1 KiB blocks of 64 vectors (mode 13).
+template <int RMW>
+__device__ __forceinline__ int64_t member_off(int i, int64_t stride, int n, uint32_t t) {
+  if constexpr (RMW == 13)
+    return ((int64_t)(t >> 6) * n + i) * 1024 + (int64_t)(t & 63u) * 16;
+  else
+    return (int64_t)i * stride + (int64_t)t * 16;
+}
 
 template <int RMW>
 __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem, int64_t stride, int n,
@@ -48,7 +62,7 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
     u32x4 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      v[u] = __builtin_nontemporal_load((gu32x4 *)(mem + member(i + u) * stride + t * 16u));
+      v[u] = __builtin_nontemporal_load((gu32x4 *)(mem + member_off<RMW>(member(i + u), stride, n, t)));
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       a0 += v[u].x;
@@ -58,7 +72,7 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
     }
   }
   for (; i < n; ++i) {
-    const u32x4 v = __builtin_nontemporal_load((gu32x4 *)(mem + member(i) * stride + t * 16u));
+    const u32x4 v = __builtin_nontemporal_load((gu32x4 *)(mem + member_off<RMW>(member(i), stride, n, t)));
     a0 += v.x;
     a1 += v.y;
     a2 += v.z;
@@ -74,7 +88,7 @@ __global__ __launch_bounds__(256) void k_ceiling(const uint8_t *__restrict__ mem
       const uint4 o = c16[q];
       c16[q] = make_uint4(o.x + a0, o.y + a1, o.z + a2, o.w + a3);
     }
-  } else if (RMW == 4 || RMW == 6) {
+  } else if (RMW == 4 || RMW == 6 || RMW == 13) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       c[q] = make_uint4(a0 + q, a1, a2, a3);
@@ -172,12 +186,13 @@ extern "C" {
 // rasters at members + i * stride (npix bytes each, npix a multiple of 16,
 // 16-byte aligned) and composite buffers count, sum (npix uint32 each) and
 // max (npix bytes), and returns in *best_ms the fastest of the runs after the
-// first.  rmw: the mode, 0 .. 12 as above.  Returns 0 or a hipError_t.  The
+// first.  rmw: the mode, 0 .. 13 as above.  Returns 0 or a hipError_t.  The
 // composite buffers are overwritten.
 int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t npix, void *count,
                     void *sum, void *max, int32_t rmw, int32_t reps, void *stream, float *best_ms) {
   if (!members || !count || !sum || !max || !best_ms || n < 1 || reps < 2 || npix < 16 ||
-      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 12)
+      npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix || rmw < 0 || rmw > 13 ||
+      (rmw == 13 && npix % 1024))  // whole 1 KiB blocks: the n blocks of a wave end at n * npix
     return (int)hipErrorInvalidValue;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0, cus = 0;
@@ -203,6 +218,7 @@ int traffic_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t n
   k_ceiling<M><<<grid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, \
                                     (uint8_t *)max, nvec, 0x9e3779b9u)
     switch (rmw) {
+      case 13: CMP_CEIL(13); break;
       case 7: case 10: k_phased<2><<<pgrid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, (uint8_t *)max, nvec); break;
       case 8: case 11: k_phased<4><<<pgrid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, (uint8_t *)max, nvec); break;
       case 9: case 12: k_phased<8><<<pgrid, 256, 0, s>>>(members, stride, n, (uint32_t *)count, (uint32_t *)sum, (uint8_t *)max, nvec); break;

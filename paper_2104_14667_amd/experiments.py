@@ -71,7 +71,8 @@
   each workgroup's member order rotated (starting at member blockIdx mod n),
   and phased: a grid of 2 or 4 workgroups per compute unit whose threads
   read all members for V = 2, 4 or 8 vectors before writing those vectors'
-  composite, round after round;
+  composite, round after round, and with the members interleaved in 1 KiB
+  blocks (a wave's loads of all members walk contiguous memory);
   and a plain fill and copy of the same composite bytes (torch) for scale.
 
 Usage: python -m paper_2104_14667_amd.experiments
@@ -636,7 +637,8 @@ def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
                                   (6, "rotated_reads+composite_write"),
                                   (7, "phased_V2_2wg+composite_write"), (8, "phased_V4_2wg+composite_write"),
                                   (9, "phased_V8_2wg+composite_write"), (10, "phased_V2_4wg+composite_write"),
-                                  (11, "phased_V4_4wg+composite_write"), (12, "phased_V8_4wg+composite_write")))
+                                  (11, "phased_V4_4wg+composite_write"), (12, "phased_V8_4wg+composite_write"),
+                                  (13, "interleaved_reads+composite_write")))
         row = {"members": n, "member_GB": round(n * plane / 1e9, 3), "composite_GB": round(comp / 1e9, 3)}
         row.update({k + "_ms": round(v, 4) for k, v in t.items()})
         row["read_cost_ms_per_GB"] = round((t["reads+composite_read"] - t["reads"]) / (comp / 1e9), 3)

@@ -167,7 +167,7 @@ def test_ceiling_library_checks_arguments():
     ms = C.c_float()
     ok = dict(members=16, stride=64, n=2, npix=64, count=16, sum=16, max=16, rmw=1, reps=3)
     bads = [dict(members=None), dict(n=0), dict(npix=40), dict(stride=32), dict(reps=1),
-            dict(count=None), dict(npix=1 << 33, stride=1 << 33), dict(rmw=13), dict(rmw=-1)]
+            dict(count=None), dict(npix=1 << 33, stride=1 << 33), dict(rmw=14), dict(rmw=-1)]
     for bad in bads:
         a = dict(ok, **bad)
         rc = f(a["members"], a["stride"], a["n"], a["npix"], a["count"], a["sum"], a["max"],
