@@ -178,9 +178,90 @@ __global__ __launch_bounds__(256) void k_phased(const uint8_t *__restrict__ mem,
   }
 }
 
+// The batched matrix kernel's read pattern with trivial arithmetic: a grid of
+// `blocks` workgroups of four waves takes tiles of 512 pixels of one row
+// (tile = row * segs + segment) in turn; for each tile every wave reads 128
+// pixels (8 bytes per lane: 16 lanes per member, 4 members per load) of every
+// one of the pool's `count` rasters, 32 rasters (8 loads) per step, two steps
+// in flight.  Raster k's row y is at base + k * stride + y * pitch.  One
+// 16-byte store per lane per tile keeps the loads live.
+__global__ __launch_bounds__(256) void k_tile_reads(const uint8_t *__restrict__ base, int64_t stride,
+                                                    int64_t pitch, int32_t count, int32_t W, int32_t H,
+                                                    uint32_t *__restrict__ sink) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  typedef const __attribute__((address_space(1))) u32x2 gu32x2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row16 = lane & 15, kg = lane >> 4;
+  const int segs = (W + 511) / 512;
+  const int ntiles = H * segs;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int y = tile / segs;
+    const int xw = (tile - y * segs) * 512 + 128 * wave;
+    uint32_t a0 = 0, a1 = 0;
+    if (xw < W) {
+      const int x = min(xw + 8 * row16, W - 8);
+      const uint8_t *rb = base + (int64_t)y * pitch + x;
+      for (int c = 0; c + 32 <= count; c += 64) {
+        u32x2 v[16];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int k = c + 32 * h + 8 * kg + i;
+            v[8 * h + i] = k < count ? __builtin_nontemporal_load((gu32x2 *)(rb + (int64_t)k * stride))
+                                     : u32x2{0u, 0u};
+          }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          a0 += v[j].x;
+          a1 ^= v[j].y;
+        }
+      }
+    }
+    sink[(int64_t)tile * 256 + threadIdx.x] = a0 ^ a1;
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+// Runs k_tile_reads reps times on `stream` with `blocks` workgroups over a
+// pool of count rasters of W x H (W >= 8), raster k's row y at
+// base + k * stride + y * pitch, and returns the fastest run after the first
+// in *best_ms.  sink: H * ceil(W / 512) * 256 uint32 of device memory.
+// Returns 0 or a hipError_t.
+int tile_read_ceiling(const uint8_t *base, int64_t stride, int64_t pitch, int32_t count, int32_t W,
+                      int32_t H, void *sink, int32_t blocks, int32_t reps, void *stream, float *best_ms) {
+  if (!base || !sink || !best_ms || count < 32 || W < 8 || H < 1 || blocks < 1 || reps < 2 ||
+      stride < 1 || pitch < W)
+    return (int)hipErrorInvalidValue;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return (int)e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return (int)e;
+  }
+  float best = 0.f;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, s);
+    if (e != hipSuccess) break;
+    k_tile_reads<<<blocks, 256, 0, s>>>(base, stride, pitch, count, W, H, (uint32_t *)sink);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && r > 0 && (r == 1 || ms < best)) best = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *best_ms = best;
+  return (int)e;
+}
 
 // Runs the kernel reps times on `stream` (a hipStream_t, or NULL) over n
 // rasters at members + i * stride (npix bytes each, npix a multiple of 16,

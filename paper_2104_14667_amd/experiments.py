@@ -64,6 +64,9 @@
 * ``serve-layout``: the served workload's continuous-batching run for a
   few seconds of its schedule with the pool's depth maps at a stride of
   4096^2 + pad bytes, for several pads: device time per request, p50, p99.
+* ``tile-reads``: the batched matrix kernel's read pattern with trivial
+  arithmetic over the batched pool's shape, rasters stored one after another
+  or row-interleaved (row y of every raster side by side).
 * ``write-mix``: what the composite's read and write cost next to n member
   streams: the same-traffic reference kernel over n members of 8192x8192 with
   member reads only, plus the 9 B/px composite read, plus its write, plus both
@@ -77,7 +80,7 @@
 
 Usage: python -m paper_2104_14667_amd.experiments
            {repack-sweep,repack-rate,paper-table,kernel-table,h2d-sweep,subdivide,
-            member-layout,pool-layout,serve-layout,write-mix}
+            member-layout,pool-layout,serve-layout,tile-reads,write-mix}
            [--out FILE]
 """
 
@@ -619,6 +622,34 @@ def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: in
     return {"seconds": seconds, "sessions": wl.sessions, "rows": rows}
 
 
+def tile_reads(blocks_per_cu=(1, 2, 4), pads=(0, 4096)) -> dict:
+    """The batched matrix kernel's read pattern (every pool raster's 512-pixel
+    piece of every tile, 4 waves per tile) with trivial arithmetic, over the
+    batched workload's pool shape (2048 rasters of 2048x2048): rasters stored
+    one after another at 4 MiB + pad, or row-interleaved (row y of every
+    raster side by side: raster k's row y at (y * 2048 + k) * 2048)."""
+    import torch
+
+    from . import synth
+    from .ceiling import tile_read_ceiling
+    wl = synth.BATCHED
+    P, W, H = wl.pool, wl.W, wl.H
+    plane = W * H
+    buf = torch.randint(0, 256, (P * (plane + max(pads)) + 64,), dtype=torch.uint8, device="cuda:0")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    layouts = [(f"raster-major, stride 4 MiB + {pad}", plane + pad, W) for pad in pads]
+    layouts.append(("row-interleaved", W, P * W))
+    rows = []
+    for name, stride, pitch in layouts:
+        for b in blocks_per_cu:
+            ms = tile_read_ceiling(torch, buf.data_ptr(), stride, pitch, P, W, H, cus * b)
+            rows.append({"layout": name, "stride_bytes": stride, "row_pitch_bytes": pitch,
+                         "workgroups_per_cu": b, "ms": round(ms, 4),
+                         "GBps": round(P * plane / (ms * 1e-3) / 1e9, 1)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"pool": P, "W": W, "H": H, "bytes": P * plane, "rows": rows}
+
+
 def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
     import torch
 
@@ -710,6 +741,8 @@ def main(argv=None):
     sl.add_argument("--pads", default=None, help="comma-separated pads in bytes")
     sl.add_argument("--seconds", type=float, default=3.0)
     sl.add_argument("--out", default=None)
+    tr = sub.add_parser("tile-reads")
+    tr.add_argument("--out", default=None)
     w = sub.add_parser("write-mix")
     w.add_argument("--ns", default="16,64,128")
     w.add_argument("--pad", type=int, default=0)
@@ -748,6 +781,9 @@ def main(argv=None):
         if args.pads:
             kw["pads"] = tuple(int(x) for x in args.pads.split(","))
         res = serve_layout(**kw)
+        print(json.dumps(res))
+    elif args.cmd == "tile-reads":
+        res = tile_reads()
         print(json.dumps(res))
     elif args.cmd == "write-mix":
         res = write_mix(tuple(int(x) for x in args.ns.split(",")), pad=args.pad)
