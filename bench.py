@@ -150,8 +150,9 @@ def run_context_ops(torch, ens, e, dev, reps=3):
     """The single-context operations besides add, on the resident depth
     workload: clear (a1), removal of half the members with max rebuilt from
     the retained rest (a6), and reads (a7): the whole count composite to
-    pinned host memory (PCIe), a 1024x1024 window to pinned host memory, and
-    the same window to device memory.  Best of `reps` each; every result is
+    pinned host memory (PCIe), a 1024x1024 window to pinned host memory, the
+    same window to device memory, and the whole count composite to device
+    memory.  Best of `reps` each; every result is
     checked against the closed form."""
     from paper_2104_14667_amd.composite import Composite
     log("  context operations (clear, remove, read)")
@@ -213,8 +214,16 @@ def run_context_ops(torch, ens, e, dev, reps=3):
         out["read_window_to_device"] = {"ms": round(ms, 4), "window": f"{v}x{v}"}
         exact = exact and bool(np.array_equal(dwin.cpu().numpy().view(np.uint32).astype(np.int64),
                                               lut["count"][e[y0:y0 + v, x0:x0 + v]]))
+        dfull = torch.empty((H, W), dtype=torch.int32, device="cuda:0")
+        ms = min(timed(lambda: c.read_device("count", dfull)) for _ in range(reps))
+        out["read_count_to_device"] = {"ms": round(ms, 4), "bytes": 2 * 4 * npix,
+                                       "GBps": round(2 * 4 * npix / ms / 1e6, 1),
+                                       "note": "the whole count composite copied within HBM "
+                                               "(16-byte moves): read + write"}
+        exact = exact and bool(np.array_equal(dfull.cpu().numpy().view(np.uint32).astype(np.int64),
+                                              lut["count"][e]))
         out["exact"] = exact
-        del full, win, dwin
+        del full, win, dwin, dfull
     return out
 
 
@@ -464,6 +473,17 @@ def run_batched(torch, reps, tuned=True, cpu_seconds=3.0):
                                "unique_bytes": reads + writes,
                                "unique_bytes_note": "each (member, 512-pixel row tile) a covering "
                                                     "request holds, read once, plus the outputs"}
+            # the kernel's read pattern with trivial arithmetic on the same
+            # pool (every raster's piece of every tile): what the memory
+            # system sustains for these loads
+            from paper_2104_14667_amd.ceiling import tile_read_ceiling
+            cus = torch.cuda.get_device_properties(0).multi_processor_count
+            ref_ms = tile_read_ceiling(torch, buf.data_ptr(), stride, wl.W, wl.pool, wl.W, wl.H, cus * 2)
+            ref = wl.pool * plane / (ref_ms * 1e-3) / 1e9
+            out["roofline"]["attainable"] = {
+                "kernel": "read-pattern reference: 4 waves per 512-pixel tile, 8-byte loads of every "
+                          "raster's piece, 2 workgroups per CU, trivial arithmetic",
+                "GBps": round(ref, 1), "frac": round(ach / ref, 4)}
     if cpu_seconds > 0:
         log("  batched cpu baseline")
         out["cpu_baseline"] = batched_cpu_baseline(e, lv, reqs, cpu_seconds)

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libcomposite.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kernels.hip", "repack.hip", "context.hip", "batch.hip", "serve.hip", "verify.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "repack.hip", "utility.hip", "context.hip", "batch.hip", "serve.hip", "verify.hip", "noalloc.hip"]
 CEILING_SRC = "ceiling.hip"
 CEILING_OUT = os.path.join(PKG, "libceiling.so")
 

@@ -335,123 +335,7 @@ hipError_t run_tiled(const uint8_t *const *tab, int n, int64_t nvec, const Tiled
       return c16 ? FN<O, true, true>(__VA_ARGS__) : FN<O, true, false>(__VA_ARGS__); \
     return c16 ? FN<O, false, true>(__VA_ARGS__) : FN<O, false, false>(__VA_ARGS__);
 
-__global__ __launch_bounds__(256) void k_fill(uint8_t *__restrict__ p, uint32_t word,
-                                              int64_t nvec, int64_t bytes) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < nvec) reinterpret_cast<uint4 *>(p)[v] = make_uint4(word, word, word, word);
-  if (v == 0)
-    for (int64_t b = nvec * 16; b < bytes; ++b) p[b] = (uint8_t)word;
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_pack(const T *__restrict__ src, int32_t W, int32_t x0,
-                                              int32_t y0, int32_t w, int32_t h,
-                                              uint8_t *__restrict__ dst, int64_t dst_pitch) {
-  const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t y = blockIdx.y;
-  if (x >= w || y >= h) return;
-  reinterpret_cast<T *>(dst + (int64_t)y * dst_pitch)[x] = src[(int64_t)(y0 + y) * W + x0 + x];
-}
-
-// One workgroup walks vectors of 8 counts with a grid stride and counts them
-// into bins privatized in LDS (or straight into global memory for large bin
-// counts), one atomic per run of equal values; LDS bins are flushed once per
-// workgroup.
-template <bool C16, bool LDS>
-__global__ __launch_bounds__(256) void k_histogram(const void *__restrict__ count, uint32_t npix,
-                                                   int32_t nbins,
-                                                   unsigned long long *__restrict__ bins) {
-  extern __shared__ uint32_t sh[];
-  if constexpr (LDS) {
-    for (int b = threadIdx.x; b <= nbins; b += blockDim.x) sh[b] = 0u;
-    __syncthreads();
-  }
-  auto put = [&](uint32_t c, uint32_t k) {
-    const int b = c < (uint32_t)nbins ? (int)c : nbins;
-    if constexpr (LDS) atomicAdd(&sh[b], k);
-    else atomicAdd(&bins[b], (unsigned long long)k);
-  };
-  // Neighbouring pixels of a composite mostly share their class: a run of
-  // equal values among a thread's 8 pixels costs one atomic.
-  auto put8 = [&](const uint32_t (&c)[8]) {
-    uint32_t cur = c[0], run = 1;
-#pragma unroll
-    for (int k = 1; k < 8; ++k) {
-      if (c[k] == cur) {
-        ++run;
-      } else {
-        put(cur, run);
-        cur = c[k];
-        run = 1;
-      }
-    }
-    put(cur, run);
-  };
-  // one vector of 8 counts: 16 bytes of u16 or 32 bytes of u32
-  typedef uint4 vec_t[C16 ? 1 : 2];
-  auto load = [&](uint32_t v, vec_t &x) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(count) + (C16 ? 1 : 2) * (size_t)v;
-#pragma unroll
-    for (int h = 0; h < (C16 ? 1 : 2); ++h) x[h] = p[h];
-  };
-  auto count8 = [&](const vec_t &x) {
-    if constexpr (C16) {
-      const uint32_t c[8] = {x[0].x & 0xffffu, x[0].x >> 16, x[0].y & 0xffffu, x[0].y >> 16,
-                             x[0].z & 0xffffu, x[0].z >> 16, x[0].w & 0xffffu, x[0].w >> 16};
-      put8(c);
-    } else {
-      const uint32_t c[8] = {x[0].x, x[0].y, x[0].z, x[0].w, x[1].x, x[1].y, x[1].z, x[1].w};
-      put8(c);
-    }
-  };
-  const uint32_t nv = npix / 8;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  // four grid-stride steps at a time, their loads issued before any atomic,
-  // so that each wave keeps several loads in flight (nv < 2^29: no overflow)
-  for (; v + 3 * stride < nv; v += 4 * stride) {
-    vec_t x[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) load(v + u * stride, x[u]);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) count8(x[u]);
-  }
-  for (; v < nv; v += stride) {
-    vec_t x;
-    load(v, x);
-    count8(x);
-  }
-  // the last npix % 8 values
-  if (blockIdx.x == 0 && threadIdx.x < npix - nv * 8) {
-    const uint32_t i = nv * 8 + threadIdx.x;
-    put(C16 ? static_cast<const uint16_t *>(count)[i] : static_cast<const uint32_t *>(count)[i], 1u);
-  }
-  if constexpr (LDS) {
-    __syncthreads();
-    for (int b = threadIdx.x; b <= nbins; b += blockDim.x)
-      if (sh[b]) atomicAdd(&bins[b], (unsigned long long)sh[b]);
-  }
-}
-
 }  // namespace
-
-hipError_t launch_histogram(const void *count, bool count16, int64_t npix, int32_t nbins,
-                            unsigned long long *bins, int cus, hipStream_t s) {
-  if (npix <= 0) return hipSuccess;
-  if (npix >= (int64_t(1) << 32) || nbins < 1) return hipErrorInvalidValue;
-  const bool lds = nbins <= kLdsBins;
-  const int64_t nv = npix / 8;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nv + 255) / 256, (int64_t)cus * 2));
-  const size_t shm = lds ? sizeof(uint32_t) * (nbins + 1) : 0;
-  if (count16) {
-    if (lds) k_histogram<true, true><<<grid, 256, shm, s>>>(count, (uint32_t)npix, nbins, bins);
-    else k_histogram<true, false><<<grid, 256, 0, s>>>(count, (uint32_t)npix, nbins, bins);
-  } else {
-    if (lds) k_histogram<false, true><<<grid, 256, shm, s>>>(count, (uint32_t)npix, nbins, bins);
-    else k_histogram<false, false><<<grid, 256, 0, s>>>(count, (uint32_t)npix, nbins, bins);
-  }
-  return hipGetLastError();
-}
 
 hipError_t launch_composite_linear(const uint8_t *const *d_tab, int n, int64_t npix,
                                    const Outputs &o, uint32_t outs, bool sub, hipStream_t s) {
@@ -466,36 +350,6 @@ hipError_t launch_composite_tiled(const uint8_t *const *d_tab, int n, const Tili
   const TiledMap map{(uint32_t)t.W, (uint32_t)t.H, (uint32_t)t.tw, (uint32_t)t.th, (uint32_t)t.ntx()};
   const int64_t nvec = t.plane() / 16;
   CMP_DISPATCH(run_tiled, outs, sub, o.count16, d_tab, n, nvec, map, o, s);
-}
-
-hipError_t launch_fill(void *p, uint8_t value, int64_t bytes, hipStream_t s) {
-  if (bytes <= 0) return hipSuccess;
-  const uint32_t word = 0x01010101u * value;
-  const int64_t nvec = bytes / 16;
-  const int64_t blocks = nvec > 0 ? (nvec + 255) / 256 : 1;
-  k_fill<<<(unsigned)blocks, 256, 0, s>>>(static_cast<uint8_t *>(p), word, nvec, bytes);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack_window(const void *src, int elem, int32_t W, int32_t x0, int32_t y0,
-                              int32_t w, int32_t h, void *dst, int64_t dst_pitch,
-                              hipStream_t s) {
-  if (w <= 0 || h <= 0) return hipSuccess;
-  if (elem != 1 && elem != 2 && elem != 4) return hipErrorInvalidValue;
-  // one grid row per window row, at most 65535 rows per launch
-  for (int32_t r0 = 0; r0 < h; r0 += 65535) {
-    const int32_t hr = std::min<int32_t>(65535, h - r0);
-    dim3 grid((unsigned)((w + 255) / 256), (unsigned)hr);
-    uint8_t *d = static_cast<uint8_t *>(dst) + (int64_t)r0 * dst_pitch;
-    switch (elem) {
-      case 1: k_pack<uint8_t><<<grid, 256, 0, s>>>(static_cast<const uint8_t *>(src), W, x0, y0 + r0, w, hr, d, dst_pitch); break;
-      case 2: k_pack<uint16_t><<<grid, 256, 0, s>>>(static_cast<const uint16_t *>(src), W, x0, y0 + r0, w, hr, d, dst_pitch); break;
-      default: k_pack<uint32_t><<<grid, 256, 0, s>>>(static_cast<const uint32_t *>(src), W, x0, y0 + r0, w, hr, d, dst_pitch); break;
-    }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 }  // namespace cmp

@@ -244,6 +244,36 @@ def test_read_windows_and_device_destination():
             assert np.array_equal(arr, oracle.window(full[k], 2, 1, W - 5, H - 3))
 
 
+@pytest.mark.parametrize("count_bits", [16, 32])
+def test_read_device_windows_vector_and_element_paths(count_bits):
+    """Windows read into device memory: 16-byte moves where every source and
+    destination row starts on a 16-byte boundary (with the row's ragged end
+    element by element), one element per thread otherwise."""
+    W, H, n = 320, 40, 4
+    stack = _random_stack(9, n, H, W)
+    full = oracle.narrow(oracle.accumulate(list(stack), shape=(H, W)), count_bits)
+    dev = dev_of(stack)
+    elem = {"count": count_bits // 8, "sum": 4, "max": 1}
+    with Composite(W, H, ALL, count_bits) as c:
+        c.add_device([dev[i] for i in range(n)])
+        for (x0, y0, w, h) in [(0, 0, W, H), (16, 3, 37, 5), (4, 2, 50, 7), (5, 1, 19, 3), (304, 39, 16, 1)]:
+            for k in ALL:
+                e = elem[k]
+                want = oracle.window(full[k], x0, y0, w, h)
+                for pitch in (-(-w * e // 64) * 64, w * e + e):   # aligned rows; rows off 16 B
+                    buf = torch.full((h * pitch + 64,), 0x5A, dtype=torch.uint8, device="cuda")
+                    torch.cuda.synchronize()
+                    c.read_device(k, buf, (x0, y0, w, h), pitch_bytes=pitch)
+                    torch.cuda.synchronize()
+                    b = buf.cpu().numpy()
+                    got = np.stack([b[r * pitch:r * pitch + w * e].view(want.dtype) for r in range(h)])
+                    assert np.array_equal(got, want), (k, x0, y0, w, h, pitch)
+                    # nothing written between rows or after the last one
+                    for r in range(h):
+                        assert (b[r * pitch + w * e:(r + 1) * pitch] == 0x5A).all(), (k, r, pitch)
+                    assert (b[h * pitch:] == 0x5A).all()
+
+
 def test_clear_forgets_members():
     W, H = 32, 32
     stack = _random_stack(8, 3, H, W)
