@@ -910,6 +910,7 @@ def main():
             **run_streamed(torch, synth.STREAMED, e1, args.stream_reps, {
                 "dual_buffer_linear": dict(nbuf=2, chunk_depth=8),
                 "dual_buffer_linear_host_paced": dict(nbuf=2, chunk_depth=8, host_paced=1),
+                "dual_buffer_linear_two_copy_streams": dict(nbuf=2, chunk_depth=8, copy_streams=2),
                 "single_buffer_linear": dict(nbuf=1, chunk_depth=8),
                 "dual_buffer_tiled": dict(nbuf=2, chunk_depth=8, layout="tiled"),
             })}
@@ -917,7 +918,8 @@ def main():
         out["streamed_depth"] = {
             "workload": "depth N=128 x 8192x8192 from pinned host, chunk 8, PCIe-inclusive",
             **run_streamed(torch, ens, e, max(1, args.stream_reps - 1), {
-                "dual_buffer_linear": dict(nbuf=2, chunk_depth=8)})}
+                "dual_buffer_linear": dict(nbuf=2, chunk_depth=8),
+                "dual_buffer_linear_two_copy_streams": dict(nbuf=2, chunk_depth=8, copy_streams=2)})}
     if not args.no_batched:
         log("batched", synth.BATCHED.name)
         out["batched"] = run_batched(torch, args.stream_reps + 2, not args.no_autotune,

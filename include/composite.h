@@ -147,7 +147,15 @@ typedef struct cmp_opts {
                              updated in place (its buffer-kernel 1).  Results
                              are identical; pingpong doubles the composite's
                              device memory.  Default 0 */
-  int32_t reserved[1];    /* must be zero */
+  int32_t copy_streams;   /* streams the uploads of composite_add/remove run on:
+                             0 or 1, the copy stream; 2 (with nbuf = 2), slot
+                             k's uploads on a stream of their own, so that one
+                             slot's upload can start while the other's is still
+                             running and the copy engines are not idle between
+                             chunks (the second stream is created by the
+                             library).  Ordering per slot is unchanged: each
+                             upload waits for the kernel that last read its
+                             slot.  Default 0 */
 } cmp_opts;
 
 typedef struct cmp_ctx cmp_ctx;

@@ -42,7 +42,7 @@ class cmp_opts(C.Structure):
                 ("retain_members", C.c_int32), ("debug_poison", C.c_int32),
                 ("profile", C.c_int32), ("pageable_host", C.c_int32),
                 ("host_paced", C.c_int32), ("verify_members", C.c_int32),
-                ("pingpong", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("pingpong", C.c_int32), ("copy_streams", C.c_int32)]
 
 
 class cmp_request(C.Structure):

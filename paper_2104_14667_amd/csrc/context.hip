@@ -49,6 +49,7 @@ struct cmp_ctx {
   bool poisoned = false;
 
   hipStream_t copy_s = nullptr, comp_s = nullptr;
+  hipStream_t copy_s2 = nullptr;  // slot 1's uploads with copy_streams = 2
   bool own_copy = false, own_comp = false;
 
   void *d_count = nullptr;
@@ -165,6 +166,7 @@ void free_all(cmp_ctx *ctx) {
   (void)hipSetDevice(ctx->dev);
   if (ctx->comp_s) (void)hipStreamSynchronize(ctx->comp_s);
   if (ctx->copy_s) (void)hipStreamSynchronize(ctx->copy_s);
+  if (ctx->copy_s2) (void)hipStreamSynchronize(ctx->copy_s2);
   dfree(ctx, ctx->d_count);
   dfree(ctx, ctx->d_sum);
   dfree(ctx, ctx->d_max);
@@ -195,6 +197,7 @@ void free_all(cmp_ctx *ctx) {
     (void)hipEventDestroy(t.b);
   }
   if (ctx->own_copy && ctx->copy_s) (void)hipStreamDestroy(ctx->copy_s);
+  if (ctx->copy_s2) (void)hipStreamDestroy(ctx->copy_s2);
   if (ctx->own_comp && ctx->comp_s) (void)hipStreamDestroy(ctx->comp_s);
 }
 
@@ -420,12 +423,14 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
   for (int32_t k0 = 0, k = 0; k0 < n; k0 += d, ++k) {
     const int slot = k % nb;
     const int cnt = std::min<int32_t>(d, n - k0);
+    // the slot's uploads: on the copy stream, or slot 1's on a stream of its own
+    hipStream_t cs = (slot == 1 && ctx->copy_s2) ? ctx->copy_s2 : ctx->copy_s;
     if (ctx->o.host_paced) {
       // the slot's last reader (chunk k - nbuf) is a short kernel that ran
       // while chunk k - 1 was uploading; that upload is still in flight
       CMP_TRY(hipEventSynchronize(ctx->ev_free[slot]));
     } else {
-      CMP_TRY(hipStreamWaitEvent(ctx->copy_s, ctx->ev_free[slot], 0));
+      CMP_TRY(hipStreamWaitEvent(cs, ctx->ev_free[slot], 0));
     }
     if (pinned) {
       // Runs of host rasters that are contiguous, and staged contiguously, go
@@ -436,7 +441,7 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
         if (ctx->stage_stride == plane)
           while (r < cnt && maps[k0 + r] == maps[k0 + r - 1] + plane) ++r;
         CMP_TRY(hipMemcpyAsync(ctx->d_stage[slot] + j * ctx->stage_stride, maps[k0 + j],
-                               (size_t)(plane * (r - j)), hipMemcpyHostToDevice, ctx->copy_s));
+                               (size_t)(plane * (r - j)), hipMemcpyHostToDevice, cs));
         j = r;
       }
     } else {
@@ -446,10 +451,10 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
         std::memcpy(ctx->h_bounce[slot] + j * ctx->stage_stride, maps[k0 + j], (size_t)plane);
       CMP_TRY(hipMemcpyAsync(ctx->d_stage[slot], ctx->h_bounce[slot],
                              (size_t)((cnt - 1) * ctx->stage_stride + plane), hipMemcpyHostToDevice,
-                             ctx->copy_s));
-      CMP_TRY(hipEventRecord(ctx->ev_bounce[slot], ctx->copy_s));
+                             cs));
+      CMP_TRY(hipEventRecord(ctx->ev_bounce[slot], cs));
     }
-    CMP_TRY(hipEventRecord(ctx->ev_copied[slot], ctx->copy_s));
+    CMP_TRY(hipEventRecord(ctx->ev_copied[slot], cs));
     CMP_TRY(hipStreamWaitEvent(ctx->comp_s, ctx->ev_copied[slot], 0));
     if (fp && !tiled)
       CMP_TRY(cmp::launch_fingerprint(nullptr, ctx->d_stage[slot], ctx->stage_stride, cnt, plane,
@@ -490,6 +495,7 @@ int stream_members(cmp_ctx *ctx, const uint8_t *const *maps, int32_t n, bool sub
   }
   CMP_TRY(hipEventRecord(ctx->ev_host_done, ctx->copy_s));
   CMP_TRY(hipEventSynchronize(ctx->ev_host_done));
+  if (ctx->copy_s2) CMP_TRY(hipStreamSynchronize(ctx->copy_s2));
   return CMP_OK;
 }
 
@@ -583,14 +589,14 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
   if (o.pageable_host != 0 && o.pageable_host != 1) return CMP_EINVAL;
   if (o.verify_members != 0 && o.verify_members != 1) return CMP_EINVAL;
   if (o.pingpong != 0 && o.pingpong != 1) return CMP_EINVAL;
+  if (o.copy_streams < 0 || o.copy_streams > 2 || (o.copy_streams == 2 && o.nbuf != 2))
+    return CMP_EINVAL;
   if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) return CMP_EINVAL;
   if (o.layout == CMP_TILED) {
     if (o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64 && o.tile_w != 128) return CMP_EINVAL;
     if (o.tile_h < 1 || o.tile_h > 256) return CMP_EINVAL;
     if (W % 16) return CMP_EUNSUPPORTED;
   }
-  for (int r : o.reserved)
-    if (r) return CMP_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CMP_EDEVICE;
   if (o.device < 0 || o.device >= ndev) return CMP_EINVAL;
@@ -613,6 +619,9 @@ int composite_init(cmp_ctx **out, int32_t W, int32_t H, uint32_t outputs, int32_
       if (hipStreamCreateWithFlags(&ctx->copy_s, hipStreamNonBlocking) != hipSuccess) break;
       ctx->own_copy = true;
     }
+    if (o.copy_streams == 2 &&
+        hipStreamCreateWithFlags(&ctx->copy_s2, hipStreamNonBlocking) != hipSuccess)
+      break;
     if (o.compute_stream) {
       ctx->comp_s = (hipStream_t)o.compute_stream;
     } else {

@@ -55,7 +55,10 @@ def test_argument_checks_before_any_device_call():
     o.layout = cb.CMP_TILED
     assert cb.lib.composite_init(C.byref(h), 24, 4, 1, 32, C.byref(o)) == cb.CMP_EUNSUPPORTED
     o = cb.composite_default_opts()
-    o.reserved[0] = 1
+    o.copy_streams = 3
+    assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
+    o = cb.composite_default_opts()
+    o.copy_streams, o.nbuf = 2, 1                           # two copy streams need two slots
     assert cb.lib.composite_init(C.byref(h), 16, 4, 1, 32, C.byref(o)) == cb.CMP_EINVAL
     o = cb.composite_default_opts()
     o.pingpong = 2

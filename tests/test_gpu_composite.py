@@ -73,8 +73,11 @@ def test_ragged_streamed(W, H, nbuf, depth):
     stack = _random_stack(W * 7 + H * 3 + depth, n, H, W)
     exp = expect_oracle(stack, ALL, 32)
     host = pinned_copy(torch.from_numpy(stack))
-    for paced in (1, 0):
-        with Composite(W, H, ALL, 32, nbuf=nbuf, chunk_depth=depth, host_paced=paced) as c:
+    for paced, streams in ((1, 0), (0, 0), (0, 2)):
+        if streams == 2 and nbuf != 2:
+            continue
+        with Composite(W, H, ALL, 32, nbuf=nbuf, chunk_depth=depth, host_paced=paced,
+                       copy_streams=streams) as c:
             c.add([host[i] for i in range(n)])
             check_full(c, exp)
 

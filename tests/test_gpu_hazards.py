@@ -19,17 +19,19 @@ SPIN_CYCLES = 2_000_000
 
 
 @pytest.mark.parametrize("delayed", ["copy", "compute"])
-@pytest.mark.parametrize("nbuf,host_paced,layout", [(2, 1, "linear"), (2, 0, "linear"),
-                                                    (1, 1, "linear"), (2, 1, "tiled")])
-def test_delayed_stream_stays_exact(delayed, nbuf, host_paced, layout):
-    say("hazard", delayed, nbuf, host_paced, layout)
+@pytest.mark.parametrize("nbuf,host_paced,layout,copy_streams",
+                         [(2, 1, "linear", 0), (2, 0, "linear", 0), (1, 1, "linear", 0),
+                          (2, 1, "tiled", 0), (2, 0, "linear", 2), (2, 0, "tiled", 2)])
+def test_delayed_stream_stays_exact(delayed, nbuf, host_paced, layout, copy_streams):
+    say("hazard", delayed, nbuf, host_paced, layout, copy_streams)
     W, H = 256, 48
     A = synth.random_members(61, 21, H, W)
     hA = pinned_copy(torch.from_numpy(A))
     copy_s, comp_s = torch.cuda.Stream(), torch.cuda.Stream()
     spin_on = copy_s if delayed == "copy" else comp_s
+    # with two copy streams the delayed copy stream carries slot 0's uploads only
     kw = dict(nbuf=nbuf, chunk_depth=3, host_paced=host_paced, debug_poison=1,
-              copy_stream=copy_s, compute_stream=comp_s)
+              copy_stream=copy_s, compute_stream=comp_s, copy_streams=copy_streams)
     if layout == "tiled":
         kw.update(layout=CMP_TILED, tile_w=64, tile_h=16)
     outs = ("count", "sum")
