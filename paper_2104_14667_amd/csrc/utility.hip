@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_pack(const T *__restrict__ src, int32_t
   }
 }
 
-// One workgroup walks vectors of 8 counts with a grid stride and counts them
+// One workgroup walks a contiguous band of vectors of 8 counts and counts them
 // into bins privatized in LDS (or straight into global memory for large bin
 // counts), one atomic per run of equal values; LDS bins are flushed once per
 // workgroup.
@@ -96,19 +96,26 @@ __global__ __launch_bounds__(256) void k_histogram(const void *__restrict__ coun
       put8(c);
     }
   };
+  // Each workgroup takes one contiguous band of the composite: a band of a
+  // smooth composite holds few of its classes, so the workgroup's flush
+  // below touches few bins (with a grid stride every workgroup met every
+  // class, and the flush's global atomics, all workgroups' at once, were a
+  // visible part of the kernel).
   const uint32_t nv = npix / 8;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  // four grid-stride steps at a time, their loads issued before any atomic,
-  // so that each wave keeps several loads in flight (nv < 2^29: no overflow)
-  for (; v + 3 * stride < nv; v += 4 * stride) {
+  const uint32_t stride = blockDim.x;
+  const uint32_t per = (nv + gridDim.x - 1) / gridDim.x;
+  const uint32_t v1 = min(nv, blockIdx.x * per + per);  // nv < 2^29: no overflow
+  uint32_t v = blockIdx.x * per + threadIdx.x;
+  // four steps at a time, their loads issued before any atomic, so that each
+  // wave keeps several loads in flight
+  for (; v + 3 * stride < v1; v += 4 * stride) {
     vec_t x[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) load(v + u * stride, x[u]);
 #pragma unroll
     for (int u = 0; u < 4; ++u) count8(x[u]);
   }
-  for (; v < nv; v += stride) {
+  for (; v < v1; v += stride) {
     vec_t x;
     load(v, x);
     count8(x);
