@@ -57,3 +57,25 @@ def tile_read_ceiling(torch, ptr, stride, pitch, count, W, H, blocks, reps=6):
     if rc != 0:
         raise RuntimeError(f"tile_read_ceiling failed: hip error {rc}")
     return ms.value
+
+
+def two_phase_ceiling(torch, ptr, stride, n, npix, V, blocks_per_cu, reps=6):
+    """Best time in ms of the two-phase reference (reads of a band by the whole
+    grid, a grid-wide barrier, the band's writes, a barrier) over n device
+    rasters at ptr + i * stride of npix bytes each."""
+    lib = C.CDLL(LIB_PATH)
+    lib.two_phase_ceiling.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_int32, C.c_void_p, C.POINTER(C.c_float)]
+    cnt = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
+    sm = torch.zeros(npix, dtype=torch.int32, device="cuda:0")
+    mx = torch.zeros(npix, dtype=torch.uint8, device="cuda:0")
+    scratch = torch.zeros(2, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    ms = C.c_float()
+    rc = lib.two_phase_ceiling(ptr, stride, n, npix, cnt.data_ptr(), sm.data_ptr(), mx.data_ptr(), V,
+                               blocks_per_cu, scratch.data_ptr(), reps,
+                               torch.cuda.current_stream().cuda_stream, C.byref(ms))
+    if rc != 0:
+        raise RuntimeError(f"two_phase_ceiling failed: {rc}")
+    return ms.value

@@ -222,9 +222,149 @@ __global__ __launch_bounds__(256) void k_tile_reads(const uint8_t *__restrict__ 
   }
 }
 
+// Grid-wide barrier of a co-resident (cooperatively launched) grid: every
+// workgroup adds one to *bar per barrier, and barrier k is passed once *bar
+// reaches k * gridDim.x.  The wait is bounded: after `limit` polls the
+// workgroup sets *err and goes on, so the kernel always ends (its result is
+// then void and the host reports the error).
+__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t *err, uint32_t &target,
+                                             uint32_t limit) {
+  __syncthreads();
+  target += gridDim.x;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1u);
+    uint32_t polls = 0;
+    // once any wait has given up, no later one waits at all
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target &&
+           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      if (++polls >= limit) {
+        atomicOr(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// Mode 4's traffic with the reads and the writes of the whole grid kept apart:
+// the pixels go in bands of gridDim.x * 256 * V vectors; in each band every
+// thread reads all n members for its V vectors (non-temporal 16-byte loads,
+// two members' loads in flight), then, after a grid-wide barrier, writes
+// those vectors' 9 bytes per pixel, and a second barrier closes the band, so
+// that no read of the grid is in flight while the band is written.
+template <int V>
+__global__ __launch_bounds__(256) void k_two_phase(const uint8_t *__restrict__ mem, int64_t stride,
+                                                   int n, uint32_t *__restrict__ cnt,
+                                                   uint32_t *__restrict__ sum, uint8_t *__restrict__ mx,
+                                                   uint32_t nvec, uint32_t *bar, uint32_t *err,
+                                                   uint32_t limit) {
+  const uint32_t nthreads = gridDim.x * 256u;
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  uint32_t target = 0;
+  for (uint32_t base = 0; base < nvec; base += nthreads * V) {
+    uint32_t a[V][4];
+#pragma unroll
+    for (int u = 0; u < V; ++u) a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0u;
+    for (int i = 0; i < n; i += 2) {
+      u32x4 x[2][V];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const uint32_t idx = base + u * nthreads + t;
+          x[m][u] = (idx < nvec && i + m < n)
+                        ? __builtin_nontemporal_load((gu32x4 *)(mem + (int64_t)(i + m) * stride + idx * 16u))
+                        : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          a[u][0] += x[m][u].x;
+          a[u][1] += x[m][u].y;
+          a[u][2] += x[m][u].z;
+          a[u][3] ^= x[m][u].w;
+        }
+    }
+    grid_barrier(bar, err, target, limit);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const uint32_t idx = base + u * nthreads + t;
+      if (idx >= nvec) continue;
+      uint4 *c = reinterpret_cast<uint4 *>(cnt + idx * 16u);
+      uint4 *s = reinterpret_cast<uint4 *>(sum + idx * 16u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = make_uint4(a[u][0] + q, a[u][1], a[u][2], a[u][3]);
+        s[q] = make_uint4(a[u][0] ^ q, a[u][1], a[u][2], a[u][3]);
+      }
+      reinterpret_cast<uint4 *>(mx + idx * 16u)[0] = make_uint4(a[u][0] | 1u, a[u][1], a[u][2], a[u][3]);
+    }
+    grid_barrier(bar, err, target, limit);
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+// Runs k_two_phase<V> (V = 2, 4 or 8) reps times on `stream` with
+// blocks_per_cu workgroups per compute unit, launched cooperatively (the
+// runtime refuses a grid that cannot be resident at once), over n rasters at
+// members + i * stride (npix bytes each, a multiple of 16, 16-byte aligned)
+// and composite buffers as traffic_ceiling's; *best_ms: the fastest run after
+// the first.  scratch: 8 bytes of device memory (barrier counter and error
+// flag).  Returns 0, a hipError_t, or -1 if a barrier wait gave up.
+int two_phase_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t npix, void *count,
+                      void *sum, void *max, int32_t V, int32_t blocks_per_cu, void *scratch,
+                      int32_t reps, void *stream, float *best_ms) {
+  if (!members || !count || !sum || !max || !scratch || !best_ms || n < 1 || reps < 2 ||
+      npix < 16 || npix % 16 || npix > (int64_t(1) << 32) - 16 || stride < npix ||
+      (V != 2 && V != 4 && V != 8) || blocks_per_cu < 1 || blocks_per_cu > 8)
+    return (int)hipErrorInvalidValue;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return (int)e;
+  uint32_t nvec = (uint32_t)(npix / 16);
+  uint32_t *bar = static_cast<uint32_t *>(scratch), *err = bar + 1;
+  uint32_t limit = 1u << 20;  // polls of at most a few us: a wait gives up within seconds
+  const void *fn = V == 2 ? (const void *)k_two_phase<2>
+                   : V == 4 ? (const void *)k_two_phase<4> : (const void *)k_two_phase<8>;
+  void *args[] = {(void *)&members, (void *)&stride, (void *)&n, (void *)&count, (void *)&sum,
+                  (void *)&max, (void *)&nvec, (void *)&bar, (void *)&err, (void *)&limit};
+  hipEvent_t e0, e1;
+  e = hipEventCreate(&e0);
+  if (e != hipSuccess) return (int)e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return (int)e;
+  }
+  float best = 0.f;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipMemsetAsync(scratch, 0, 8, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess)
+      e = hipLaunchCooperativeKernel(fn, dim3((unsigned)(cus * blocks_per_cu)), dim3(256), args, 0, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && r > 0 && (r == 1 || ms < best)) best = ms;
+  }
+  uint32_t h[2] = {0u, 0u};
+  if (e == hipSuccess) e = hipMemcpy(h, scratch, 8, hipMemcpyDeviceToHost);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *best_ms = best;
+  if (e != hipSuccess) return (int)e;
+  return h[1] ? -1 : 0;
+}
 
 // Runs k_tile_reads reps times on `stream` with `blocks` workgroups over a
 // pool of count rasters of W x H (W >= 8), raster k's row y at

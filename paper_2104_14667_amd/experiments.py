@@ -67,6 +67,9 @@
 * ``tile-reads``: the batched matrix kernel's read pattern with trivial
   arithmetic over the batched pool's shape, rasters stored one after another
   or row-interleaved (row y of every raster side by side).
+* ``two-phase``: the set pass's traffic with the whole grid's reads and
+  writes kept apart band by band (grid-wide barriers of a cooperatively
+  launched grid), against the same traffic interleaved.
 * ``write-mix``: what the composite's read and write cost next to n member
   streams: the same-traffic reference kernel over n members of 8192x8192 with
   member reads only, plus the 9 B/px composite read, plus its write, plus both
@@ -80,7 +83,7 @@
 
 Usage: python -m paper_2104_14667_amd.experiments
            {repack-sweep,repack-rate,paper-table,kernel-table,h2d-sweep,subdivide,
-            member-layout,pool-layout,serve-layout,tile-reads,write-mix}
+            member-layout,pool-layout,serve-layout,tile-reads,two-phase,write-mix}
            [--out FILE]
 """
 
@@ -650,6 +653,33 @@ def tile_reads(blocks_per_cu=(1, 2, 4), pads=(0, 4096)) -> dict:
     return {"pool": P, "W": W, "H": H, "bytes": P * plane, "rows": rows}
 
 
+def two_phase(n=128, side=8192, configs=((2, 1), (2, 2), (4, 1), (4, 2), (8, 1), (8, 2))) -> dict:
+    """The set pass's traffic (n member streams read, the 9 B/px composite
+    written) with the grid's reads and writes kept apart by grid-wide
+    barriers, band by band, against the same traffic interleaved (mode 4 of
+    the reference)."""
+    import torch
+
+    from .ceiling import same_traffic_ceiling, two_phase_ceiling
+    plane = side * side
+    buf = torch.randint(0, 256, (n * plane + 64,), dtype=torch.uint8, device="cuda:0")
+    base = same_traffic_ceiling(torch, buf.data_ptr(), plane, n, plane, ((4, "set"), (0, "reads")))
+    rows = [{"variant": "interleaved (mode 4)", "ms": round(base["set"], 4)},
+            {"variant": "member reads only (mode 0)", "ms": round(base["reads"], 4)}]
+    for r in rows:
+        print(json.dumps(r), file=sys.stderr, flush=True)
+    for V, bpc in configs:
+        ms = two_phase_ceiling(torch, buf.data_ptr(), plane, n, plane, V, bpc)
+        rows.append({"variant": f"two-phase V={V}, {bpc} workgroups per CU", "V": V, "workgroups_per_cu": bpc,
+                     "bands": -(-plane // 16 // (torch.cuda.get_device_properties(0).multi_processor_count
+                                                  * bpc * 256 * V)), "ms": round(ms, 4)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    algo = n * plane + 9 * plane
+    for r in rows:
+        r["GBps_of_set_pass_bytes"] = round(algo / (r["ms"] * 1e-3) / 1e9, 1)
+    return {"members": n, "side": side, "rows": rows}
+
+
 def write_mix(ns=(16, 64, 128), side=8192, pad=0) -> dict:
     import torch
 
@@ -743,6 +773,8 @@ def main(argv=None):
     sl.add_argument("--out", default=None)
     tr = sub.add_parser("tile-reads")
     tr.add_argument("--out", default=None)
+    tp = sub.add_parser("two-phase")
+    tp.add_argument("--out", default=None)
     w = sub.add_parser("write-mix")
     w.add_argument("--ns", default="16,64,128")
     w.add_argument("--pad", type=int, default=0)
@@ -784,6 +816,9 @@ def main(argv=None):
         print(json.dumps(res))
     elif args.cmd == "tile-reads":
         res = tile_reads()
+        print(json.dumps(res))
+    elif args.cmd == "two-phase":
+        res = two_phase()
         print(json.dumps(res))
     elif args.cmd == "write-mix":
         res = write_mix(tuple(int(x) for x in args.ns.split(",")), pad=args.pad)
