@@ -35,14 +35,33 @@ struct Geom {
 };
 
 // 16 bytes of row-major raster s at (x, y), zero past its right and bottom
-// edges; bytes past the right edge are never read.
+// edges.  A vector that crosses the right edge is loaded whole when its 16
+// bytes lie inside the raster (they run into the next row) and the bytes past
+// the edge are cleared; only at the raster's very end, where a whole load
+// would leave the raster, it is read byte by byte, all 15 loads issued at
+// once.
 __device__ __forceinline__ uint4 load_vec(const uint8_t *__restrict__ s, const Geom &g, uint32_t x,
                                           uint32_t y) {
   if (y >= g.H || x >= g.W) return make_uint4(0u, 0u, 0u, 0u);
   const uint32_t off = y * g.W + x;  // < W * H < 2^32
   if (x + 16u <= g.W) return ld16(s, off);
+  const uint32_t nb = g.W - x;  // bytes of the vector inside the row: 1 .. 15
+  if ((uint64_t)off + 16u <= (uint64_t)g.W * g.H) {
+    const uint4 v = ld16(s, off);
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (uint32_t d = 0; d < 4; ++d) {
+      const uint32_t keep = nb >= 4 * d + 4 ? 4u : (nb > 4 * d ? nb - 4 * d : 0u);  // bytes kept
+      w[d] &= keep == 4u ? 0xffffffffu : (1u << (8 * keep)) - 1u;
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  uint32_t b[15];
+#pragma unroll
+  for (uint32_t k = 0; k < 15; ++k) b[k] = k < nb ? (uint32_t)s[off + k] : 0u;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
-  for (uint32_t k = 0; k < g.W - x; ++k) w[k >> 2] |= (uint32_t)s[off + k] << (8 * (k & 3));
+#pragma unroll
+  for (uint32_t k = 0; k < 15; ++k) w[k >> 2] |= b[k] << (8 * (k & 3));
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
