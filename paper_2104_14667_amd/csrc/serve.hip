@@ -8,8 +8,12 @@
 //   worker            forms a step from the queue (the oldest request of each
 //                     session, at most max_batch), makes the step's sessions
 //                     resident, uploads the step's descriptors and launches
-//                     one update kernel on the compute stream; the copy
-//                     stream then moves the viewports to host memory;
+//                     the update kernel on the compute stream; the copy
+//                     stream then moves the viewports to host memory.  Unless
+//                     a full step's worth of requests already waits, the rows
+//                     holding viewports are launched first and the rest
+//                     second, so that the viewport copy overlaps the rest of
+//                     the update;
 //   completer         waits for each step's copies in order and completes its
 //                     requests (timestamps, waiters).
 // At most two steps are in flight; their descriptors, staging and events
@@ -72,7 +76,7 @@ static_assert(sizeof(SHeader) == 64, "arena header is 64 bytes");
 template <bool C16>
 __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base, int64_t stride,
                                                int32_t W, const char *__restrict__ arena,
-                                               uint32_t *__restrict__ queue) {
+                                               uint32_t *__restrict__ queue, int32_t item0) {
   const SHeader *hd = reinterpret_cast<const SHeader *>(arena);
   const int nitems = hd->nitems;
   const SReq *reqs = reinterpret_cast<const SReq *>(arena + hd->reqs_off);
@@ -90,8 +94,9 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       it = __builtin_amdgcn_readfirstlane(s_item);
       __syncthreads();
     } else {
-      // one item per workgroup: no queue, no barrier
-      it = pass == 0 ? (int)blockIdx.x : nitems;
+      // one item per workgroup (items item0 .. item0 + gridDim.x - 1): no
+      // queue, no barrier
+      it = pass == 0 ? item0 + (int)blockIdx.x : nitems;
     }
     if (it >= nitems) break;  // the queue counter only grows: every wave exits
     const SItem I = items[it];
@@ -243,6 +248,7 @@ struct cmp_server {
   int64_t arena_cap = 0;
   uint32_t *stage[2] = {nullptr, nullptr};
   hipEvent_t ev_k0[2] = {nullptr, nullptr}, ev_k1[2] = {nullptr, nullptr};
+  hipEvent_t ev_view[2] = {nullptr, nullptr};  // the step's viewport rows are final
   hipEvent_t ev_copied[2] = {nullptr, nullptr};
 
   std::mutex mu;
@@ -360,6 +366,7 @@ void worker_body(cmp_server *s) {
   for (;;) {
     std::vector<Request> step;
     uint64_t index;
+    bool backlog = false;  // a full step's worth of requests still waiting
     {
       std::unique_lock<std::mutex> lk(s->mu);
       // a paused server forms no step (free stops it anyway, after draining)
@@ -380,6 +387,7 @@ void worker_body(cmp_server *s) {
           ++it;
         }
       }
+      backlog = s->queue.size() >= (size_t)s->o.max_batch;
     }
     const int half = (int)(index & 1);
     std::unordered_set<int64_t> in_step;
@@ -387,7 +395,7 @@ void worker_body(cmp_server *s) {
     // residency and descriptors (slots are touched by this thread only)
     std::vector<SReq> rd(step.size());
     std::vector<std::vector<int32_t>> rebuilt(step.size());  // ids of rebuilt composites
-    std::vector<SItem> items;
+    std::vector<SItem> items, rest;  // work items: rows of viewports, the other rows
     int64_t nids = 0;
     hipError_t e = hipSuccess;
     // Residency changes hold the lock: sessions may be opened and closed
@@ -432,8 +440,16 @@ void worker_body(cmp_server *s) {
       nids += d.n;
       const int nvr = s->W / 16;
       const int rows = std::max(1, s->o.tile_vecs / nvr);
-      for (int r0 = 0; r0 < s->H; r0 += rows) items.push_back(SItem{(int32_t)k, r0, std::min(rows, s->H - r0), 0});
+      // items holding viewport rows first: their launch ends before the
+      // rest's, and the viewport copy overlaps the rest
+      for (int r0 = 0; r0 < s->H; r0 += rows) {
+        const SItem it{(int32_t)k, r0, std::min(rows, s->H - r0), 0};
+        if (r0 < r.vy0 + r.vh && r0 + it.nrows > r.vy0) items.push_back(it);
+        else rest.push_back(it);
+      }
     }
+    const int64_t nview = (int64_t)items.size();
+    items.insert(items.end(), rest.begin(), rest.end());
     lk.unlock();
     if (e != hipSuccess) {
       fail(s, CMP_EDEVICE);
@@ -471,16 +487,32 @@ void worker_body(cmp_server *s) {
     e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
     if (e == hipSuccess && persistent) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
     if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);
-    if (e == hipSuccess && grid > 0) {
-      uint32_t *q = persistent ? s->d_queue : nullptr;
+    auto launch = [&](int g, uint32_t *q, int32_t item0) {
+      if (g <= 0) return hipSuccess;
       if (s->o.count_bits == 16)
-        k_serve<true><<<grid, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q);
+        k_serve<true><<<g, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q, item0);
       else
-        k_serve<false><<<grid, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q);
-      e = hipGetLastError();
+        k_serve<false><<<g, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q, item0);
+      return hipGetLastError();
+    };
+    if (persistent) {
+      // one persistent grid over all items; the viewports are final at its end
+      if (e == hipSuccess) e = launch(grid, s->d_queue, 0);
+      if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
+    } else if (backlog) {
+      // the next step is full already: one launch, the least device time
+      if (e == hipSuccess) e = launch(grid, nullptr, 0);
+      if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
+    } else {
+      // the viewport rows' items, then the rest, so that the viewport copy
+      // starts after the first launch and overlaps the second (lower latency
+      // for a few more microseconds of device time)
+      if (e == hipSuccess) e = launch((int)nview, nullptr, 0);
+      if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
+      if (e == hipSuccess) e = launch((int)((int64_t)items.size() - nview), nullptr, (int32_t)nview);
     }
     if (e == hipSuccess) e = hipEventRecord(s->ev_k1[half], s->comp);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s->copy, s->ev_k1[half], 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->copy, s->ev_view[half], 0);
     for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
       const Request &r = step[k];
       e = hipMemcpy2DAsync(r.dst, (size_t)r.pitch * 4, rd[k].stage, (size_t)r.vw * 4,
@@ -525,10 +557,14 @@ void completer_loop(cmp_server *s) {
       }
       st = s->steps.front();
     }
+    // the step's requests are complete once their viewports are copied out;
+    // the rows outside the viewports may still be updating then (later
+    // steps' kernels follow them on the compute stream)
     const hipError_t e = hipEventSynchronize(s->ev_copied[st.half]);
     const int64_t t = now_ns();
     float ms = 0.f;
-    const hipError_t e2 = e == hipSuccess ? hipEventElapsedTime(&ms, s->ev_k0[st.half], s->ev_k1[st.half]) : e;
+    hipError_t e2 = e == hipSuccess ? hipEventSynchronize(s->ev_k1[st.half]) : e;
+    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, s->ev_k0[st.half], s->ev_k1[st.half]);
     std::lock_guard<std::mutex> lk(s->mu);
     s->steps.pop_front();
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -611,6 +647,7 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i)
       ok = hipEventCreate(&s->ev_k0[i]) == hipSuccess && hipEventCreate(&s->ev_k1[i]) == hipSuccess &&
+           hipEventCreateWithFlags(&s->ev_view[i], hipEventDisableTiming) == hipSuccess &&
            hipEventCreateWithFlags(&s->ev_copied[i], hipEventDisableTiming) == hipSuccess;
     if (!ok) break;
     rc = CMP_ENOMEM;
@@ -675,6 +712,7 @@ void composite_server_free(cmp_server *s) {
     (void)hipFree(s->stage[i]);
     if (s->ev_k0[i]) (void)hipEventDestroy(s->ev_k0[i]);
     if (s->ev_k1[i]) (void)hipEventDestroy(s->ev_k1[i]);
+    if (s->ev_view[i]) (void)hipEventDestroy(s->ev_view[i]);
     if (s->ev_copied[i]) (void)hipEventDestroy(s->ev_copied[i]);
   }
   if (s->comp) (void)hipStreamDestroy(s->comp);
