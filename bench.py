@@ -569,6 +569,8 @@ def run_served(torch, duration_s, extra=False, cpu_seconds=3.0):
     n = int(wl.rate * duration_s)
     sched = wl.schedule(n)
     budget = wl.sessions // 2 * plane * 4          # 8 GiB
+    # viewport buffers of uint32 counts; a uint16 server's viewport fills the
+    # first half of one
     ring = [torch.empty((wl.view, wl.view), dtype=torch.int32, pin_memory=True) for _ in range(128)]
     out = {"workload": "served: 256 sessions x 4096x4096 counts, pool 1024 depth maps, "
                        "Poisson 2000 req/s, add/remove 1-32 members (60/40), 1024x1024 viewport",
@@ -599,7 +601,8 @@ def run_served(torch, duration_s, extra=False, cpu_seconds=3.0):
             lvs = np.sort(np.repeat(lv[list(c)], list(c.values()))) if c else np.zeros(0, lv.dtype)
             ev = e[y0:y0 + wl.view, x0:x0 + wl.view]
             exp = len(lvs) - np.searchsorted(lvs, ev, side="right")
-            ok = ok and bool(np.array_equal(dst.numpy().view(np.uint32), exp))
+            got = dst.numpy().reshape(-1).view(srv.count_dtype)[: wl.view * wl.view]
+            ok = ok and bool(np.array_equal(got.reshape(wl.view, wl.view), exp))
         return ok, len(pick)
 
     def one(name, roofline=False, **opts):
@@ -644,6 +647,14 @@ def run_served(torch, duration_s, extra=False, cpu_seconds=3.0):
                "device_ms_per_request": round(st["device_ms"] / max(1, st["requests"]), 4),
                "gpx_member_per_s": round(pxm / wall / 1e9, 1),
                "exact": exact, "sessions_checked": checked}
+        # mean milliseconds of a request's latency: queued, host preparation,
+        # in flight (device, copies, completion seen); per step on the
+        # device: start to viewport rows final, then to viewports copied out
+        nq, ns = max(1, st["requests"]), max(1, st["steps"])
+        res["latency_breakdown"] = {
+            "wait_ms": round(st["wait_ms"] / nq, 4), "host_ms": round(st["host_ms"] / nq, 4),
+            "flight_ms": round(st["flight_ms"] / nq, 4),
+            "step_view_ms": round(st["view_ms"] / ns, 4), "step_copy_ms": round(st["copy_ms"] / ns, 4)}
         out[name] = res
         if roofline and st["device_ms"] > 0 and st["drops"] + st["spills"] == 0:
             # HBM bytes the step kernels must move per request: its members
@@ -655,7 +666,8 @@ def run_served(torch, duration_s, extra=False, cpu_seconds=3.0):
                     continue
                 first = r["sid"] not in seen
                 seen.add(r["sid"])
-                byts += len(r["ids"]) * plane + (1 if first else 2) * cb // 8 * plane + 4 * r["vw"] * r["vh"]
+                byts += (len(r["ids"]) * plane + (1 if first else 2) * cb // 8 * plane
+                         + cb // 8 * r["vw"] * r["vh"])
             ach = byts / (st["device_ms"] * 1e-3) / 1e9
             res["roofline"] = {"bound": "hbm", "kernel": f"k_serve<u{cb}>", "unit": "GB/s", "peak": 8000.0,
                                "achieved": round(ach, 1), "frac": round(ach / 8000.0, 4),

@@ -362,11 +362,14 @@ int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items, int32
  * pool, with its own device-resident uint32 count composite of the pool's
  * W x H (uint32, or uint16 with count_bits = 16).  A request adds or removes
  * pool members and asks for a viewport of the updated composite; the viewport
- * is always returned as uint32 counts.  One server thread batches continuously: every step
- * takes the oldest queued request of each session (at most max_batch), runs
- * one launch that updates all their composites and writes their viewports to
- * device staging, and queues the copies of the viewports to host memory on a
- * second stream, so the next step's launch overlaps them.  Requests of one
+ * is returned in the composite's width (uint16 counts with count_bits = 16,
+ * uint32 with 32).  One server thread batches continuously: every step takes
+ * the oldest queued request of each session (at most max_batch), updates all
+ * their composites and writes their viewports to device staging (the rows
+ * holding viewports in a first launch and the other rows in a second, unless
+ * a full step's worth of requests already waits), and queues the copies of
+ * the viewports to host memory on a second stream after the first launch, so
+ * the copies overlap the rest of the update and the next step.  Requests of one
  * session are applied in submission order; sessions interleave.  Session
  * composites live in a device slab of hbm_budget_bytes; when a request needs
  * a session that is not resident and the slab is full, a session that is not
@@ -457,8 +460,8 @@ int composite_session_close(cmp_server *srv, int64_t sid);
 
 /* Queues one request: op (cmp_op) of n pool ids, then the viewport
  * (vx0, vy0, vw, vh) of the session's count composite copied to dst (host
- * memory allocated page-locked, vh rows of vw uint32 with dst_pitch elements
- * between rows).  The request is validated against the session's working set
+ * memory allocated page-locked, vh rows of vw counts with dst_pitch elements
+ * between rows; a count is a uint16 with count_bits = 16, else a uint32).  The request is validated against the session's working set
  * as it will be after all its earlier requests: removing an id it will not
  * hold gives CMP_ENOTMEMBER, and with count_bits = 16 an add that would take
  * it past 65535 members gives CMP_ERANGE.  CMP_EBUSY when max_queue requests
@@ -468,7 +471,7 @@ int composite_session_close(cmp_server *srv, int64_t sid);
  * valid and untouched until the request completes. */
 int composite_session_submit(cmp_server *srv, int64_t sid, int32_t op, const int32_t *ids,
                              int32_t n, int32_t vx0, int32_t vy0, int32_t vw, int32_t vh,
-                             uint32_t *dst, int64_t dst_pitch, uint64_t *ticket);
+                             void *dst, int64_t dst_pitch, uint64_t *ticket);
 
 /* Waits until the request is complete (its viewport is in dst) or timeout_us
  * passes (CMP_ETIMEDOUT; negative waits forever).  Optionally returns the
@@ -487,6 +490,16 @@ typedef struct cmp_server_stats {
   int64_t refused_sessions;  /* session opens refused by admission */
   int64_t refused_busy;      /* submits refused because the queue was full */
   int64_t queue_peak;        /* most requests waiting for a step at once */
+  /* Where the latency goes, summed over completed requests (divide by
+   * `requests` for means): from submit until a step takes the request; from
+   * then until the step's last launch and copy are enqueued (residency,
+   * descriptors, launches); from then until its viewport is in host memory
+   * and the completion is seen. */
+  double wait_ms, host_ms, flight_ms;
+  /* Device time summed over steps (divide by `steps`): from the step's start
+   * until its viewport rows are final, and from then until its viewports are
+   * in host memory (the copy stream's wait and the copies). */
+  double view_ms, copy_ms;
 } cmp_server_stats;
 
 /* Counters since the server was created. */
@@ -511,7 +524,7 @@ typedef struct cmp_replay_req {
 /* Submits the requests at their arrival times from the calling thread (an
  * open-loop Poisson schedule does not wait for completions), then waits for
  * all of them.  Request i copies its viewport to dst_ring[i % ring] (pinned
- * host buffers of at least vh * dst_pitch uint32).  latency_ns[i] = completion
+ * host buffers of at least vh * dst_pitch counts of the composite's width).  latency_ns[i] = completion
  * time - scheduled arrival time, or -1 for a request that did not complete.
  * status: NULL, or nreq entries that receive each request's status.  With
  * status, a request refused by submit with CMP_EBUSY, CMP_ENOTMEMBER (it
@@ -520,7 +533,7 @@ typedef struct cmp_replay_req {
  * status is NULL, ends the replay (requests after it get CMP_ECANCELED).
  * Returns the first status that ended it, else CMP_OK. */
 int composite_server_replay(cmp_server *srv, const cmp_replay_req *reqs, int64_t nreq,
-                            const int32_t *ids, uint32_t *const *dst_ring, int32_t ring,
+                            const int32_t *ids, void *const *dst_ring, int32_t ring,
                             int64_t dst_pitch, int64_t *latency_ns, int32_t *status);
 
 /* Histogram of overlap classes (Figure 1, lower-left panel: the frequency of

@@ -78,7 +78,8 @@ class cmp_server_stats(C.Structure):
                 ("spills", C.c_int64), ("restores", C.c_int64), ("resident_slots", C.c_int64),
                 ("device_ms", C.c_double), ("drops", C.c_int64), ("rebuilds", C.c_int64),
                 ("refused_sessions", C.c_int64), ("refused_busy", C.c_int64),
-                ("queue_peak", C.c_int64)]
+                ("queue_peak", C.c_int64), ("wait_ms", C.c_double), ("host_ms", C.c_double),
+                ("flight_ms", C.c_double), ("view_ms", C.c_double), ("copy_ms", C.c_double)]
 
 
 class cmp_replay_req(C.Structure):
@@ -539,6 +540,12 @@ class Server:
                "composite_server_create")
         self.handle = h.value
 
+    @property
+    def count_dtype(self):
+        """numpy dtype of the returned viewport counts: the session
+        composites' width (uint16 with count_bits = 16, else uint32)."""
+        return np.uint16 if self.opts.count_bits == 16 else np.uint32
+
     def open(self) -> int:
         sid = C.c_int64()
         _check(lib.composite_session_open(self.handle, C.byref(sid)), "composite_session_open")
@@ -560,7 +567,8 @@ class Server:
         _check(lib.composite_session_close(self.handle, int(sid)), "composite_session_close")
 
     def submit(self, sid: int, op: int, ids, viewport, dst, pitch: Optional[int] = None) -> int:
-        """dst: page-locked host memory (a pinned torch tensor or its address)."""
+        """dst: page-locked host memory (a pinned torch tensor or its address)
+        of counts of the width count_dtype gives."""
         ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int32))
         vx0, vy0, vw, vh = viewport
         t = C.c_uint64()

@@ -52,7 +52,7 @@ enum : int32_t { kModeAdd = 0, kModeSub = 1, kModeSet = 2 };
 
 struct SReq {
   void *comp;         // session composite (device): uint16 or uint32 counts
-  uint32_t *stage;    // viewport staging (device), vh rows of vw
+  void *stage;        // viewport staging (device), vh rows of vw counts of the composite's width
   int32_t mode, ids_off, n;  // kMode*: composite += / -= / = count of ids
   int32_t vx0, vy0, vw, vh;
   int32_t pad;
@@ -70,7 +70,8 @@ static_assert(sizeof(SHeader) == 64, "arena header is 64 bytes");
 // One work item: rows [row0, row0 + nrows) of a session composite.  Each thread
 // updates 16 pixels (count +/- the nonzero members, or count set to that of
 // the whole working set when the composite is rebuilt) and copies the pixels
-// that fall in the request's viewport to staging (always uint32).  C16: the
+// that fall in the request's viewport to staging (in the composite's width:
+// uint16 or uint32, as they are returned to the caller).  C16: the
 // session composites are uint16 (the server refuses a request that would take
 // a session past 65535 members, so no lane carries into its neighbour).
 template <bool C16>
@@ -178,7 +179,10 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
 #pragma unroll
         for (int k = 0; k < 16; ++k)
           if (x + k >= R.vx0 && x + k < R.vx0 + R.vw)
-            ((__attribute__((address_space(1))) uint32_t *)R.stage)[row_base + (x + k - R.vx0)] = nv[k];
+            if constexpr (C16)
+              ((__attribute__((address_space(1))) uint16_t *)R.stage)[row_base + (x + k - R.vx0)] = (uint16_t)nv[k];
+            else
+              ((__attribute__((address_space(1))) uint32_t *)R.stage)[row_base + (x + k - R.vx0)] = nv[k];
       }
     }
   }
@@ -196,7 +200,7 @@ struct Request {
   int32_t op;
   std::vector<int32_t> ids;
   int32_t vx0, vy0, vw, vh;
-  uint32_t *dst;
+  void *dst;  // vh rows of vw counts (uint16 or uint32: the composite's width)
   int64_t pitch;
   int64_t t_submit;
 };
@@ -227,6 +231,7 @@ struct Step {
   std::vector<int64_t> sids;
   int half;
   uint64_t index;
+  int64_t t_formed, t_enq;  // requests taken from the queue; last enqueue done
 };
 
 }  // namespace
@@ -389,6 +394,7 @@ void worker_body(cmp_server *s) {
       }
       backlog = s->queue.size() >= (size_t)s->o.max_batch;
     }
+    const int64_t t_formed = now_ns();
     const int half = (int)(index & 1);
     std::unordered_set<int64_t> in_step;
     for (auto &r : step) in_step.insert(r.sid);
@@ -423,7 +429,7 @@ void worker_body(cmp_server *s) {
       ss->last_use = ++s->use_clock;
       SReq &d = rd[k];
       d.comp = s->slab + (int64_t)ss->slot * s->comp_bytes;
-      d.stage = s->stage[half] + (int64_t)k * view_stride;
+      d.stage = s->stage[half] + (int64_t)k * view_stride;  // slots of max_view_pixels uint32
       d.mode = rebuild ? kModeSet : r.op == CMP_OP_REMOVE ? kModeSub : kModeAdd;
       if (rebuild) {
         std::vector<int32_t> &v = rebuilt[k];
@@ -515,8 +521,9 @@ void worker_body(cmp_server *s) {
     if (e == hipSuccess) e = hipStreamWaitEvent(s->copy, s->ev_view[half], 0);
     for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
       const Request &r = step[k];
-      e = hipMemcpy2DAsync(r.dst, (size_t)r.pitch * 4, rd[k].stage, (size_t)r.vw * 4,
-                           (size_t)r.vw * 4, (size_t)r.vh, hipMemcpyDeviceToHost, s->copy);
+      const size_t el = (size_t)s->o.count_bits / 8;  // bytes per returned count
+      e = hipMemcpy2DAsync(r.dst, (size_t)r.pitch * el, rd[k].stage, (size_t)r.vw * el,
+                           (size_t)r.vw * el, (size_t)r.vh, hipMemcpyDeviceToHost, s->copy);
     }
     if (e == hipSuccess) e = hipEventRecord(s->ev_copied[half], s->copy);
     if (e != hipSuccess) {
@@ -528,6 +535,8 @@ void worker_body(cmp_server *s) {
       Step st;
       st.half = half;
       st.index = index;
+      st.t_formed = t_formed;
+      st.t_enq = now_ns();
       for (auto &r : step) {
         st.tickets.push_back(r.ticket);
         st.sids.push_back(r.sid);
@@ -562,18 +571,27 @@ void completer_loop(cmp_server *s) {
     // steps' kernels follow them on the compute stream)
     const hipError_t e = hipEventSynchronize(s->ev_copied[st.half]);
     const int64_t t = now_ns();
-    float ms = 0.f;
+    float ms = 0.f, view_ms = 0.f, copy_ms = 0.f;
     hipError_t e2 = e == hipSuccess ? hipEventSynchronize(s->ev_k1[st.half]) : e;
     if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, s->ev_k0[st.half], s->ev_k1[st.half]);
+    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&view_ms, s->ev_k0[st.half], s->ev_view[st.half]);
+    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&copy_ms, s->ev_view[st.half], s->ev_copied[st.half]);
     std::lock_guard<std::mutex> lk(s->mu);
     s->steps.pop_front();
     if (e != hipSuccess || e2 != hipSuccess) {
       if (s->failed == CMP_OK) s->failed = CMP_EDEVICE;
     }
     s->st.device_ms += ms;
+    s->st.view_ms += view_ms;
+    s->st.copy_ms += copy_ms;
     for (size_t k = 0; k < st.tickets.size(); ++k) {
       auto it = s->done.find(st.tickets[k]);
-      if (it != s->done.end()) it->second.t_done = t;
+      if (it != s->done.end()) {
+        it->second.t_done = t;
+        s->st.wait_ms += 1e-6 * (double)(st.t_formed - it->second.t_submit);
+        s->st.host_ms += 1e-6 * (double)(st.t_enq - st.t_formed);
+        s->st.flight_ms += 1e-6 * (double)(t - st.t_enq);
+      }
       s->pending.erase(st.tickets[k]);
       s->sessions[st.sids[k]].inflight -= 1;
       s->st.requests += 1;
@@ -647,8 +665,7 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i)
       ok = hipEventCreate(&s->ev_k0[i]) == hipSuccess && hipEventCreate(&s->ev_k1[i]) == hipSuccess &&
-           hipEventCreateWithFlags(&s->ev_view[i], hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&s->ev_copied[i], hipEventDisableTiming) == hipSuccess;
+           hipEventCreate(&s->ev_view[i]) == hipSuccess && hipEventCreate(&s->ev_copied[i]) == hipSuccess;
     if (!ok) break;
     rc = CMP_ENOMEM;
     if (hipMalloc((void **)&s->slab, nslots * comp_bytes) != hipSuccess) break;
@@ -763,7 +780,7 @@ int composite_session_close(cmp_server *s, int64_t sid) {
 }
 
 int composite_session_submit(cmp_server *s, int64_t sid, int32_t op, const int32_t *ids, int32_t n,
-                             int32_t vx0, int32_t vy0, int32_t vw, int32_t vh, uint32_t *dst,
+                             int32_t vx0, int32_t vy0, int32_t vw, int32_t vh, void *dst,
                              int64_t dst_pitch, uint64_t *ticket) {
   if (!s || !ticket) return CMP_EINVAL;
   if (op != CMP_OP_ADD && op != CMP_OP_REMOVE) return CMP_EINVAL;
@@ -861,7 +878,7 @@ int composite_server_stats(cmp_server *s, cmp_server_stats *st) {
 }
 
 int composite_server_replay(cmp_server *s, const cmp_replay_req *reqs, int64_t nreq, const int32_t *ids,
-                            uint32_t *const *dst_ring, int32_t ring, int64_t dst_pitch,
+                            void *const *dst_ring, int32_t ring, int64_t dst_pitch,
                             int64_t *latency_ns, int32_t *status) {
   if (!s || nreq < 0 || (nreq > 0 && (!reqs || !dst_ring || ring < 1 || !latency_ns))) return CMP_EINVAL;
   std::vector<uint64_t> tickets(nreq, 0);

@@ -583,8 +583,8 @@ def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: in
     buf = torch.empty(wl.pool * (plane + max(pads)) + 64, dtype=torch.uint8, device="cuda:0")
     sched = wl.schedule(int(wl.rate * seconds))
     budget = wl.sessions // 2 * plane * 4
-    ring = [torch.empty((wl.view, wl.view), dtype=torch.int32, pin_memory=True) for _ in range(64)]
-    dst = torch.empty((wl.view, wl.view), dtype=torch.int32, pin_memory=True)
+    ring = [torch.empty((wl.view, wl.view), dtype=torch.int16, pin_memory=True) for _ in range(64)]
+    dst = torch.empty((wl.view, wl.view), dtype=torch.int16, pin_memory=True)
     rows = []
     for pad in pads:
         stride = plane + pad
@@ -613,7 +613,7 @@ def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: in
                     c = cur[k]
                     lvs = np.sort(np.repeat(lv[list(c)], list(c.values()))) if c else np.zeros(0, lv.dtype)
                     exp = len(lvs) - np.searchsorted(lvs, e[:wl.view, :wl.view], side="right")
-                    exact &= bool(np.array_equal(dst.numpy().view(np.uint32), exp))
+                    exact &= bool(np.array_equal(dst.numpy().view(np.uint16), exp))
         ok = status == 0
         lat_ms = lat[ok] / 1e6
         nreq = st["requests"] - st0["requests"]

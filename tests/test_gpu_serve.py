@@ -25,6 +25,17 @@ def _pool(stack):
     return buf
 
 
+def _vbuf(cb, shape, fill=0):
+    """Page-locked host buffer for viewport counts of a server whose session
+    composites hold cb bits (viewports come back in that width)."""
+    return torch.full(shape, fill, dtype=torch.int16 if cb == 16 else torch.int32, pin_memory=True)
+
+
+def _counts(t):
+    """Viewport counts of a buffer made by _vbuf, as int64."""
+    return t.numpy().view(np.uint16 if t.dtype == torch.int16 else np.uint32).astype(np.int64)
+
+
 def _small(seed=0, sessions=5, pool=40, H=48, W=64, n=160):
     wl = synth.ServeWorkload(sessions=sessions, pool=pool, H=H, W=W, sigma=4.0, view=16,
                              k_lo=1, k_hi=6, seed=seed)
@@ -38,7 +49,7 @@ def _run_mix(srv, wl, sched, view_dims=None):
     sids = [srv.open() for _ in range(wl.sessions)]
     outs, tickets = [], []
     for r in sched:
-        dst = torch.full((r["vh"], r["vw"]), -1, dtype=torch.int32, pin_memory=True)
+        dst = _vbuf(srv.opts.count_bits, (r["vh"], r["vw"]), -1)
         op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
         tickets.append(srv.submit(sids[r["sid"]], op, r["ids"],
                                   (r["vx0"], r["vy0"], r["vw"], r["vh"]), dst))
@@ -53,7 +64,7 @@ def _check_alone(wl, stack, sched, outs):
         idx = [i for i, r in enumerate(sched) if r["sid"] == sid]
         views = oracle.replay_session(stack, [sched[i] for i in idx])
         for i, v in zip(idx, views):
-            got = outs[i].numpy().view(np.uint32).astype(np.int64)
+            got = _counts(outs[i])
             assert np.array_equal(got, v["count"]), f"request {i} (session {sid})"
 
 
@@ -97,7 +108,7 @@ def test_submit_validation():
     wl, stack, sched = _small(seed=3, n=10)
     P, H, W = stack.shape
     buf = _pool(stack)
-    dst = torch.zeros((16, 16), dtype=torch.int32, pin_memory=True)
+    dst = _vbuf(32, (16, 16), 0)
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=4, hbm_budget_bytes=8 * H * W * 4, max_view_pixels=256,
                     max_sessions=2) as srv:
@@ -148,14 +159,15 @@ def test_heavy_requests_automatic_launch(bpc):
     _check_alone(wl, stack, sched, outs)
 
 
-def test_replay_small_open_loop():
+@pytest.mark.parametrize("cb", [32, 16])
+def test_replay_small_open_loop(cb):
     wl, stack, sched = _small(seed=5, n=300)
     P, H, W = stack.shape
     buf = _pool(stack)
-    ring = [torch.zeros((16, 16), dtype=torch.int32, pin_memory=True) for _ in range(8)]
+    ring = [_vbuf(cb, (16, 16), 0) for _ in range(8)]
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=16, hbm_budget_bytes=16 * H * W * 4, max_view_pixels=256,
-                    tile_vecs=64, blocks_per_cu=2) as srv:
+                    tile_vecs=64, blocks_per_cu=2, count_bits=cb) as srv:
             sids = [srv.open() for _ in range(wl.sessions)]
             sched = [dict(r, t=r["t"] * 0.25) for r in sched]      # 8000 req/s offered
             lat = srv.replay(sched, sids, ring, 16)
@@ -190,7 +202,7 @@ def test_full_served_shape_bursts(remat, cb):
                 burst = sched[b0:b0 + 64]
                 outs, tickets = [], []
                 for r in burst:
-                    dst = torch.empty((r["vh"], r["vw"]), dtype=torch.int32, pin_memory=True)
+                    dst = _vbuf(cb, (r["vh"], r["vw"]), 0)
                     op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
                     tickets.append(srv.submit(sids[r["sid"]], op, r["ids"],
                                               (r["vx0"], r["vy0"], r["vw"], r["vh"]), dst))
@@ -206,7 +218,7 @@ def test_full_served_shape_bursts(remat, cb):
                     lvs = np.sort(lv[held[r["sid"]]])
                     ev = e[r["vy0"]:r["vy0"] + r["vh"], r["vx0"]:r["vx0"] + r["vw"]]
                     exp = len(lvs) - np.searchsorted(lvs, ev, side="right")
-                    assert np.array_equal(dst.numpy().view(np.uint32), exp)
+                    assert np.array_equal(_counts(dst), exp)
             st = srv.stats()
             assert st["requests"] == len(sched)
             if remat:
@@ -237,7 +249,7 @@ def test_threaded_submitters_and_close_semantics():
                 for i, r in enumerate(sched):
                     if r["sid"] != sid_idx:
                         continue
-                    dst = torch.full((r["vh"], r["vw"]), -1, dtype=torch.int32, pin_memory=True)
+                    dst = _vbuf(32, (r["vh"], r["vw"]), -1)
                     op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
                     tickets.append(srv.submit(sids[sid_idx], op, r["ids"],
                                               (r["vx0"], r["vy0"], r["vw"], r["vh"]), dst))
@@ -298,7 +310,7 @@ def test_admission_refuses_with_state_unchanged(cb, pct):
             # every admitted session serves, in the mix, what it serves alone
             outs = []
             for r in sched:
-                dst = torch.full((r["vh"], r["vw"]), -1, dtype=torch.int32, pin_memory=True)
+                dst = _vbuf(cb, (r["vh"], r["vw"]), -1)
                 op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
                 outs.append((srv.submit(sids[r["sid"]], op, r["ids"],
                                         (r["vx0"], r["vy0"], r["vw"], r["vh"]), dst), dst))
@@ -311,11 +323,11 @@ def test_admission_refuses_with_state_unchanged(cb, pct):
             with pytest.raises(CompositeError) as ei:
                 srv.open()
             assert ei.value.status == CMP_ENOMEM
-            dst = torch.full((16, 16), -1, dtype=torch.int32, pin_memory=True)
+            dst = _vbuf(cb, (16, 16), -1)
             srv.wait(srv.submit(sid, CMP_OP_ADD, [0, 1], (0, 0, 16, 16), dst))
             held = {0: 1, 1: 1}
             exp = _expect_view(stack, held, dict(vx0=0, vy0=0, vw=16, vh=16))
-            assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64), exp)
+            assert np.array_equal(_counts(dst), exp)
 
 
 def test_queue_bound_refuses_busy_with_state_unchanged():
@@ -335,10 +347,10 @@ def test_queue_bound_refuses_busy_with_state_unchanged():
                     (b, CMP_OP_REMOVE, [3])]
             views, tickets = [], []
             for sid, op, ids in plan:
-                dst = torch.full((16, 16), -1, dtype=torch.int32, pin_memory=True)
+                dst = _vbuf(32, (16, 16), -1)
                 tickets.append(srv.submit(sid, op, ids, (0, 0, 16, 16), dst))
                 views.append(dst)
-            spare = torch.full((16, 16), -7, dtype=torch.int32, pin_memory=True)
+            spare = _vbuf(32, (16, 16), -7)
             with pytest.raises(CompositeError) as ei:
                 srv.submit(a, CMP_OP_ADD, [5], (0, 0, 16, 16), spare)
             assert ei.value.status == CMP_EBUSY
@@ -356,7 +368,7 @@ def test_queue_bound_refuses_busy_with_state_unchanged():
                 for i in ids:
                     held[sid][i] = held[sid].get(i, 0) + (1 if op == CMP_OP_ADD else -1)
                 exp = _expect_view(stack, held[sid], dict(vx0=0, vy0=0, vw=16, vh=16))
-                assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64), exp)
+                assert np.array_equal(_counts(dst), exp)
             assert srv.stats()["requests"] == len(plan)
 
 
@@ -373,11 +385,11 @@ def test_uint16_sessions_at_their_limit():
         with Server(pool, max_batch=1, hbm_budget_bytes=H * W * 2, max_view_pixels=H * W,
                     tile_vecs=64, count_bits=16) as srv:
             sid = srv.open()
-            dst = torch.full((H, W), -1, dtype=torch.int32, pin_memory=True)
+            dst = _vbuf(16, (H, W), -1)
             vp = (0, 0, W, H)
             srv.wait(srv.submit(sid, CMP_OP_ADD, [0] * 65535, vp, dst))
             held = {0: 65535}
-            assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64),
+            assert np.array_equal(_counts(dst),
                                   _expect_view(stack, held, dict(vx0=0, vy0=0, vw=W, vh=H)))
             with pytest.raises(CompositeError) as ei:
                 srv.submit(sid, CMP_OP_ADD, [1], vp, dst)
@@ -385,14 +397,15 @@ def test_uint16_sessions_at_their_limit():
             srv.wait(srv.submit(sid, CMP_OP_REMOVE, [0], vp, dst))
             srv.wait(srv.submit(sid, CMP_OP_ADD, [1], vp, dst))
             held = {0: 65534, 1: 1}
-            assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64),
+            assert np.array_equal(_counts(dst),
                                   _expect_view(stack, held, dict(vx0=0, vy0=0, vw=W, vh=H)))
             with pytest.raises(CompositeError) as ei:
                 srv.submit(sid, CMP_OP_ADD, [2], vp, dst)
             assert ei.value.status == CMP_ERANGE
 
 
-def test_replay_records_refusals_and_goes_on():
+@pytest.mark.parametrize("cb", [32, 16])
+def test_replay_records_refusals_and_goes_on(cb):
     """An open-loop replay into a server whose queue holds one request: some
     submits are refused (CMP_EBUSY, or CMP_ENOTMEMBER for removes of ids only
     a refused add would have held); the replay records them and goes on, and
@@ -402,11 +415,11 @@ def test_replay_records_refusals_and_goes_on():
     P, H, W = stack.shape
     say("serve replay refusals")
     buf = _pool(stack)
-    ring = [torch.zeros((16, 16), dtype=torch.int32, pin_memory=True) for _ in range(8)]
+    ring = [_vbuf(cb, (16, 16), 0) for _ in range(8)]
     sched = [dict(r, t=r["t"] * 0.01) for r in sched]          # a burst: 200 requests in ~1 ms
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=1, overlap=0, hbm_budget_bytes=4 * H * W * 4,
-                    max_view_pixels=H * W, tile_vecs=64, max_queue=1) as srv:
+                    max_view_pixels=H * W, tile_vecs=64, max_queue=1, count_bits=cb) as srv:
             sids = [srv.open() for _ in range(wl.sessions)]
             lat, status = srv.replay(sched, sids, ring, 16, with_status=True)
             ok = status == 0
@@ -416,7 +429,7 @@ def test_replay_records_refusals_and_goes_on():
             st = srv.stats()
             assert st["requests"] == int(ok.sum())
             assert st["refused_busy"] == int((status == CMP_EBUSY).sum())
-            dst = torch.full((H, W), -1, dtype=torch.int32, pin_memory=True)
+            dst = _vbuf(cb, (H, W), -1)
             for k, sid in enumerate(sids):
                 held = {}
                 for r, good in zip(sched, ok):
@@ -425,4 +438,4 @@ def test_replay_records_refusals_and_goes_on():
                             held[int(i)] = held.get(int(i), 0) + (1 if r["op"] == "add" else -1)
                 srv.wait(srv.submit(sid, CMP_OP_ADD, [], (0, 0, W, H), dst))
                 exp = _expect_view(stack, held, dict(vx0=0, vy0=0, vw=W, vh=H))
-                assert np.array_equal(dst.numpy().view(np.uint32).astype(np.int64), exp), k
+                assert np.array_equal(_counts(dst), exp), k
