@@ -7,8 +7,9 @@
 //                     working set and append it to the queue;
 //   worker            forms a step from the queue (the oldest request of each
 //                     session, at most max_batch), makes the step's sessions
-//                     resident, uploads the step's descriptors and launches
-//                     the update kernel on the compute stream; the copy
+//                     resident and launches the update kernel on the compute
+//                     stream, with the step's descriptors in its kernel
+//                     arguments (small steps) or uploaded ahead of it; the copy
 //                     stream then moves the viewports to host memory.  Unless
 //                     a full step's worth of requests already waits, the rows
 //                     holding viewports are launched first and the rest
@@ -55,34 +56,77 @@ struct SReq {
   void *stage;        // viewport staging (device), vh rows of vw counts of the composite's width
   int32_t mode, ids_off, n;  // kMode*: composite += / -= / = count of ids
   int32_t vx0, vy0, vw, vh;
+  int32_t vb0, vb1;          // the row blocks holding the viewport: [vb0, vb1)
+  int32_t it_view, it_rest;  // this request's first item among the viewport blocks / the others
   int32_t pad;
 };
-struct SItem {
-  int32_t req, row0, nrows, pad;
-};
-struct SHeader {
-  int32_t nitems, nreq;
-  int64_t reqs_off, items_off, ids_off;
-  int64_t pad[4];
-};
-static_assert(sizeof(SHeader) == 64, "arena header is 64 bytes");
+static_assert(sizeof(SReq) == 64, "request descriptor is 64 bytes");
 
-// One work item: rows [row0, row0 + nrows) of a session composite.  Each thread
-// updates 16 pixels (count +/- the nonzero members, or count set to that of
-// the whole working set when the composite is rebuilt) and copies the pixels
-// that fall in the request's viewport to staging (in the composite's width:
-// uint16 or uint32, as they are returned to the caller).  C16: the
-// session composites are uint16 (the server refuses a request that would take
-// a session past 65535 members, so no lane carries into its neighbour).
-template <bool C16>
+// A step's descriptors: in device memory (an uploaded arena), or, for a step
+// of at most kArgReqs requests and kArgIds ids, in the launch's own kernel
+// arguments, which need no upload.
+struct ArenaStep {
+  const SReq *reqs;
+  const int32_t *ids;
+  __device__ const SReq &req(int k) const { return reqs[k]; }
+  __device__ int32_t id(int i) const { return ids[i]; }
+};
+constexpr int kArgReqs = 8, kArgIds = 512;
+struct ArgStep {
+  SReq reqs[kArgReqs];
+  int32_t ids[kArgIds];
+  __device__ const SReq &req(int k) const { return reqs[k]; }
+  __device__ int32_t id(int i) const { return ids[i]; }
+};
+static_assert(sizeof(ArgStep) <= 4096, "kernel arguments stay within 4 KiB");
+
+// Work items.  A session composite is nb blocks of `rows` rows; a step's
+// items are all blocks of all its requests (phase 0, request-major), only the
+// blocks holding viewports (phase 1) or only the others (phase 2), each
+// request's in order.  The request of an item in phases 1 and 2 is found by a
+// binary search over the requests' first items (the last request whose first
+// item is at most it; a request with no items in the phase shares its first
+// item with the next one and is passed over).
+enum : int32_t { kPhaseAll = 0, kPhaseView = 1, kPhaseRest = 2 };
+
+template <class D>
+__device__ __forceinline__ void item_of(const D &d, int nreq, int nb, int phase, int it, int &k,
+                                        int &b) {
+  if (phase == kPhaseAll) {
+    k = it / nb;
+    b = it - k * nb;
+    return;
+  }
+  int lo = 0, hi = nreq - 1;  // invariant: first(lo) <= it
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int f = phase == kPhaseView ? d.req(mid).it_view : d.req(mid).it_rest;
+    if (f <= it) lo = mid;
+    else hi = mid - 1;
+  }
+  k = lo;
+  const SReq &R = d.req(k);
+  if (phase == kPhaseView) {
+    b = R.vb0 + (it - R.it_view);
+  } else {
+    const int j = it - R.it_rest;
+    b = j < R.vb0 ? j : j + (R.vb1 - R.vb0);
+  }
+}
+
+// One work item: rows [b * rows, b * rows + rows) of a session composite.
+// Each thread updates 16 pixels (count +/- the nonzero members, or count set
+// to that of the whole working set when the composite is rebuilt) and copies
+// the pixels that fall in the request's viewport to staging (in the
+// composite's width: uint16 or uint32, as they are returned to the caller).
+// C16: the session composites are uint16 (the server refuses a request that
+// would take a session past 65535 members, so no lane carries into its
+// neighbour).
+template <bool C16, class D>
 __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base, int64_t stride,
-                                               int32_t W, const char *__restrict__ arena,
-                                               uint32_t *__restrict__ queue, int32_t item0) {
-  const SHeader *hd = reinterpret_cast<const SHeader *>(arena);
-  const int nitems = hd->nitems;
-  const SReq *reqs = reinterpret_cast<const SReq *>(arena + hd->reqs_off);
-  const SItem *items = reinterpret_cast<const SItem *>(arena + hd->items_off);
-  const int32_t *ids_all = reinterpret_cast<const int32_t *>(arena + hd->ids_off);
+                                               int32_t W, int32_t H, int32_t rows, int32_t nb,
+                                               int32_t nreq, int32_t phase, int32_t nitems,
+                                               uint32_t *__restrict__ queue, const D d) {
   const int nvr = W >> 4;
   constexpr int NQ = C16 ? 2 : 4;  // 16-byte words of composite per 16 pixels
   __shared__ int s_item;
@@ -95,21 +139,22 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       it = __builtin_amdgcn_readfirstlane(s_item);
       __syncthreads();
     } else {
-      // one item per workgroup (items item0 .. item0 + gridDim.x - 1): no
-      // queue, no barrier
-      it = pass == 0 ? item0 + (int)blockIdx.x : nitems;
+      // one item per workgroup: no queue, no barrier
+      it = pass == 0 ? (int)blockIdx.x : nitems;
     }
     if (it >= nitems) break;  // the queue counter only grows: every wave exits
-    const SItem I = items[it];
-    const SReq R = reqs[I.req];
-    const int32_t *ids = ids_all + R.ids_off;
-    const int total = I.nrows * nvr;
+    int k, b;
+    item_of(d, nreq, nb, phase, it, k, b);
+    const SReq &R = d.req(k);
+    const int row0 = b * rows;
+    const int nrows = min(rows, H - row0);
+    const int total = nrows * nvr;
     for (int v = threadIdx.x; v < total; v += blockDim.x) {
       const int row = v / nvr, j = v - row * nvr;
-      const int y = I.row0 + row, x = 16 * j;
+      const int y = row0 + row, x = 16 * j;
       const uint32_t off = (uint32_t)y * (uint32_t)W + (uint32_t)x;
-      // global-space pointers (the arena's are generic): global, not flat,
-      // loads and stores
+      // global-space pointers (the descriptors' are generic): global, not
+      // flat, loads and stores
       typedef unsigned int v4u __attribute__((ext_vector_type(4)));
       __attribute__((address_space(1))) v4u *c =
           C16 ? (__attribute__((address_space(1))) v4u *)(static_cast<uint16_t *>(R.comp) + off)
@@ -125,29 +170,30 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       }
       uint32_t cnt[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) cnt[k] = 0u;
-      for (int g0 = 0; g0 < R.n; g0 += cmp::kGroup) {
-        const int g1 = min(R.n, g0 + cmp::kGroup);
+      for (int q = 0; q < 16; ++q) cnt[q] = 0u;
+      const int ids0 = R.ids_off, n = R.n;
+      for (int g0 = 0; g0 < n; g0 += cmp::kGroup) {
+        const int g1 = min(n, g0 + cmp::kGroup);
         cmp::Acc<cmp::kCount> a;
         a.zero();
         int i = g0;
         for (; i + 16 <= g1; i += 16) {
           uint4 xs[16];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
+          for (int u = 0; u < 16; ++u) xs[u] = cmp::ld16(base + (int64_t)d.id(ids0 + i + u) * stride, off);
 #pragma unroll
           for (int u = 0; u < 16; ++u) a.fold(xs[u]);
         }
         for (; i + 4 <= g1; i += 4) {
           uint4 xs[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) xs[u] = cmp::ld16(base + (int64_t)ids[i + u] * stride, off);
+          for (int u = 0; u < 4; ++u) xs[u] = cmp::ld16(base + (int64_t)d.id(ids0 + i + u) * stride, off);
 #pragma unroll
           for (int u = 0; u < 4; ++u) a.fold(xs[u]);
         }
-        for (; i < g1; ++i) a.fold(cmp::ld16(base + (int64_t)ids[i] * stride, off));
+        for (; i < g1; ++i) a.fold(cmp::ld16(base + (int64_t)d.id(ids0 + i) * stride, off));
 #pragma unroll
-        for (int k = 0; k < 16; ++k) cnt[k] += cmp::lane_px(a.c, k);
+        for (int q = 0; q < 16; ++q) cnt[q] += cmp::lane_px(a.c, q);
       }
       uint32_t nv[16];
       if constexpr (C16) {
@@ -156,20 +202,20 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
         for (int q = 0; q < 2; ++q) {
           uint32_t w[4] = {o[q].x, o[q].y, o[q].z, o[q].w};
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const uint32_t d = cnt[8 * q + 2 * k] | (cnt[8 * q + 2 * k + 1] << 16);
-            w[k] = R.mode == kModeSub ? cmp::psub(w[k], d) : cmp::padd(w[k], d);
-            nv[8 * q + 2 * k] = w[k] & 0xffffu;
-            nv[8 * q + 2 * k + 1] = w[k] >> 16;
+          for (int m = 0; m < 4; ++m) {
+            const uint32_t dd = cnt[8 * q + 2 * m] | (cnt[8 * q + 2 * m + 1] << 16);
+            w[m] = R.mode == kModeSub ? cmp::psub(w[m], dd) : cmp::padd(w[m], dd);
+            nv[8 * q + 2 * m] = w[m] & 0xffffu;
+            nv[8 * q + 2 * m + 1] = w[m] >> 16;
           }
           c[q] = v4u{w[0], w[1], w[2], w[3]};
         }
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const v4u d = {cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]};
-          if (R.mode == kModeSub) o[q] -= d;
-          else o[q] += d;
+          const v4u dd = {cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]};
+          if (R.mode == kModeSub) o[q] -= dd;
+          else o[q] += dd;
           c[q] = o[q];
           nv[4 * q] = o[q].x; nv[4 * q + 1] = o[q].y; nv[4 * q + 2] = o[q].z; nv[4 * q + 3] = o[q].w;
         }
@@ -177,12 +223,13 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       if (y >= R.vy0 && y < R.vy0 + R.vh && x + 16 > R.vx0 && x < R.vx0 + R.vw) {
         const int64_t row_base = (int64_t)(y - R.vy0) * R.vw;
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (x + k >= R.vx0 && x + k < R.vx0 + R.vw)
+        for (int q = 0; q < 16; ++q)
+          if (x + q >= R.vx0 && x + q < R.vx0 + R.vw) {
             if constexpr (C16)
-              ((__attribute__((address_space(1))) uint16_t *)R.stage)[row_base + (x + k - R.vx0)] = (uint16_t)nv[k];
+              ((__attribute__((address_space(1))) uint16_t *)R.stage)[row_base + (x + q - R.vx0)] = (uint16_t)nv[q];
             else
-              ((__attribute__((address_space(1))) uint32_t *)R.stage)[row_base + (x + k - R.vx0)] = nv[k];
+              ((__attribute__((address_space(1))) uint32_t *)R.stage)[row_base + (x + q - R.vx0)] = nv[q];
+          }
       }
     }
   }
@@ -401,7 +448,9 @@ void worker_body(cmp_server *s) {
     // residency and descriptors (slots are touched by this thread only)
     std::vector<SReq> rd(step.size());
     std::vector<std::vector<int32_t>> rebuilt(step.size());  // ids of rebuilt composites
-    std::vector<SItem> items, rest;  // work items: rows of viewports, the other rows
+    const int rows = std::max(1, s->o.tile_vecs / (s->W / 16));  // rows per work item
+    const int nb = (s->H + rows - 1) / rows;                     // work items per session
+    int64_t nview = 0;  // work items holding viewport rows
     int64_t nids = 0;
     hipError_t e = hipSuccess;
     // Residency changes hold the lock: sessions may be opened and closed
@@ -442,44 +491,22 @@ void worker_body(cmp_server *s) {
       d.vy0 = r.vy0;
       d.vw = r.vw;
       d.vh = r.vh;
+      // the row blocks holding the viewport, and this request's first item
+      // among the step's viewport blocks and among the others
+      d.vb0 = r.vy0 / rows;
+      d.vb1 = (r.vy0 + r.vh + rows - 1) / rows;
+      d.it_view = (int32_t)nview;
+      d.it_rest = (int32_t)((int64_t)k * nb - nview);
       d.pad = 0;
+      nview += d.vb1 - d.vb0;
       nids += d.n;
-      const int nvr = s->W / 16;
-      const int rows = std::max(1, s->o.tile_vecs / nvr);
-      // items holding viewport rows first: their launch ends before the
-      // rest's, and the viewport copy overlaps the rest
-      for (int r0 = 0; r0 < s->H; r0 += rows) {
-        const SItem it{(int32_t)k, r0, std::min(rows, s->H - r0), 0};
-        if (r0 < r.vy0 + r.vh && r0 + it.nrows > r.vy0) items.push_back(it);
-        else rest.push_back(it);
-      }
     }
-    const int64_t nview = (int64_t)items.size();
-    items.insert(items.end(), rest.begin(), rest.end());
     lk.unlock();
     if (e != hipSuccess) {
       fail(s, CMP_EDEVICE);
       return;
     }
-    SHeader hd{};
-    hd.nitems = (int32_t)items.size();
-    hd.nreq = (int32_t)step.size();
-    hd.reqs_off = 64;
-    hd.items_off = (hd.reqs_off + (int64_t)sizeof(SReq) * rd.size() + 63) / 64 * 64;
-    hd.ids_off = (hd.items_off + (int64_t)sizeof(SItem) * items.size() + 63) / 64 * 64;
-    const int64_t bytes = hd.ids_off + 4 * nids;
-    if (bytes > s->arena_cap) {
-      fail(s, CMP_ENOMEM);
-      return;
-    }
-    char *h = s->h_arena[half];
-    std::memcpy(h, &hd, sizeof(hd));
-    std::memcpy(h + hd.reqs_off, rd.data(), sizeof(SReq) * rd.size());
-    std::memcpy(h + hd.items_off, items.data(), sizeof(SItem) * items.size());
-    for (size_t k = 0; k < step.size(); ++k) {
-      const std::vector<int32_t> &v = rd[k].mode == kModeSet ? rebuilt[k] : step[k].ids;
-      if (!v.empty()) std::memcpy(h + hd.ids_off + 4 * (int64_t)rd[k].ids_off, v.data(), 4 * v.size());
-    }
+    const int64_t nall = (int64_t)step.size() * nb;  // work items of the step
     // blocks_per_cu 0 (automatic): steps of small requests (16 members on
     // average in the served workload) run one workgroup per item, with no
     // queue, atomic or barrier per item; steps whose requests average more
@@ -487,35 +514,71 @@ void worker_body(cmp_server *s) {
     // persistent grid of 2 workgroups per compute unit, whose lower
     // occupancy interleaves fewer member streams (both measured faster)
     const bool persistent = s->o.blocks_per_cu > 0 || nids > kServeHeavy * (int64_t)step.size() ||
-                            items.size() > kServeMaxGrid;
+                            nall > (int64_t)kServeMaxGrid;
     const int bpc = s->o.blocks_per_cu > 0 ? s->o.blocks_per_cu : 2;
-    const int grid = persistent ? s->pool->cus * bpc : (int)items.size();
-    e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
+    // descriptors: a small step's travel in the kernel arguments; a larger
+    // one's are uploaded (requests, then ids) ahead of its launches
+    const bool small = (int64_t)step.size() <= kArgReqs && nids <= kArgIds;
+    ArgStep as;
+    ArenaStep ar{};
+    auto put_ids = [&](int32_t *dst) {
+      for (size_t k = 0; k < step.size(); ++k) {
+        const std::vector<int32_t> &v = rd[k].mode == kModeSet ? rebuilt[k] : step[k].ids;
+        if (!v.empty()) std::memcpy(dst + rd[k].ids_off, v.data(), 4 * v.size());
+      }
+    };
+    if (small) {
+      std::memcpy(as.reqs, rd.data(), sizeof(SReq) * rd.size());
+      put_ids(as.ids);
+    } else {
+      const int64_t ids_off = ((int64_t)sizeof(SReq) * rd.size() + 63) / 64 * 64;
+      const int64_t bytes = ids_off + 4 * nids;
+      if (bytes > s->arena_cap) {
+        fail(s, CMP_ENOMEM);
+        return;
+      }
+      char *h = s->h_arena[half];
+      std::memcpy(h, rd.data(), sizeof(SReq) * rd.size());
+      put_ids(reinterpret_cast<int32_t *>(h + ids_off));
+      e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
+      ar.reqs = reinterpret_cast<const SReq *>(s->d_arena[half]);
+      ar.ids = reinterpret_cast<const int32_t *>(s->d_arena[half] + ids_off);
+    }
     if (e == hipSuccess && persistent) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
     if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);
-    auto launch = [&](int g, uint32_t *q, int32_t item0) {
-      if (g <= 0) return hipSuccess;
-      if (s->o.count_bits == 16)
-        k_serve<true><<<g, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q, item0);
-      else
-        k_serve<false><<<g, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->d_arena[half], q, item0);
+    const int nreq = (int)step.size();
+    auto launch = [&](int64_t items, int phase, uint32_t *q) {
+      if (items <= 0) return hipSuccess;
+      const unsigned g = q ? (unsigned)(s->pool->cus * bpc) : (unsigned)items;
+      const int ni = (int)items;
+#define CMP_SERVE(C16, D, arg)                                                                        \
+  k_serve<C16, D><<<g, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->H, rows, nb, nreq, \
+                                          phase, ni, q, arg)
+      if (s->o.count_bits == 16) {
+        if (small) CMP_SERVE(true, ArgStep, as);
+        else CMP_SERVE(true, ArenaStep, ar);
+      } else {
+        if (small) CMP_SERVE(false, ArgStep, as);
+        else CMP_SERVE(false, ArenaStep, ar);
+      }
+#undef CMP_SERVE
       return hipGetLastError();
     };
     if (persistent) {
       // one persistent grid over all items; the viewports are final at its end
-      if (e == hipSuccess) e = launch(grid, s->d_queue, 0);
+      if (e == hipSuccess) e = launch(nall, kPhaseAll, s->d_queue);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
     } else if (backlog) {
       // the next step is full already: one launch, the least device time
-      if (e == hipSuccess) e = launch(grid, nullptr, 0);
+      if (e == hipSuccess) e = launch(nall, kPhaseAll, nullptr);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
     } else {
       // the viewport rows' items, then the rest, so that the viewport copy
       // starts after the first launch and overlaps the second (lower latency
       // for a few more microseconds of device time)
-      if (e == hipSuccess) e = launch((int)nview, nullptr, 0);
+      if (e == hipSuccess) e = launch(nview, kPhaseView, nullptr);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
-      if (e == hipSuccess) e = launch((int)((int64_t)items.size() - nview), nullptr, (int32_t)nview);
+      if (e == hipSuccess) e = launch(nall - nview, kPhaseRest, nullptr);
     }
     if (e == hipSuccess) e = hipEventRecord(s->ev_k1[half], s->comp);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->copy, s->ev_view[half], 0);
@@ -642,6 +705,11 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
       o.hbm_budget_bytes < 1)
     return CMP_EINVAL;
   if (pool->W % 16) return CMP_EUNSUPPORTED;
+  {
+    // a step's work items (max_batch sessions of row blocks) are counted in int32
+    const int64_t rows = std::max<int64_t>(1, o.tile_vecs / (pool->W / 16));
+    if ((int64_t)o.max_batch * ((pool->H + rows - 1) / rows) >= (int64_t(1) << 31)) return CMP_EUNSUPPORTED;
+  }
   const int64_t comp_bytes = (int64_t)pool->W * pool->H * (o.count_bits / 8);
   // a step must fit in the slab: at least max_batch resident composites
   if (o.hbm_budget_bytes / comp_bytes < o.max_batch) return CMP_EINVAL;
@@ -671,12 +739,9 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
     if (hipMalloc((void **)&s->slab, nslots * comp_bytes) != hipSuccess) break;
     s->slot_owner.assign(nslots, -1);
     if (hipMalloc((void **)&s->d_queue, 64) != hipSuccess) break;
-    const int64_t nvr = s->W / 16;
-    const int64_t rows = std::max<int64_t>(1, o.tile_vecs / nvr);
-    const int64_t items = (int64_t)o.max_batch * ((s->H + rows - 1) / rows);
     // ids per request are capped at 65535 by submit; a rebuilt composite
     // takes at most remat_max_members more (its working set before the request)
-    s->arena_cap = 64 + 64 + (int64_t)sizeof(SReq) * o.max_batch + 64 + (int64_t)sizeof(SItem) * items +
+    s->arena_cap = (int64_t)sizeof(SReq) * o.max_batch + 64 +
                    4 * (int64_t)o.max_batch * (65535 + (int64_t)o.remat_max_members);
     for (int i = 0; i < 2 && rc == CMP_ENOMEM; ++i) {
       if (hipHostMalloc((void **)&s->h_arena[i], s->arena_cap, hipHostMallocDefault) != hipSuccess ||
