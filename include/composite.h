@@ -364,12 +364,11 @@ int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items, int32
  * pool members and asks for a viewport of the updated composite; the viewport
  * is returned in the composite's width (uint16 counts with count_bits = 16,
  * uint32 with 32).  One server thread batches continuously: every step takes
- * the oldest queued request of each session (at most max_batch), updates all
- * their composites and writes their viewports to device staging (the rows
- * holding viewports in a first launch and the other rows in a second, unless
- * a full step's worth of requests already waits), and queues the copies of
- * the viewports to host memory on a second stream after the first launch, so
- * the copies overlap the rest of the update and the next step.  Requests of one
+ * the oldest queued request of each session (at most max_batch) and updates
+ * all their composites, the kernel writing each viewport straight into the
+ * caller's page-locked memory: the rows holding viewports in a first launch,
+ * after which the step's requests are complete, and the other rows in a
+ * second (one launch when a full step's worth of requests already waits).  Requests of one
  * session are applied in submission order; sessions interleave.  Session
  * composites live in a device slab of hbm_budget_bytes; when a request needs
  * a session that is not resident and the slab is full, a session that is not
@@ -410,8 +409,8 @@ typedef struct cmp_server_opts {
                                queue) for steps whose requests average at most
                                64 members, else 2 persistent per compute unit.
                                Default 0 */
-  int32_t overlap;          /* 1: a step may launch while the previous step's
-                               viewports are still being copied out; 0: each
+  int32_t overlap;          /* 1: a step may be formed and launched while the
+                               previous step is still on the device; 0: each
                                step completes before the next starts.
                                Default 1 */
   int32_t remat_max_members; /* eviction of a resident composite when a step
@@ -461,7 +460,9 @@ int composite_session_close(cmp_server *srv, int64_t sid);
 /* Queues one request: op (cmp_op) of n pool ids, then the viewport
  * (vx0, vy0, vw, vh) of the session's count composite copied to dst (host
  * memory allocated page-locked, vh rows of vw counts with dst_pitch elements
- * between rows; a count is a uint16 with count_bits = 16, else a uint32).  The request is validated against the session's working set
+ * between rows; a count is a uint16 with count_bits = 16, else a uint32; the
+ * update kernel writes it there directly).  CMP_EINVAL if dst is not
+ * page-locked memory the device can address, or not aligned to a count.  The request is validated against the session's working set
  * as it will be after all its earlier requests: removing an id it will not
  * hold gives CMP_ENOTMEMBER, and with count_bits = 16 an add that would take
  * it past 65535 members gives CMP_ERANGE.  CMP_EBUSY when max_queue requests
@@ -497,9 +498,9 @@ typedef struct cmp_server_stats {
    * and the completion is seen. */
   double wait_ms, host_ms, flight_ms;
   /* Device time summed over steps (divide by `steps`): from the step's start
-   * until its viewport rows are final, and from then until its viewports are
-   * in host memory (the copy stream's wait and the copies). */
-  double view_ms, copy_ms;
+   * until its viewports are in host memory (the end of the launch that writes
+   * them). */
+  double view_ms;
 } cmp_server_stats;
 
 /* Counters since the server was created. */

@@ -79,7 +79,7 @@ class cmp_server_stats(C.Structure):
                 ("device_ms", C.c_double), ("drops", C.c_int64), ("rebuilds", C.c_int64),
                 ("refused_sessions", C.c_int64), ("refused_busy", C.c_int64),
                 ("queue_peak", C.c_int64), ("wait_ms", C.c_double), ("host_ms", C.c_double),
-                ("flight_ms", C.c_double), ("view_ms", C.c_double), ("copy_ms", C.c_double)]
+                ("flight_ms", C.c_double), ("view_ms", C.c_double)]
 
 
 class cmp_replay_req(C.Structure):

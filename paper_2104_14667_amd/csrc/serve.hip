@@ -9,14 +9,14 @@
 //                     session, at most max_batch), makes the step's sessions
 //                     resident and launches the update kernel on the compute
 //                     stream, with the step's descriptors in its kernel
-//                     arguments (small steps) or uploaded ahead of it; the copy
-//                     stream then moves the viewports to host memory.  Unless
-//                     a full step's worth of requests already waits, the rows
-//                     holding viewports are launched first and the rest
-//                     second, so that the viewport copy overlaps the rest of
-//                     the update;
-//   completer         waits for each step's copies in order and completes its
-//                     requests (timestamps, waiters).
+//                     arguments (small steps) or uploaded ahead of it; the
+//                     kernel writes the viewports into the callers' page-
+//                     locked memory.  Unless a full step's worth of requests
+//                     already waits, the rows holding viewports are launched
+//                     first and the rest second, so that the requests are
+//                     complete before the rest of the update is;
+//   completer         waits for each step's viewport launch in order and
+//                     completes its requests (timestamps, waiters).
 // At most two steps are in flight; their descriptors, staging and events
 // alternate between two halves.  With overlap = 0 the worker waits for each
 // step to complete before forming the next (the unbatched FIFO baseline uses
@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -33,6 +34,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -53,12 +55,13 @@ enum : int32_t { kModeAdd = 0, kModeSub = 1, kModeSet = 2 };
 
 struct SReq {
   void *comp;         // session composite (device): uint16 or uint32 counts
-  void *stage;        // viewport staging (device), vh rows of vw counts of the composite's width
+  void *view;         // the caller's page-locked viewport (device address): vh rows of vw
+                      // counts of the composite's width, vpitch counts apart
   int32_t mode, ids_off, n;  // kMode*: composite += / -= / = count of ids
   int32_t vx0, vy0, vw, vh;
   int32_t vb0, vb1;          // the row blocks holding the viewport: [vb0, vb1)
   int32_t it_view, it_rest;  // this request's first item among the viewport blocks / the others
-  int32_t pad;
+  int32_t vpitch;
 };
 static_assert(sizeof(SReq) == 64, "request descriptor is 64 bytes");
 
@@ -82,16 +85,25 @@ static_assert(sizeof(ArgStep) <= 4096, "kernel arguments stay within 4 KiB");
 
 // Work items.  A session composite is nb blocks of `rows` rows; a step's
 // items are all blocks of all its requests (phase 0, request-major), only the
-// blocks holding viewports (phase 1) or only the others (phase 2), each
-// request's in order.  The request of an item in phases 1 and 2 is found by a
+// blocks holding viewports (phase 1), only the others (phase 2), each
+// request's in order, or the nview blocks of phase 1 followed by those of
+// phase 2 (phase 3: one launch that writes the viewports first).  The request of an item in phases 1 and 2 is found by a
 // binary search over the requests' first items (the last request whose first
 // item is at most it; a request with no items in the phase shares its first
 // item with the next one and is passed over).
-enum : int32_t { kPhaseAll = 0, kPhaseView = 1, kPhaseRest = 2 };
+enum : int32_t { kPhaseAll = 0, kPhaseView = 1, kPhaseRest = 2, kPhaseViewFirst = 3 };
 
 template <class D>
-__device__ __forceinline__ void item_of(const D &d, int nreq, int nb, int phase, int it, int &k,
-                                        int &b) {
+__device__ __forceinline__ void item_of(const D &d, int nreq, int nb, int nview, int phase, int it,
+                                        int &k, int &b) {
+  if (phase == kPhaseViewFirst) {
+    if (it < nview) {
+      phase = kPhaseView;
+    } else {
+      phase = kPhaseRest;
+      it -= nview;
+    }
+  }
   if (phase == kPhaseAll) {
     k = it / nb;
     b = it - k * nb;
@@ -114,22 +126,55 @@ __device__ __forceinline__ void item_of(const D &d, int nreq, int nb, int phase,
   }
 }
 
-// One work item: rows [b * rows, b * rows + rows) of a session composite.
-// Each thread updates 16 pixels (count +/- the nonzero members, or count set
-// to that of the whole working set when the composite is rebuilt) and copies
-// the pixels that fall in the request's viewport to staging (in the
-// composite's width: uint16 or uint32, as they are returned to the caller).
-// C16: the session composites are uint16 (the server refuses a request that
-// would take a session past 65535 members, so no lane carries into its
-// neighbour).
+// Row segment [0, n) of a viewport from LDS (element l0 on) to the caller's
+// host memory: 16-byte stores from the first 16-byte boundary of the
+// destination on, single counts before it and after the last whole vector, so
+// that the writes cross PCIe as whole lines whatever the viewport's position.
+template <class T>
+__device__ __forceinline__ void put_row(T *__restrict__ drow, const T *__restrict__ lds, int l0, int n) {
+  constexpr int E = 16 / sizeof(T);  // counts per 16-byte store
+  const int mis = (int)((reinterpret_cast<uintptr_t>(drow) & 15u) / sizeof(T));
+  const int h = min(n, (E - mis) % E);  // counts before the first boundary
+  const int nvec = (n - h) / E;
+  typedef __attribute__((address_space(1))) T gT;
+  gT *g = (gT *)drow;
+  for (int i = threadIdx.x; i < h; i += blockDim.x) g[i] = lds[l0 + i];
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+    uint32_t w[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if constexpr (sizeof(T) == 2)
+        w[m] = (uint32_t)lds[l0 + h + E * i + 2 * m] | ((uint32_t)lds[l0 + h + E * i + 2 * m + 1] << 16);
+      else
+        w[m] = lds[l0 + h + E * i + m];
+    }
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    *(__attribute__((address_space(1))) v4u *)(g + h + E * i) = v4u{w[0], w[1], w[2], w[3]};
+  }
+  for (int i = h + E * nvec + (int)threadIdx.x; i < n; i += blockDim.x) g[i] = lds[l0 + i];
+}
+
+// One work item: rows [b * rows, b * rows + rows) of a session composite, in
+// chunks of 256 vectors of 16 pixels.  Each thread updates 16 pixels (count
+// +/- the nonzero members, or count set to that of the whole working set when
+// the composite is rebuilt).  A chunk holding viewport rows also stages its
+// new counts in LDS, and the workgroup writes the viewport's part of them to
+// the caller's page-locked memory (in the composite's width: uint16 or
+// uint32), visible to the host once the launch has completed.  C16: the
+// session composites are uint16 (the server refuses a request that would take
+// a session past 65535 members, so no lane carries into its neighbour).
 template <bool C16, class D>
 __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base, int64_t stride,
                                                int32_t W, int32_t H, int32_t rows, int32_t nb,
                                                int32_t nreq, int32_t phase, int32_t nitems,
-                                               uint32_t *__restrict__ queue, const D d) {
+                                               int32_t nview, uint32_t *__restrict__ queue,
+                                               const D d) {
   const int nvr = W >> 4;
   constexpr int NQ = C16 ? 2 : 4;  // 16-byte words of composite per 16 pixels
+  typedef typename std::conditional<C16, uint16_t, uint32_t>::type T;
   __shared__ int s_item;
+  __shared__ uint4 s_px[256 * NQ];  // a chunk's new counts, pixel-major
+  T *px = reinterpret_cast<T *>(s_px);
   for (int pass = 0;; ++pass) {
     int it;
     if (queue) {
@@ -144,12 +189,20 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
     }
     if (it >= nitems) break;  // the queue counter only grows: every wave exits
     int k, b;
-    item_of(d, nreq, nb, phase, it, k, b);
+    item_of(d, nreq, nb, nview, phase, it, k, b);
     const SReq &R = d.req(k);
     const int row0 = b * rows;
     const int nrows = min(rows, H - row0);
     const int total = nrows * nvr;
-    for (int v = threadIdx.x; v < total; v += blockDim.x) {
+    // chunks of blockDim vectors: every thread takes every chunk, so the
+    // barriers of a chunk holding viewport rows are reached by all
+    for (int v0 = 0; v0 < total; v0 += blockDim.x) {
+      const int cend = min(total, v0 + (int)blockDim.x);
+      // item rows r_lo .. r_hi hold this chunk; va .. vb of them are viewport rows
+      const int r_lo = v0 / nvr, r_hi = (cend - 1) / nvr;
+      const int va = max(r_lo, R.vy0 - row0), vb = min(r_hi, R.vy0 + R.vh - 1 - row0);
+      const int v = v0 + (int)threadIdx.x;
+      if (v < total) {
       const int row = v / nvr, j = v - row * nvr;
       const int y = row0 + row, x = 16 * j;
       const uint32_t off = (uint32_t)y * (uint32_t)W + (uint32_t)x;
@@ -220,16 +273,36 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
           nv[4 * q] = o[q].x; nv[4 * q + 1] = o[q].y; nv[4 * q + 2] = o[q].z; nv[4 * q + 3] = o[q].w;
         }
       }
-      if (y >= R.vy0 && y < R.vy0 + R.vh && x + 16 > R.vx0 && x < R.vx0 + R.vw) {
-        const int64_t row_base = (int64_t)(y - R.vy0) * R.vw;
+      if (va <= vb) {
+        // this chunk holds viewport rows: its new counts to LDS
+        uint32_t pk[4 * NQ];
+        if constexpr (C16) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (x + q >= R.vx0 && x + q < R.vx0 + R.vw) {
-            if constexpr (C16)
-              ((__attribute__((address_space(1))) uint16_t *)R.stage)[row_base + (x + q - R.vx0)] = (uint16_t)nv[q];
-            else
-              ((__attribute__((address_space(1))) uint32_t *)R.stage)[row_base + (x + q - R.vx0)] = nv[q];
+          for (int m = 0; m < 8; ++m) pk[m] = nv[2 * m] | (nv[2 * m + 1] << 16);
+        } else {
+#pragma unroll
+          for (int m = 0; m < 16; ++m) pk[m] = nv[m];
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          s_px[NQ * threadIdx.x + q] = make_uint4(pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]);
+      }
+      }  // v < total
+      if (va <= vb) {
+        __syncthreads();
+        for (int r = va; r <= vb; ++r) {
+          // pixels of item row r in this chunk (item-local, row-major), and
+          // their part inside the viewport
+          const int p0 = max(16 * v0, r * W), p1 = min(16 * cend, r * W + W);
+          const int xa = max(p0 - r * W, R.vx0), xb = min(p1 - r * W, R.vx0 + R.vw);
+          if (xa < xb) {
+            T *drow = static_cast<T *>(R.view) + (int64_t)(row0 + r - R.vy0) * R.vpitch + (xa - R.vx0);
+            put_row<T>(drow, px, r * W + xa - 16 * v0, xb - xa);
           }
+        }
+        // LDS is free for the next chunk; after the last one nothing waits
+        // for the host writes to drain (the launch's end does)
+        if (v0 + (int)blockDim.x < total) __syncthreads();
       }
     }
   }
@@ -247,7 +320,8 @@ struct Request {
   int32_t op;
   std::vector<int32_t> ids;
   int32_t vx0, vy0, vw, vh;
-  void *dst;  // vh rows of vw counts (uint16 or uint32: the composite's width)
+  void *dst;    // vh rows of vw counts (uint16 or uint32: the composite's width)
+  void *dview;  // dst's device address
   int64_t pitch;
   int64_t t_submit;
 };
@@ -279,6 +353,7 @@ struct Step {
   int half;
   uint64_t index;
   int64_t t_formed, t_enq;  // requests taken from the queue; last enqueue done
+  bool split;               // viewport launch, and a rest launch on the second stream
 };
 
 }  // namespace
@@ -290,7 +365,8 @@ struct cmp_server {
   int32_t W = 0, H = 0;
   int64_t comp_bytes = 0;         // one session composite: W*H*count_bits/8
   int64_t admit_limit = 0;        // sessions admitted at most (HBM budget)
-  hipStream_t comp = nullptr, copy = nullptr;
+  hipStream_t comp = nullptr;
+  hipStream_t rest = nullptr;  // a split step's launch of the rows outside its viewports
   uint8_t *slab = nullptr;
   std::vector<int64_t> slot_owner;  // session id per slot, or -1
   uint32_t *d_queue = nullptr;
@@ -298,10 +374,10 @@ struct cmp_server {
   char *h_arena[2] = {nullptr, nullptr};
   char *d_arena[2] = {nullptr, nullptr};
   int64_t arena_cap = 0;
-  uint32_t *stage[2] = {nullptr, nullptr};
-  hipEvent_t ev_k0[2] = {nullptr, nullptr}, ev_k1[2] = {nullptr, nullptr};
-  hipEvent_t ev_view[2] = {nullptr, nullptr};  // the step's viewport rows are final
-  hipEvent_t ev_copied[2] = {nullptr, nullptr};
+  hipEvent_t ev_k0[2] = {nullptr, nullptr};      // a step's start (compute stream)
+  hipEvent_t ev_rest[2] = {nullptr, nullptr};    // a split step's rest launch has ended
+  hipEvent_t ev_pre[2] = {nullptr, nullptr};     // compute stream before a viewport launch
+  hipEvent_t ev_view[2] = {nullptr, nullptr};  // the step's viewports are in host memory
 
   std::mutex mu;
   std::condition_variable cv_queue, cv_done, cv_steps;
@@ -414,7 +490,7 @@ void worker_loop(cmp_server *s) {
 }
 
 void worker_body(cmp_server *s) {
-  const int64_t view_stride = s->o.max_view_pixels;  // uint32 per staging slot
+  bool prev_split = false;  // the previous step launched rows on the rest stream
   for (;;) {
     std::vector<Request> step;
     uint64_t index;
@@ -442,7 +518,19 @@ void worker_body(cmp_server *s) {
       backlog = s->queue.size() >= (size_t)s->o.max_batch;
     }
     const int64_t t_formed = now_ns();
-    const int half = (int)(index & 1);
+    const int half = (int)(index & 1), prev = half ^ 1;
+    hipError_t e = hipSuccess;
+    // Everything this step puts on the compute stream (residency copies,
+    // launches) follows the previous step's rest launch: they may touch the
+    // same slots.  (Not needed once it has ended.)
+    if (prev_split) {
+      e = hipEventQuery(s->ev_rest[prev]);
+      if (e == hipErrorNotReady) {
+        (void)hipGetLastError();
+        e = hipStreamWaitEvent(s->comp, s->ev_rest[prev], 0);
+      }
+    }
+    const int64_t copies0 = s->st.spills + s->st.restores;
     std::unordered_set<int64_t> in_step;
     for (auto &r : step) in_step.insert(r.sid);
     // residency and descriptors (slots are touched by this thread only)
@@ -452,13 +540,13 @@ void worker_body(cmp_server *s) {
     const int nb = (s->H + rows - 1) / rows;                     // work items per session
     int64_t nview = 0;  // work items holding viewport rows
     int64_t nids = 0;
-    hipError_t e = hipSuccess;
     // Residency changes hold the lock: sessions may be opened and closed
     // concurrently, and a close releases the slot of an idle session.
     std::unique_lock<std::mutex> lk(s->mu);
     for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
       Request &r = step[k];
       Session *ss = &s->sessions[r.sid];
+      // (make_resident enqueues its spill and restore copies on the compute stream)
       bool rebuild = false;
       e = make_resident(s, *ss, r.sid, in_step, &rebuild);
       if (e != hipSuccess) break;
@@ -478,7 +566,8 @@ void worker_body(cmp_server *s) {
       ss->last_use = ++s->use_clock;
       SReq &d = rd[k];
       d.comp = s->slab + (int64_t)ss->slot * s->comp_bytes;
-      d.stage = s->stage[half] + (int64_t)k * view_stride;  // slots of max_view_pixels uint32
+      d.view = r.dview;
+      d.vpitch = (int32_t)r.pitch;
       d.mode = rebuild ? kModeSet : r.op == CMP_OP_REMOVE ? kModeSub : kModeAdd;
       if (rebuild) {
         std::vector<int32_t> &v = rebuilt[k];
@@ -497,7 +586,6 @@ void worker_body(cmp_server *s) {
       d.vb1 = (r.vy0 + r.vh + rows - 1) / rows;
       d.it_view = (int32_t)nview;
       d.it_rest = (int32_t)((int64_t)k * nb - nview);
-      d.pad = 0;
       nview += d.vb1 - d.vb0;
       nids += d.n;
     }
@@ -545,15 +633,16 @@ void worker_body(cmp_server *s) {
       ar.ids = reinterpret_cast<const int32_t *>(s->d_arena[half] + ids_off);
     }
     if (e == hipSuccess && persistent) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
+    const bool copies = s->st.spills + s->st.restores != copies0;  // residency copies this step
     if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);
     const int nreq = (int)step.size();
-    auto launch = [&](int64_t items, int phase, uint32_t *q) {
+    auto launch = [&](hipStream_t st, int64_t items, int phase, uint32_t *q) {
       if (items <= 0) return hipSuccess;
       const unsigned g = q ? (unsigned)(s->pool->cus * bpc) : (unsigned)items;
       const int ni = (int)items;
-#define CMP_SERVE(C16, D, arg)                                                                        \
-  k_serve<C16, D><<<g, 256, 0, s->comp>>>(s->pool->base, s->pool->stride, s->W, s->H, rows, nb, nreq, \
-                                          phase, ni, q, arg)
+#define CMP_SERVE(C16, D, arg)                                                                     \
+  k_serve<C16, D><<<g, 256, 0, st>>>(s->pool->base, s->pool->stride, s->W, s->H, rows, nb, nreq, \
+                                     phase, ni, (int)nview, q, arg)
       if (s->o.count_bits == 16) {
         if (small) CMP_SERVE(true, ArgStep, as);
         else CMP_SERVE(true, ArenaStep, ar);
@@ -564,31 +653,39 @@ void worker_body(cmp_server *s) {
 #undef CMP_SERVE
       return hipGetLastError();
     };
+    const bool split = !persistent && !backlog && nall > nview;
     if (persistent) {
       // one persistent grid over all items; the viewports are final at its end
-      if (e == hipSuccess) e = launch(nall, kPhaseAll, s->d_queue);
+      if (e == hipSuccess) e = launch(s->comp, nall, kPhaseAll, s->d_queue);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
-    } else if (backlog) {
-      // the next step is full already: one launch, the least device time
-      if (e == hipSuccess) e = launch(nall, kPhaseAll, nullptr);
+    } else if (!split) {
+      // the next step is full already (or every row holds a viewport): one
+      // launch, the viewport rows first
+      if (e == hipSuccess) e = launch(s->comp, nall, kPhaseViewFirst, nullptr);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
     } else {
-      // the viewport rows' items, then the rest, so that the viewport copy
-      // starts after the first launch and overlaps the second (lower latency
-      // for a few more microseconds of device time)
-      if (e == hipSuccess) e = launch(nview, kPhaseView, nullptr);
+      // The viewport rows' items on the compute stream: the step's requests
+      // are complete when that launch is, and it is mostly the PCIe writes of
+      // the viewports.  The other rows on the rest stream at the same time.
+      // The rest launch follows what the compute stream holds before the
+      // viewport launch (this step's residency copies and uploaded
+      // descriptors, the previous step's launches): unless nothing is
+      // pending there, it waits for an event recorded just before the
+      // viewport launch.
+      bool wait = copies || !small;
+      if (!wait && e == hipSuccess) {
+        const hipError_t q = hipEventQuery(s->ev_view[prev]);
+        if (q == hipErrorNotReady) (void)hipGetLastError();
+        wait = q != hipSuccess;
+      }
+      if (wait && e == hipSuccess) e = hipEventRecord(s->ev_pre[half], s->comp);
+      if (wait && e == hipSuccess) e = hipStreamWaitEvent(s->rest, s->ev_pre[half], 0);
+      if (e == hipSuccess) e = launch(s->comp, nview, kPhaseView, nullptr);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
-      if (e == hipSuccess) e = launch(nall - nview, kPhaseRest, nullptr);
+      if (e == hipSuccess) e = launch(s->rest, nall - nview, kPhaseRest, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(s->ev_rest[half], s->rest);
     }
-    if (e == hipSuccess) e = hipEventRecord(s->ev_k1[half], s->comp);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s->copy, s->ev_view[half], 0);
-    for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
-      const Request &r = step[k];
-      const size_t el = (size_t)s->o.count_bits / 8;  // bytes per returned count
-      e = hipMemcpy2DAsync(r.dst, (size_t)r.pitch * el, rd[k].stage, (size_t)r.vw * el,
-                           (size_t)r.vw * el, (size_t)r.vh, hipMemcpyDeviceToHost, s->copy);
-    }
-    if (e == hipSuccess) e = hipEventRecord(s->ev_copied[half], s->copy);
+    prev_split = split;
     if (e != hipSuccess) {
       fail(s, CMP_EDEVICE);
       return;
@@ -600,6 +697,7 @@ void worker_body(cmp_server *s) {
       st.index = index;
       st.t_formed = t_formed;
       st.t_enq = now_ns();
+      st.split = split;
       for (auto &r : step) {
         st.tickets.push_back(r.ticket);
         st.sids.push_back(r.sid);
@@ -629,36 +727,45 @@ void completer_loop(cmp_server *s) {
       }
       st = s->steps.front();
     }
-    // the step's requests are complete once their viewports are copied out;
-    // the rows outside the viewports may still be updating then (later
-    // steps' kernels follow them on the compute stream)
-    const hipError_t e = hipEventSynchronize(s->ev_copied[st.half]);
+    // The step's requests are complete once the launch that writes their
+    // viewports has ended (its writes to host memory are visible then): they
+    // complete now, while the rows outside the viewports may still be
+    // updating on the rest stream.
+    const hipError_t e = hipEventSynchronize(s->ev_view[st.half]);
     const int64_t t = now_ns();
-    float ms = 0.f, view_ms = 0.f, copy_ms = 0.f;
-    hipError_t e2 = e == hipSuccess ? hipEventSynchronize(s->ev_k1[st.half]) : e;
-    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, s->ev_k0[st.half], s->ev_k1[st.half]);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (e != hipSuccess) {
+        // waiters of this step see the failure (their tickets stay pending)
+        if (s->failed == CMP_OK) s->failed = CMP_EDEVICE;
+      } else {
+        for (size_t k = 0; k < st.tickets.size(); ++k) {
+          auto it = s->done.find(st.tickets[k]);
+          if (it != s->done.end()) {
+            it->second.t_done = t;
+            s->st.wait_ms += 1e-6 * (double)(st.t_formed - it->second.t_submit);
+            s->st.host_ms += 1e-6 * (double)(st.t_enq - st.t_formed);
+            s->st.flight_ms += 1e-6 * (double)(t - st.t_enq);
+          }
+          s->pending.erase(st.tickets[k]);
+          s->sessions[st.sids[k]].inflight -= 1;
+          s->st.requests += 1;
+        }
+      }
+    }
+    s->cv_done.notify_all();
+    // device time: from the step's start until its last launch has ended;
+    // the step's half is free again after that
+    float view_ms = 0.f, rest_ms = 0.f;
+    hipError_t e2 = e;
     if (e2 == hipSuccess) e2 = hipEventElapsedTime(&view_ms, s->ev_k0[st.half], s->ev_view[st.half]);
-    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&copy_ms, s->ev_view[st.half], s->ev_copied[st.half]);
+    if (e2 == hipSuccess && st.split) e2 = hipEventSynchronize(s->ev_rest[st.half]);
+    if (e2 == hipSuccess && st.split) e2 = hipEventElapsedTime(&rest_ms, s->ev_k0[st.half], s->ev_rest[st.half]);
     std::lock_guard<std::mutex> lk(s->mu);
     s->steps.pop_front();
-    if (e != hipSuccess || e2 != hipSuccess) {
-      if (s->failed == CMP_OK) s->failed = CMP_EDEVICE;
-    }
-    s->st.device_ms += ms;
+    if (e2 != hipSuccess && s->failed == CMP_OK) s->failed = CMP_EDEVICE;
+    s->st.device_ms += std::max(view_ms, rest_ms);
     s->st.view_ms += view_ms;
-    s->st.copy_ms += copy_ms;
-    for (size_t k = 0; k < st.tickets.size(); ++k) {
-      auto it = s->done.find(st.tickets[k]);
-      if (it != s->done.end()) {
-        it->second.t_done = t;
-        s->st.wait_ms += 1e-6 * (double)(st.t_formed - it->second.t_submit);
-        s->st.host_ms += 1e-6 * (double)(st.t_enq - st.t_formed);
-        s->st.flight_ms += 1e-6 * (double)(t - st.t_enq);
-      }
-      s->pending.erase(st.tickets[k]);
-      s->sessions[st.sids[k]].inflight -= 1;
-      s->st.requests += 1;
-    }
     s->steps_completed += 1;
     s->cv_done.notify_all();
     s->cv_steps.notify_all();
@@ -729,11 +836,12 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
   do {
     if (hipSetDevice(s->dev) != hipSuccess) break;
     if (hipStreamCreateWithFlags(&s->comp, hipStreamNonBlocking) != hipSuccess) break;
-    if (hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess) break;
+    if (hipStreamCreateWithFlags(&s->rest, hipStreamNonBlocking) != hipSuccess) break;
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i)
-      ok = hipEventCreate(&s->ev_k0[i]) == hipSuccess && hipEventCreate(&s->ev_k1[i]) == hipSuccess &&
-           hipEventCreate(&s->ev_view[i]) == hipSuccess && hipEventCreate(&s->ev_copied[i]) == hipSuccess;
+      ok = hipEventCreate(&s->ev_k0[i]) == hipSuccess && hipEventCreate(&s->ev_rest[i]) == hipSuccess &&
+           hipEventCreateWithFlags(&s->ev_pre[i], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreate(&s->ev_view[i]) == hipSuccess;
     if (!ok) break;
     rc = CMP_ENOMEM;
     if (hipMalloc((void **)&s->slab, nslots * comp_bytes) != hipSuccess) break;
@@ -745,8 +853,7 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
                    4 * (int64_t)o.max_batch * (65535 + (int64_t)o.remat_max_members);
     for (int i = 0; i < 2 && rc == CMP_ENOMEM; ++i) {
       if (hipHostMalloc((void **)&s->h_arena[i], s->arena_cap, hipHostMallocDefault) != hipSuccess ||
-          hipMalloc((void **)&s->d_arena[i], s->arena_cap) != hipSuccess ||
-          hipMalloc((void **)&s->stage[i], (int64_t)o.max_batch * o.max_view_pixels * 4) != hipSuccess) {
+          hipMalloc((void **)&s->d_arena[i], s->arena_cap) != hipSuccess) {
         rc = -100;  // marker: allocation failed
       }
     }
@@ -783,7 +890,7 @@ void composite_server_free(cmp_server *s) {
   if (s->completer.joinable()) s->completer.join();
   (void)hipSetDevice(s->dev);
   if (s->comp) (void)hipStreamSynchronize(s->comp);
-  if (s->copy) (void)hipStreamSynchronize(s->copy);
+  if (s->rest) (void)hipStreamSynchronize(s->rest);
   for (auto &kv : s->sessions)
     if (kv.second.spill) (void)hipHostFree(kv.second.spill);
   (void)hipFree(s->slab);
@@ -791,14 +898,13 @@ void composite_server_free(cmp_server *s) {
   for (int i = 0; i < 2; ++i) {
     if (s->h_arena[i]) (void)hipHostFree(s->h_arena[i]);
     (void)hipFree(s->d_arena[i]);
-    (void)hipFree(s->stage[i]);
     if (s->ev_k0[i]) (void)hipEventDestroy(s->ev_k0[i]);
-    if (s->ev_k1[i]) (void)hipEventDestroy(s->ev_k1[i]);
+    if (s->ev_rest[i]) (void)hipEventDestroy(s->ev_rest[i]);
+    if (s->ev_pre[i]) (void)hipEventDestroy(s->ev_pre[i]);
     if (s->ev_view[i]) (void)hipEventDestroy(s->ev_view[i]);
-    if (s->ev_copied[i]) (void)hipEventDestroy(s->ev_copied[i]);
   }
   if (s->comp) (void)hipStreamDestroy(s->comp);
-  if (s->copy) (void)hipStreamDestroy(s->copy);
+  if (s->rest) (void)hipStreamDestroy(s->rest);
   delete s;
 }
 
@@ -852,9 +958,26 @@ int composite_session_submit(cmp_server *s, int64_t sid, int32_t op, const int32
   if (n < 0 || n > 65535 || (n > 0 && !ids)) return CMP_EINVAL;
   if (vw < 1 || vh < 1 || vx0 < 0 || vy0 < 0 || (int64_t)vx0 + vw > s->W || (int64_t)vy0 + vh > s->H)
     return CMP_EINVAL;
-  if ((int64_t)vw * vh > s->o.max_view_pixels || !dst || dst_pitch < vw) return CMP_EINVAL;
+  if ((int64_t)vw * vh > s->o.max_view_pixels || !dst || dst_pitch < vw || dst_pitch > INT32_MAX)
+    return CMP_EINVAL;
   for (int32_t i = 0; i < n; ++i)
     if (ids[i] < 0 || ids[i] >= s->pool->count) return CMP_EINVAL;
+  // the kernel writes the viewport into dst: it must be page-locked host
+  // memory (which has a device address) aligned to a count
+  if (reinterpret_cast<uintptr_t>(dst) % (uintptr_t)(s->o.count_bits / 8)) return CMP_EINVAL;
+  // (the attributes may describe the allocation dst lies in: its device
+  // address is the allocation's plus dst's offset from the allocation's host
+  // address)
+  hipPointerAttribute_t pa{};
+  if (hipPointerGetAttributes(&pa, dst) != hipSuccess) {
+    (void)hipGetLastError();  // leave no error behind for the caller's next HIP call
+    return CMP_EINVAL;
+  }
+  if (pa.type != hipMemoryTypeHost || !pa.devicePointer || !pa.hostPointer ||
+      reinterpret_cast<uintptr_t>(pa.hostPointer) > reinterpret_cast<uintptr_t>(dst))
+    return CMP_EINVAL;
+  void *dview = static_cast<char *>(pa.devicePointer) +
+                (reinterpret_cast<uintptr_t>(dst) - reinterpret_cast<uintptr_t>(pa.hostPointer));
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->failed != CMP_OK) return s->failed;
   if (s->stop) return CMP_EINVAL;
@@ -894,6 +1017,7 @@ int composite_session_submit(cmp_server *s, int64_t sid, int32_t op, const int32
   r.vw = vw;
   r.vh = vh;
   r.dst = dst;
+  r.dview = dview;
   r.pitch = dst_pitch;
   r.t_submit = now_ns();
   ss.inflight += 1;

@@ -118,7 +118,7 @@ def test_tiled_bytes_and_repack_argument_checks():
 
 def test_server_opts_and_stats_layout():
     o = cb.composite_default_server_opts()
-    assert C.sizeof(cb.cmp_server_opts) == 56 and C.sizeof(cb.cmp_server_stats) == 136
+    assert C.sizeof(cb.cmp_server_opts) == 56 and C.sizeof(cb.cmp_server_stats) == 128
     assert (o.max_batch, o.tile_vecs, o.blocks_per_cu, o.overlap) == (64, 256, 0, 1)
     assert o.remat_max_members == 2048 and o.hbm_budget_bytes == 16 << 30
     assert (o.count_bits, o.oversubscribe_pct, o.max_queue) == (32, 0, 1024)

@@ -439,3 +439,72 @@ def test_replay_records_refusals_and_goes_on(cb):
                 srv.wait(srv.submit(sid, CMP_OP_ADD, [], (0, 0, W, H), dst))
                 exp = _expect_view(stack, held, dict(vx0=0, vy0=0, vw=W, vh=H))
                 assert np.array_equal(_counts(dst), exp), k
+
+
+@pytest.mark.parametrize("cb", [32, 16])
+def test_viewport_edges_and_destination_layout(cb):
+    """The kernel writes each viewport straight into the caller's page-locked
+    buffer, 16 bytes at a time from the destination's first 16-byte boundary:
+    viewports at every column phase, of widths around the vector width, into
+    destinations at every element offset and with wider pitches, in work
+    items of several rows and in one row split over chunks.  Each equals the
+    oracle's window, and no count outside it is touched."""
+    rng = np.random.default_rng(61 + cb)
+    for (P, H, W, tv) in [(6, 40, 96, 64), (4, 5, 4608, 256)]:
+        stack = rng.integers(0, 3, size=(P, H, W), dtype=np.uint8)
+        buf = _pool(stack)
+        say("serve viewport edges", cb, H, W, tv)
+        with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+            with Server(pool, max_batch=4, hbm_budget_bytes=4 * H * W * 4, max_view_pixels=H * W,
+                        tile_vecs=tv, count_bits=cb) as srv:
+                sid = srv.open()
+                held = {1: 2, 3: 1, 2: 1}
+                srv.wait(srv.submit(sid, CMP_OP_ADD, [1, 1, 3, 2], (0, 0, 16, 1), _vbuf(cb, (1, 16), 0)))
+                cases = []
+                for vx0 in list(range(0, 17)) + [W - 33, W - 9]:
+                    for vw in (1, 7, 8, 9, 16, 17, 33):
+                        if vx0 + vw <= W:
+                            cases.append((vx0, vw))
+                cases.append((0, W))
+                for c, (vx0, vw) in enumerate(cases):
+                    vy0 = int(rng.integers(0, H))
+                    vh = int(rng.integers(1, H - vy0 + 1))
+                    off = c % 9                                   # destination element offset
+                    pitch = vw + (0, 1, 3, 8)[c % 4]
+                    dst = _vbuf(cb, (off + vh * pitch + 8,), -1)
+                    el = 2 if cb == 16 else 4
+                    srv.wait(srv.submit(sid, CMP_OP_ADD, [], (vx0, vy0, vw, vh),
+                                        dst.data_ptr() + off * el, pitch))
+                    got = _counts(dst)
+                    sent = 65535 if cb == 16 else 2 ** 32 - 1     # -1 in the buffer's width
+                    inside = np.zeros(got.shape, bool)
+                    for y in range(vh):
+                        inside[off + y * pitch: off + y * pitch + vw] = True
+                    assert (got[~inside] == sent).all(), (vx0, vw, off, pitch)
+                    view = np.stack([got[off + y * pitch: off + y * pitch + vw] for y in range(vh)])
+                    exp = _expect_view(stack, held, dict(vx0=vx0, vy0=vy0, vw=vw, vh=vh))
+                    assert np.array_equal(view, exp), (vx0, vy0, vw, vh, off, pitch)
+
+
+def test_submit_refuses_destinations_the_kernel_cannot_write():
+    """dst must be page-locked memory the device can address and aligned to a
+    count: pageable memory and a misaligned address are refused with
+    CMP_EINVAL, nothing changes, and the session serves on."""
+    wl, stack, sched = _small(seed=71, n=10)
+    P, H, W = stack.shape
+    buf = _pool(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=2, hbm_budget_bytes=2 * H * W * 2, max_view_pixels=256,
+                    tile_vecs=64, count_bits=16) as srv:
+            sid = srv.open()
+            pageable = np.zeros((16, 16), np.uint16)
+            pinned = _vbuf(16, (16 * 16 + 1,), -1)
+            for bad in (pageable, pinned.data_ptr() + 1):
+                with pytest.raises(CompositeError) as ei:
+                    srv.submit(sid, CMP_OP_ADD, [2], (0, 0, 16, 16), bad)
+                assert ei.value.status == CMP_EINVAL
+            assert srv.stats()["requests"] == 0
+            torch.cuda.synchronize()                           # no error left behind
+            srv.wait(srv.submit(sid, CMP_OP_ADD, [2], (0, 0, 16, 16), pinned))
+            exp = _expect_view(stack, {2: 1}, dict(vx0=0, vy0=0, vw=16, vh=16))
+            assert np.array_equal(_counts(pinned)[:256].reshape(16, 16), exp)
