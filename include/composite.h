@@ -431,7 +431,12 @@ typedef struct cmp_server_opts {
   int32_t max_queue;        /* requests waiting for a step at most, >= 1;
                                submit refuses beyond it (CMP_EBUSY).
                                Default 1024 */
-  int32_t reserved[2];      /* must be zero */
+  int32_t view_group;       /* row blocks (of tile_vecs vectors) per workgroup
+                               of the launch that writes a step's viewports,
+                               1 .. 64, or 0 (automatic: 1, the lowest
+                               latency; larger groups trade latency for less
+                               device time).  Default 0 */
+  int32_t reserved[1];      /* must be zero */
 } cmp_server_opts;
 
 void composite_default_server_opts(cmp_server_opts *opts);

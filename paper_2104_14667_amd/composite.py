@@ -70,7 +70,7 @@ class cmp_server_opts(C.Structure):
                 ("tile_vecs", C.c_int32), ("blocks_per_cu", C.c_int32), ("overlap", C.c_int32),
                 ("remat_max_members", C.c_int32), ("count_bits", C.c_int32),
                 ("oversubscribe_pct", C.c_int32), ("max_queue", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("view_group", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class cmp_server_stats(C.Structure):

@@ -60,7 +60,7 @@ struct SReq {
   int32_t mode, ids_off, n;  // kMode*: composite += / -= / = count of ids
   int32_t vx0, vy0, vw, vh;
   int32_t vb0, vb1;          // the row blocks holding the viewport: [vb0, vb1)
-  int32_t it_view, it_rest;  // this request's first item among the viewport blocks / the others
+  int32_t it_view, it_rest;  // this request's first item among the viewport items / the others
   int32_t vpitch;
 };
 static_assert(sizeof(SReq) == 64, "request descriptor is 64 bytes");
@@ -83,19 +83,26 @@ struct ArgStep {
 };
 static_assert(sizeof(ArgStep) <= 4096, "kernel arguments stay within 4 KiB");
 
-// Work items.  A session composite is nb blocks of `rows` rows; a step's
-// items are all blocks of all its requests (phase 0, request-major), only the
-// blocks holding viewports (phase 1), only the others (phase 2), each
-// request's in order, or the nview blocks of phase 1 followed by those of
-// phase 2 (phase 3: one launch that writes the viewports first).  The request of an item in phases 1 and 2 is found by a
+// Work items.  A session composite is nb blocks of `rows` rows.  A request's
+// viewport items are groups of `group` blocks from vb0 on over [vb0, vb1),
+// the blocks holding its viewport (the last group may be shorter): fewer,
+// larger workgroups for the launch that writes the viewports over PCIe, so
+// that the other rows' launch finds room beside it.  Its other items are the
+// single blocks outside [vb0, vb1).  A step's items are all blocks of all its
+// requests (phase 0, request-major), only the viewport items (phase 1), only
+// the others (phase 2), each request's in order, or the nview items of phase
+// 1 followed by those of phase 2 (phase 3: one launch that writes the
+// viewports first).  The request of an item in phases 1 and 2 is found by a
 // binary search over the requests' first items (the last request whose first
 // item is at most it; a request with no items in the phase shares its first
-// item with the next one and is passed over).
+// item with the next one and is passed over).  Out: request k, first block b
+// and blocks nblk.
 enum : int32_t { kPhaseAll = 0, kPhaseView = 1, kPhaseRest = 2, kPhaseViewFirst = 3 };
 
 template <class D>
-__device__ __forceinline__ void item_of(const D &d, int nreq, int nb, int nview, int phase, int it,
-                                        int &k, int &b) {
+__device__ __forceinline__ void item_of(const D &d, int nreq, int nb, int group, int nview, int phase,
+                                        int it, int &k, int &b, int &nblk) {
+  nblk = 1;
   if (phase == kPhaseViewFirst) {
     if (it < nview) {
       phase = kPhaseView;
@@ -119,7 +126,8 @@ __device__ __forceinline__ void item_of(const D &d, int nreq, int nb, int nview,
   k = lo;
   const SReq &R = d.req(k);
   if (phase == kPhaseView) {
-    b = R.vb0 + (it - R.it_view);
+    b = R.vb0 + group * (it - R.it_view);
+    nblk = min(group, R.vb1 - b);
   } else {
     const int j = it - R.it_rest;
     b = j < R.vb0 ? j : j + (R.vb1 - R.vb0);
@@ -166,8 +174,8 @@ __device__ __forceinline__ void put_row(T *__restrict__ drow, const T *__restric
 template <bool C16, class D>
 __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base, int64_t stride,
                                                int32_t W, int32_t H, int32_t rows, int32_t nb,
-                                               int32_t nreq, int32_t phase, int32_t nitems,
-                                               int32_t nview, uint32_t *__restrict__ queue,
+                                               int32_t nreq, int32_t group, int32_t phase,
+                                               int32_t nitems, int32_t nview, uint32_t *__restrict__ queue,
                                                const D d) {
   const int nvr = W >> 4;
   constexpr int NQ = C16 ? 2 : 4;  // 16-byte words of composite per 16 pixels
@@ -188,11 +196,11 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
       it = pass == 0 ? (int)blockIdx.x : nitems;
     }
     if (it >= nitems) break;  // the queue counter only grows: every wave exits
-    int k, b;
-    item_of(d, nreq, nb, nview, phase, it, k, b);
+    int k, b, nblk;
+    item_of(d, nreq, nb, group, nview, phase, it, k, b, nblk);
     const SReq &R = d.req(k);
     const int row0 = b * rows;
-    const int nrows = min(rows, H - row0);
+    const int nrows = min(nblk * rows, H - row0);
     const int total = nrows * nvr;
     // chunks of blockDim vectors: every thread takes every chunk, so the
     // barriers of a chunk holding viewport rows are reached by all
@@ -312,6 +320,13 @@ __global__ __launch_bounds__(256) void k_serve(const uint8_t *__restrict__ base,
 // and the most work items it launches one workgroup each (a larger step runs
 // persistent too, well inside the launch's grid limits).
 constexpr int64_t kServeHeavy = 64;
+// Row blocks per work item of the launch that writes the viewports, unless
+// the options set it.  On the served workload (one 1024x1024 viewport of a
+// 4096x4096 session per step) 1, 2, 4, 8 and 16 gave p50 0.090, 0.095,
+// 0.098, 0.12 and 0.17 ms for 0.088, 0.086, 0.079, 0.084 and 0.12 ms of
+// device time per request: larger groups leave the other rows' launch more
+// room and lengthen the viewport launch.  Latency first.
+constexpr int kServeViewGroup = 1;
 constexpr size_t kServeMaxGrid = size_t(1) << 22;
 
 struct Request {
@@ -537,8 +552,9 @@ void worker_body(cmp_server *s) {
     std::vector<SReq> rd(step.size());
     std::vector<std::vector<int32_t>> rebuilt(step.size());  // ids of rebuilt composites
     const int rows = std::max(1, s->o.tile_vecs / (s->W / 16));  // rows per work item
-    const int nb = (s->H + rows - 1) / rows;                     // work items per session
-    int64_t nview = 0;  // work items holding viewport rows
+    const int nb = (s->H + rows - 1) / rows;                     // row blocks per session
+    const int group = s->o.view_group > 0 ? s->o.view_group : kServeViewGroup;
+    int64_t nview = 0, nrest = 0;  // viewport items (groups of blocks), other items (blocks)
     int64_t nids = 0;
     // Residency changes hold the lock: sessions may be opened and closed
     // concurrently, and a close releases the slot of an idle session.
@@ -585,8 +601,9 @@ void worker_body(cmp_server *s) {
       d.vb0 = r.vy0 / rows;
       d.vb1 = (r.vy0 + r.vh + rows - 1) / rows;
       d.it_view = (int32_t)nview;
-      d.it_rest = (int32_t)((int64_t)k * nb - nview);
-      nview += d.vb1 - d.vb0;
+      d.it_rest = (int32_t)nrest;
+      nview += (d.vb1 - d.vb0 + group - 1) / group;
+      nrest += nb - (d.vb1 - d.vb0);
       nids += d.n;
     }
     lk.unlock();
@@ -642,7 +659,7 @@ void worker_body(cmp_server *s) {
       const int ni = (int)items;
 #define CMP_SERVE(C16, D, arg)                                                                     \
   k_serve<C16, D><<<g, 256, 0, st>>>(s->pool->base, s->pool->stride, s->W, s->H, rows, nb, nreq, \
-                                     phase, ni, (int)nview, q, arg)
+                                     group, phase, ni, (int)nview, q, arg)
       if (s->o.count_bits == 16) {
         if (small) CMP_SERVE(true, ArgStep, as);
         else CMP_SERVE(true, ArenaStep, ar);
@@ -653,7 +670,7 @@ void worker_body(cmp_server *s) {
 #undef CMP_SERVE
       return hipGetLastError();
     };
-    const bool split = !persistent && !backlog && nall > nview;
+    const bool split = !persistent && !backlog && nrest > 0;
     if (persistent) {
       // one persistent grid over all items; the viewports are final at its end
       if (e == hipSuccess) e = launch(s->comp, nall, kPhaseAll, s->d_queue);
@@ -661,7 +678,7 @@ void worker_body(cmp_server *s) {
     } else if (!split) {
       // the next step is full already (or every row holds a viewport): one
       // launch, the viewport rows first
-      if (e == hipSuccess) e = launch(s->comp, nall, kPhaseViewFirst, nullptr);
+      if (e == hipSuccess) e = launch(s->comp, nview + nrest, kPhaseViewFirst, nullptr);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
     } else {
       // The viewport rows' items on the compute stream: the step's requests
@@ -682,7 +699,7 @@ void worker_body(cmp_server *s) {
       if (wait && e == hipSuccess) e = hipStreamWaitEvent(s->rest, s->ev_pre[half], 0);
       if (e == hipSuccess) e = launch(s->comp, nview, kPhaseView, nullptr);
       if (e == hipSuccess) e = hipEventRecord(s->ev_view[half], s->comp);
-      if (e == hipSuccess) e = launch(s->rest, nall - nview, kPhaseRest, nullptr);
+      if (e == hipSuccess) e = launch(s->rest, nrest, kPhaseRest, nullptr);
       if (e == hipSuccess) e = hipEventRecord(s->ev_rest[half], s->rest);
     }
     prev_split = split;
@@ -794,6 +811,7 @@ void composite_default_server_opts(cmp_server_opts *o) {
   o->count_bits = 32;
   o->oversubscribe_pct = 0;
   o->max_queue = 1024;
+  o->view_group = 0;
 }
 
 int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_opts *opts) {
@@ -809,6 +827,7 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
       o.tile_vecs < 64 || o.tile_vecs > 65536 || o.blocks_per_cu < 0 || o.blocks_per_cu > 16 ||
       (o.overlap != 0 && o.overlap != 1) || o.remat_max_members < 0 || o.remat_max_members > 65535 ||
       (o.count_bits != 16 && o.count_bits != 32) || o.oversubscribe_pct < 0 || o.max_queue < 1 ||
+      o.view_group < 0 || o.view_group > 64 ||
       o.hbm_budget_bytes < 1)
     return CMP_EINVAL;
   if (pool->W % 16) return CMP_EUNSUPPORTED;

@@ -63,7 +63,9 @@
   form.  With pad 0 the same pixel of every raster lies exactly 4 MiB apart.
 * ``serve-layout``: the served workload's continuous-batching run for a
   few seconds of its schedule with the pool's depth maps at a stride of
-  4096^2 + pad bytes, for several pads: device time per request, p50, p99.
+  4096^2 + pad bytes, for several pads, and with several sizes of the
+  viewport launch's workgroups (view_group): device time per request, the
+  viewport launch's time, p50, p99.
 * ``tile-reads``: the batched matrix kernel's read pattern with trivial
   arithmetic over the batched pool's shape, rasters stored one after another
   or row-interleaved (row y of every raster side by side).
@@ -565,12 +567,15 @@ def pool_layout(pads=(0, 4096, 65536, 1 << 20, (1 << 20) + 4096, 4 << 20), reps=
     return {"pool": wl.pool, "W": wl.W, "H": wl.H, "requests": len(reqs), "reps": reps, "rows": rows}
 
 
-def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: int = 8) -> dict:
+def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: int = 8,
+                 view_groups=(0,)) -> dict:
     """The served workload's continuous-batching run (uint16 composites, an
     8 GiB budget, Poisson 2000 req/s) for `seconds` of its schedule, with the
-    pool's depth maps at a stride of 4096^2 + pad bytes: device time per
-    request, p50 and p99.  `check` sessions' final viewports are compared with
-    the closed form of their final members."""
+    pool's depth maps at a stride of 4096^2 + pad bytes and the server's
+    view_group (row blocks per workgroup of the viewport launch; 0: the
+    library's choice) taking each of `view_groups`: device time per request,
+    the viewport launch's time per step, p50 and p99.  `check` sessions' final
+    viewports are compared with the closed form of their final members."""
     import torch
 
     from . import synth
@@ -591,37 +596,42 @@ def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: in
         for i, L in enumerate(lv):
             synth.member_torch(et, int(L), "depth", out=buf[i * stride:i * stride + plane].view(wl.H, wl.W))
         torch.cuda.synchronize()
-        with Pool(buf, wl.pool, wl.W, wl.H, stride, buf.numel()) as pool:
-            with Server(pool, count_bits=16, max_batch=64, overlap=1, hbm_budget_bytes=budget) as srv:
-                sids = [srv.open() for _ in range(wl.sessions)]
-                st0 = srv.stats()
-                lat, status = srv.replay(sched, sids, ring, wl.view, with_status=True)
-                st = srv.stats()
-                # final members of a few sessions against their closed form
-                cur = [dict() for _ in range(wl.sessions)]
-                for r, g in zip(sched, status):
-                    if g != 0:
-                        continue
-                    c = cur[r["sid"]]
-                    for i in (int(x) for x in r["ids"]):
-                        c[i] = c.get(i, 0) + (1 if r["op"] == "add" else -1)
-                        if c[i] == 0:
-                            del c[i]
-                exact = True
-                for k in range(0, wl.sessions, wl.sessions // check):
-                    srv.wait(srv.submit(sids[k], CMP_OP_ADD, [], (0, 0, wl.view, wl.view), dst))
-                    c = cur[k]
-                    lvs = np.sort(np.repeat(lv[list(c)], list(c.values()))) if c else np.zeros(0, lv.dtype)
-                    exp = len(lvs) - np.searchsorted(lvs, e[:wl.view, :wl.view], side="right")
-                    exact &= bool(np.array_equal(dst.numpy().view(np.uint16), exp))
-        ok = status == 0
-        lat_ms = lat[ok] / 1e6
-        nreq = st["requests"] - st0["requests"]
-        rows.append({"pad_bytes": pad, "stride_bytes": stride, "requests": int(ok.sum()),
-                     "device_ms_per_request": round((st["device_ms"] - st0["device_ms"]) / max(1, nreq), 4),
-                     "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-                     "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "exact": exact})
-        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        for vg in view_groups:
+            with Pool(buf, wl.pool, wl.W, wl.H, stride, buf.numel()) as pool:
+                with Server(pool, count_bits=16, max_batch=64, overlap=1, hbm_budget_bytes=budget,
+                            view_group=vg) as srv:
+                    sids = [srv.open() for _ in range(wl.sessions)]
+                    st0 = srv.stats()
+                    lat, status = srv.replay(sched, sids, ring, wl.view, with_status=True)
+                    st = srv.stats()
+                    # final members of a few sessions against their closed form
+                    cur = [dict() for _ in range(wl.sessions)]
+                    for r, g in zip(sched, status):
+                        if g != 0:
+                            continue
+                        c = cur[r["sid"]]
+                        for i in (int(x) for x in r["ids"]):
+                            c[i] = c.get(i, 0) + (1 if r["op"] == "add" else -1)
+                            if c[i] == 0:
+                                del c[i]
+                    exact = True
+                    for k in range(0, wl.sessions, wl.sessions // check):
+                        srv.wait(srv.submit(sids[k], CMP_OP_ADD, [], (0, 0, wl.view, wl.view), dst))
+                        c = cur[k]
+                        lvs = np.sort(np.repeat(lv[list(c)], list(c.values()))) if c else np.zeros(0, lv.dtype)
+                        exp = len(lvs) - np.searchsorted(lvs, e[:wl.view, :wl.view], side="right")
+                        exact &= bool(np.array_equal(dst.numpy().view(np.uint16), exp))
+            ok = status == 0
+            lat_ms = lat[ok] / 1e6
+            nreq = st["requests"] - st0["requests"]
+            nstep = st["steps"] - st0["steps"]
+            rows.append({"pad_bytes": pad, "stride_bytes": stride, "view_group": vg,
+                         "requests": int(ok.sum()),
+                         "device_ms_per_request": round((st["device_ms"] - st0["device_ms"]) / max(1, nreq), 4),
+                         "view_launch_ms_per_step": round((st["view_ms"] - st0["view_ms"]) / max(1, nstep), 4),
+                         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "exact": exact})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     return {"seconds": seconds, "sessions": wl.sessions, "rows": rows}
 
 
@@ -770,6 +780,8 @@ def main(argv=None):
     sl = sub.add_parser("serve-layout")
     sl.add_argument("--pads", default=None, help="comma-separated pads in bytes")
     sl.add_argument("--seconds", type=float, default=3.0)
+    sl.add_argument("--view-groups", default=None,
+                    help="comma-separated view_group values (0: the library's choice)")
     sl.add_argument("--out", default=None)
     tr = sub.add_parser("tile-reads")
     tr.add_argument("--out", default=None)
@@ -812,6 +824,8 @@ def main(argv=None):
         kw = {"seconds": args.seconds}
         if args.pads:
             kw["pads"] = tuple(int(x) for x in args.pads.split(","))
+        if args.view_groups:
+            kw["view_groups"] = tuple(int(x) for x in args.view_groups.split(","))
         res = serve_layout(**kw)
         print(json.dumps(res))
     elif args.cmd == "tile-reads":

@@ -135,14 +135,14 @@ def test_server_argument_checks_before_any_device_call():
     for field, bad in (("count_bits", 24), ("count_bits", 0), ("oversubscribe_pct", -1),
                        ("max_queue", 0), ("max_batch", 0), ("max_batch", 4097),
                        ("hbm_budget_bytes", 0), ("overlap", 2), ("remat_max_members", 65536),
-                       ("tile_vecs", 63), ("blocks_per_cu", 17)):
+                       ("tile_vecs", 63), ("blocks_per_cu", 17), ("view_group", -1), ("view_group", 65)):
         o = cb.composite_default_server_opts()
         setattr(o, field, bad)
         assert cb.lib.composite_server_create(C.byref(h), fake_pool, C.byref(o)) == cb.CMP_EINVAL, field
         assert h.value is None
         h = C.c_void_p(1234)
     o = cb.composite_default_server_opts()
-    o.reserved[1] = 1
+    o.reserved[0] = 1
     assert cb.lib.composite_server_create(C.byref(h), fake_pool, C.byref(o)) == cb.CMP_EINVAL
     sid = C.c_int64()
     t = C.c_uint64()
