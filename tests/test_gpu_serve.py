@@ -73,21 +73,26 @@ def _check_alone(wl, stack, sched, outs):
 # bpc: persistent workgroups per CU, or 0 for one workgroup per work item;
 # cb: bits of the session composites.  Budgets below the 5 sessions admit
 # them by oversubscription (they live by eviction)
-@pytest.mark.parametrize("max_batch,overlap,budget_slots,remat,bpc,cb", [
-    (1, 0, 8, 0, 2, 32), (4, 1, 4, 0, 2, 32), (64, 1, 64, 512, 2, 32), (3, 0, 3, 65535, 2, 32),
-    (8, 1, 10, 4, 2, 32), (4, 1, 4, 512, 2, 32), (1, 0, 3, 4, 2, 32), (64, 1, 64, 512, 0, 32),
-    (4, 1, 4, 65535, 0, 32), (4, 1, 4, 0, 2, 16), (3, 0, 3, 65535, 2, 16), (64, 1, 64, 512, 0, 16),
-    (8, 1, 10, 4, 2, 16)])
-def test_mix_equals_alone(max_batch, overlap, budget_slots, remat, bpc, cb):
-    wl, stack, sched = _small(seed=max_batch + 10 * overlap + remat % 7 + cb)
+# bpc 0 steps launch the viewport rows and, beside them on a second stream,
+# the other rows (ordered after the step's spill and restore copies); vg: row
+# blocks per workgroup of the viewport launch (0: the library's choice)
+@pytest.mark.parametrize("max_batch,overlap,budget_slots,remat,bpc,cb,vg", [
+    (1, 0, 8, 0, 2, 32, 0), (4, 1, 4, 0, 2, 32, 0), (64, 1, 64, 512, 2, 32, 0),
+    (3, 0, 3, 65535, 2, 32, 0), (8, 1, 10, 4, 2, 32, 0), (4, 1, 4, 512, 2, 32, 0),
+    (1, 0, 3, 4, 2, 32, 0), (64, 1, 64, 512, 0, 32, 0), (4, 1, 4, 65535, 0, 32, 0),
+    (4, 1, 4, 0, 2, 16, 0), (3, 0, 3, 65535, 2, 16, 0), (64, 1, 64, 512, 0, 16, 0),
+    (8, 1, 10, 4, 2, 16, 0), (4, 1, 4, 0, 0, 32, 0), (4, 1, 4, 0, 0, 16, 3),
+    (8, 1, 10, 4, 0, 16, 2), (1, 0, 3, 0, 0, 32, 0), (2, 1, 3, 4, 0, 32, 5)])
+def test_mix_equals_alone(max_batch, overlap, budget_slots, remat, bpc, cb, vg):
+    wl, stack, sched = _small(seed=max_batch + 10 * overlap + remat % 7 + cb + vg)
     P, H, W = stack.shape
-    say("serve mix", max_batch, overlap, budget_slots, remat, bpc, cb)
+    say("serve mix", max_batch, overlap, budget_slots, remat, bpc, cb, vg)
     buf = _pool(stack)
     with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
         with Server(pool, max_batch=max_batch, overlap=overlap,
                     hbm_budget_bytes=budget_slots * H * W * cb // 8, max_view_pixels=16 * 16,
                     tile_vecs=64, blocks_per_cu=bpc, remat_max_members=remat, count_bits=cb,
-                    oversubscribe_pct=100) as srv:
+                    oversubscribe_pct=100, view_group=vg) as srv:
             sids, outs = _run_mix(srv, wl, sched)
             st = srv.stats()
             assert st["requests"] == len(sched)
@@ -441,22 +446,23 @@ def test_replay_records_refusals_and_goes_on(cb):
                 assert np.array_equal(_counts(dst), exp), k
 
 
-@pytest.mark.parametrize("cb", [32, 16])
-def test_viewport_edges_and_destination_layout(cb):
+@pytest.mark.parametrize("cb,vg", [(32, 0), (16, 0), (16, 3)])
+def test_viewport_edges_and_destination_layout(cb, vg):
     """The kernel writes each viewport straight into the caller's page-locked
     buffer, 16 bytes at a time from the destination's first 16-byte boundary:
     viewports at every column phase, of widths around the vector width, into
     destinations at every element offset and with wider pitches, in work
-    items of several rows and in one row split over chunks.  Each equals the
-    oracle's window, and no count outside it is touched."""
+    items of several rows and in one row split over chunks, and (vg 3) in
+    viewport work items of three row blocks.  Each equals the oracle's
+    window, and no count outside it is touched."""
     rng = np.random.default_rng(61 + cb)
     for (P, H, W, tv) in [(6, 40, 96, 64), (4, 5, 4608, 256)]:
         stack = rng.integers(0, 3, size=(P, H, W), dtype=np.uint8)
         buf = _pool(stack)
-        say("serve viewport edges", cb, H, W, tv)
+        say("serve viewport edges", cb, vg, H, W, tv)
         with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
             with Server(pool, max_batch=4, hbm_budget_bytes=4 * H * W * 4, max_view_pixels=H * W,
-                        tile_vecs=tv, count_bits=cb) as srv:
+                        tile_vecs=tv, count_bits=cb, view_group=vg) as srv:
                 sid = srv.open()
                 held = {1: 2, 3: 1, 2: 1}
                 srv.wait(srv.submit(sid, CMP_OP_ADD, [1, 1, 3, 2], (0, 0, 16, 1), _vbuf(cb, (1, 16), 0)))
@@ -508,3 +514,41 @@ def test_submit_refuses_destinations_the_kernel_cannot_write():
             srv.wait(srv.submit(sid, CMP_OP_ADD, [2], (0, 0, 16, 16), pinned))
             exp = _expect_view(stack, {2: 1}, dict(vx0=0, vy0=0, vw=16, vh=16))
             assert np.array_equal(_counts(pinned)[:256].reshape(16, 16), exp)
+
+
+@pytest.mark.parametrize("cb,remat,vg", [(32, 0, 0), (16, 0, 2), (32, 4, 0), (16, 65535, 0)])
+def test_split_steps_with_evictions(cb, remat, vg):
+    """At most two requests outstanding against a step size of four: no step
+    finds a backlog, so every step launches its viewport rows and, beside
+    them on the second stream, the other rows, while sessions are evicted
+    (copied out and back with remat 0, dropped and rebuilt with 65535, both
+    with 4).  Each viewport equals the oracle's replay of its session alone."""
+    wl, stack, sched = _small(seed=81 + cb + remat % 11 + vg, sessions=5, n=120)
+    P, H, W = stack.shape
+    say("serve split evictions", cb, remat, vg)
+    buf = _pool(stack)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=4, overlap=1, hbm_budget_bytes=4 * H * W * cb // 8,
+                    max_view_pixels=16 * 16, tile_vecs=64, remat_max_members=remat, count_bits=cb,
+                    oversubscribe_pct=100, view_group=vg) as srv:
+            sids = [srv.open() for _ in range(wl.sessions)]
+            outs, pending = [], []
+            for r in sched:
+                dst = _vbuf(cb, (r["vh"], r["vw"]), -1)
+                op = CMP_OP_ADD if r["op"] == "add" else CMP_OP_REMOVE
+                pending.append(srv.submit(sids[r["sid"]], op, r["ids"],
+                                          (r["vx0"], r["vy0"], r["vw"], r["vh"]), dst))
+                outs.append(dst)
+                if len(pending) == 2:
+                    srv.wait(pending.pop(0))
+            for t in pending:
+                srv.wait(t)
+            st = srv.stats()
+            assert st["requests"] == len(sched) and st["max_step"] <= 2
+            if remat == 0:
+                assert st["spills"] > 0 and st["restores"] > 0
+            elif remat >= 65535:
+                assert st["drops"] > 0 and st["spills"] == 0
+            else:
+                assert st["drops"] + st["spills"] > 0
+    _check_alone(wl, stack, sched, outs)
