@@ -490,7 +490,9 @@ typedef struct cmp_server_stats {
   int64_t requests, steps, max_step;
   int64_t spills, restores;  /* evictions copied to host memory, and copies back */
   int64_t resident_slots;
-  double device_ms;          /* summed device time of the update launches */
+  double device_ms;          /* device time of the steps: each step's span from
+                                its start to the end of its last launch,
+                                overlaps between steps counted once */
   int64_t drops, rebuilds;   /* evictions without a copy, and composites
                                 rebuilt from their members */
   int64_t refused_sessions;  /* session opens refused by admission */

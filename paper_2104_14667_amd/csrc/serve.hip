@@ -389,6 +389,8 @@ struct cmp_server {
   char *h_arena[2] = {nullptr, nullptr};
   char *d_arena[2] = {nullptr, nullptr};
   int64_t arena_cap = 0;
+  hipEvent_t ev_ref = nullptr;                    // recorded at creation: the time origin
+  double busy_until = 0.0;                        // ms after ev_ref: end of the last step's span
   hipEvent_t ev_k0[2] = {nullptr, nullptr};      // a step's start (compute stream)
   hipEvent_t ev_rest[2] = {nullptr, nullptr};    // a split step's rest launch has ended
   hipEvent_t ev_pre[2] = {nullptr, nullptr};     // compute stream before a viewport launch
@@ -427,8 +429,17 @@ void fail(cmp_server *s, int rc) {
 // Makes `sid` resident.  Called by the worker with the server lock held.
 // *rebuild is set when the slot holds no valid composite and the step's
 // kernel must write the composite of the session's whole working set.
+// A residency copy, enqueued on the compute stream once the step knows what
+// it must wait for.
+struct SlotCopy {
+  void *dst;
+  const void *src;
+  hipMemcpyKind kind;
+};
+
 hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
-                         const std::unordered_set<int64_t> &in_step, bool *rebuild) {
+                         const std::unordered_set<int64_t> &in_step, bool *rebuild,
+                         std::vector<SlotCopy> &copies) {
   *rebuild = false;
   if (ss.slot >= 0) return hipSuccess;
   int slot = -1;
@@ -466,10 +477,8 @@ hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
         hipError_t e = hipHostMalloc((void **)&vs.spill, s->comp_bytes, hipHostMallocDefault);
         if (e != hipSuccess) return e;
       }
-      // ordered after every kernel that wrote the slot (same stream)
-      hipError_t e = hipMemcpyAsync(vs.spill, s->slab + (int64_t)slot * s->comp_bytes,
-                                    s->comp_bytes, hipMemcpyDeviceToHost, s->comp);
-      if (e != hipSuccess) return e;
+      // ordered after every kernel that wrote the slot (compute stream)
+      copies.push_back({vs.spill, s->slab + (int64_t)slot * s->comp_bytes, hipMemcpyDeviceToHost});
       vs.dropped = false;
       s->st.spills += 1;
     }
@@ -478,8 +487,7 @@ hipError_t make_resident(cmp_server *s, Session &ss, int64_t sid,
   }
   uint8_t *dst = s->slab + (int64_t)slot * s->comp_bytes;
   if (ss.has_data && !ss.dropped) {
-    hipError_t e = hipMemcpyAsync(dst, ss.spill, s->comp_bytes, hipMemcpyHostToDevice, s->comp);
-    if (e != hipSuccess) return e;
+    copies.push_back({dst, ss.spill, hipMemcpyHostToDevice});
     s->st.restores += 1;
   } else {
     // new (all zero) or dropped: the step writes the whole composite
@@ -506,6 +514,7 @@ void worker_loop(cmp_server *s) {
 
 void worker_body(cmp_server *s) {
   bool prev_split = false;  // the previous step launched rows on the rest stream
+  std::vector<void *> prev_comps;  // the composites that step updates (sorted)
   for (;;) {
     std::vector<Request> step;
     uint64_t index;
@@ -535,17 +544,7 @@ void worker_body(cmp_server *s) {
     const int64_t t_formed = now_ns();
     const int half = (int)(index & 1), prev = half ^ 1;
     hipError_t e = hipSuccess;
-    // Everything this step puts on the compute stream (residency copies,
-    // launches) follows the previous step's rest launch: they may touch the
-    // same slots.  (Not needed once it has ended.)
-    if (prev_split) {
-      e = hipEventQuery(s->ev_rest[prev]);
-      if (e == hipErrorNotReady) {
-        (void)hipGetLastError();
-        e = hipStreamWaitEvent(s->comp, s->ev_rest[prev], 0);
-      }
-    }
-    const int64_t copies0 = s->st.spills + s->st.restores;
+    std::vector<SlotCopy> scopies;  // residency copies of this step, in order
     std::unordered_set<int64_t> in_step;
     for (auto &r : step) in_step.insert(r.sid);
     // residency and descriptors (slots are touched by this thread only)
@@ -564,7 +563,7 @@ void worker_body(cmp_server *s) {
       Session *ss = &s->sessions[r.sid];
       // (make_resident enqueues its spill and restore copies on the compute stream)
       bool rebuild = false;
-      e = make_resident(s, *ss, r.sid, in_step, &rebuild);
+      e = make_resident(s, *ss, r.sid, in_step, &rebuild, scopies);
       if (e != hipSuccess) break;
       // the working set the composite holds once this request has run
       for (int32_t id : r.ids) {
@@ -611,6 +610,28 @@ void worker_body(cmp_server *s) {
       fail(s, CMP_EDEVICE);
       return;
     }
+    // What this step puts on the compute stream (residency copies, launches)
+    // follows the previous step's rest launch if it touches one of that
+    // step's composite slots: the same session, or a slot given to another
+    // session since (evicted or closed).  Every slot this step touches holds
+    // one of its own composites (an evicted session's slot is handed to one).
+    // Steps before the previous one have completed.
+    std::vector<void *> comps(rd.size());
+    for (size_t k = 0; k < rd.size(); ++k) comps[k] = rd[k].comp;
+    std::sort(comps.begin(), comps.end());
+    if (prev_split) {
+      bool touch = false;
+      for (void *c : comps) touch = touch || std::binary_search(prev_comps.begin(), prev_comps.end(), c);
+      if (touch) {
+        e = hipEventQuery(s->ev_rest[prev]);
+        if (e == hipErrorNotReady) {
+          (void)hipGetLastError();
+          e = hipStreamWaitEvent(s->comp, s->ev_rest[prev], 0);
+        }
+      }
+    }
+    for (size_t i = 0; i < scopies.size() && e == hipSuccess; ++i)
+      e = hipMemcpyAsync(scopies[i].dst, scopies[i].src, s->comp_bytes, scopies[i].kind, s->comp);
     const int64_t nall = (int64_t)step.size() * nb;  // work items of the step
     // blocks_per_cu 0 (automatic): steps of small requests (16 members on
     // average in the served workload) run one workgroup per item, with no
@@ -645,12 +666,12 @@ void worker_body(cmp_server *s) {
       char *h = s->h_arena[half];
       std::memcpy(h, rd.data(), sizeof(SReq) * rd.size());
       put_ids(reinterpret_cast<int32_t *>(h + ids_off));
-      e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
+      if (e == hipSuccess) e = hipMemcpyAsync(s->d_arena[half], h, bytes, hipMemcpyHostToDevice, s->comp);
       ar.reqs = reinterpret_cast<const SReq *>(s->d_arena[half]);
       ar.ids = reinterpret_cast<const int32_t *>(s->d_arena[half] + ids_off);
     }
     if (e == hipSuccess && persistent) e = cmp::launch_fill(s->d_queue, 0, 4, s->comp);
-    const bool copies = s->st.spills + s->st.restores != copies0;  // residency copies this step
+    const bool copies = !scopies.empty();  // residency copies this step
     if (e == hipSuccess) e = hipEventRecord(s->ev_k0[half], s->comp);
     const int nreq = (int)step.size();
     auto launch = [&](hipStream_t st, int64_t items, int phase, uint32_t *q) {
@@ -703,6 +724,7 @@ void worker_body(cmp_server *s) {
       if (e == hipSuccess) e = hipEventRecord(s->ev_rest[half], s->rest);
     }
     prev_split = split;
+    prev_comps = split ? std::move(comps) : std::vector<void *>();
     if (e != hipSuccess) {
       fail(s, CMP_EDEVICE);
       return;
@@ -771,17 +793,24 @@ void completer_loop(cmp_server *s) {
       }
     }
     s->cv_done.notify_all();
-    // device time: from the step's start until its last launch has ended;
-    // the step's half is free again after that
-    float view_ms = 0.f, rest_ms = 0.f;
+    // device time: the step's span, from its start until its last launch has
+    // ended, counted where it does not overlap the previous step's (steps
+    // complete in order); the step's half is free again after that
+    // (the span from events close in time; only where it starts, for the
+    // overlap, from the reference event recorded at creation)
+    float view_ms = 0.f, rest_ms = 0.f, t0 = 0.f;
     hipError_t e2 = e;
     if (e2 == hipSuccess) e2 = hipEventElapsedTime(&view_ms, s->ev_k0[st.half], s->ev_view[st.half]);
     if (e2 == hipSuccess && st.split) e2 = hipEventSynchronize(s->ev_rest[st.half]);
     if (e2 == hipSuccess && st.split) e2 = hipEventElapsedTime(&rest_ms, s->ev_k0[st.half], s->ev_rest[st.half]);
+    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&t0, s->ev_ref, s->ev_k0[st.half]);
+    const double span = std::max(view_ms, rest_ms);
     std::lock_guard<std::mutex> lk(s->mu);
     s->steps.pop_front();
     if (e2 != hipSuccess && s->failed == CMP_OK) s->failed = CMP_EDEVICE;
-    s->st.device_ms += std::max(view_ms, rest_ms);
+    const double overlap = std::min(span, std::max(0.0, s->busy_until - (double)t0));
+    s->st.device_ms += span - overlap;
+    s->busy_until = std::max(s->busy_until, (double)t0 + span);
     s->st.view_ms += view_ms;
     s->steps_completed += 1;
     s->cv_done.notify_all();
@@ -880,6 +909,10 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
       rc = CMP_ENOMEM;
       break;
     }
+    rc = CMP_EDEVICE;
+    if (hipEventCreate(&s->ev_ref) != hipSuccess || hipEventRecord(s->ev_ref, s->comp) != hipSuccess ||
+        hipEventSynchronize(s->ev_ref) != hipSuccess)
+      break;
     s->st.resident_slots = nslots;
     rc = CMP_OK;
   } while (false);
@@ -922,6 +955,7 @@ void composite_server_free(cmp_server *s) {
     if (s->ev_pre[i]) (void)hipEventDestroy(s->ev_pre[i]);
     if (s->ev_view[i]) (void)hipEventDestroy(s->ev_view[i]);
   }
+  if (s->ev_ref) (void)hipEventDestroy(s->ev_ref);
   if (s->comp) (void)hipStreamDestroy(s->comp);
   if (s->rest) (void)hipStreamDestroy(s->rest);
   delete s;
