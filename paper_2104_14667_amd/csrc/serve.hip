@@ -561,7 +561,8 @@ void worker_body(cmp_server *s) {
     for (size_t k = 0; k < step.size() && e == hipSuccess; ++k) {
       Request &r = step[k];
       Session *ss = &s->sessions[r.sid];
-      // (make_resident enqueues its spill and restore copies on the compute stream)
+      // (make_resident collects its spill and restore copies; they are
+      // enqueued on the compute stream below)
       bool rebuild = false;
       e = make_resident(s, *ss, r.sid, in_step, &rebuild, scopies);
       if (e != hipSuccess) break;
