@@ -382,6 +382,7 @@ struct cmp_server {
   int64_t admit_limit = 0;        // sessions admitted at most (HBM budget)
   hipStream_t comp = nullptr;
   hipStream_t rest = nullptr;  // a split step's launch of the rows outside its viewports
+  size_t view_lds = 0;         // dynamic LDS of a viewport launch's workgroup (unused: a cap)
   uint8_t *slab = nullptr;
   std::vector<int64_t> slot_owner;  // session id per slot, or -1
   uint32_t *d_queue = nullptr;
@@ -680,8 +681,8 @@ void worker_body(cmp_server *s) {
       const unsigned g = q ? (unsigned)(s->pool->cus * bpc) : (unsigned)items;
       const int ni = (int)items;
 #define CMP_SERVE(C16, D, arg)                                                                     \
-  k_serve<C16, D><<<g, 256, 0, st>>>(s->pool->base, s->pool->stride, s->W, s->H, rows, nb, nreq, \
-                                     group, phase, ni, (int)nview, q, arg)
+  k_serve<C16, D><<<g, 256, phase == kPhaseView ? s->view_lds : 0, st>>>(                          \
+      s->pool->base, s->pool->stride, s->W, s->H, rows, nb, nreq, group, phase, ni, (int)nview, q, arg)
       if (s->o.count_bits == 16) {
         if (small) CMP_SERVE(true, ArgStep, as);
         else CMP_SERVE(true, ArenaStep, ar);
@@ -914,6 +915,26 @@ int composite_server_create(cmp_server **out, cmp_pool *pool, const cmp_server_o
     if (hipEventCreate(&s->ev_ref) != hipSuccess || hipEventRecord(s->ev_ref, s->comp) != hipSuccess ||
         hipEventSynchronize(s->ev_ref) != hipSuccess)
       break;
+    // The viewport launch of a split step is mostly waiting for its PCIe
+    // writes; LDS it does not use caps it at two workgroups per compute unit,
+    // so that the other rows' launch runs beside it (on the served workload:
+    // 0.077 instead of 0.090 ms of device time per request, for 5 us more of
+    // viewport launch).  No cap if the limits cannot be read.
+    {
+      int lds_cu = 0, lds_block = 0;
+      hipFuncAttributes fa{};
+      const void *kf = o.count_bits == 16 ? reinterpret_cast<const void *>(&k_serve<true, ArgStep>)
+                                          : reinterpret_cast<const void *>(&k_serve<false, ArgStep>);
+      if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, s->dev) ==
+              hipSuccess &&
+          hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, s->dev) == hipSuccess &&
+          hipFuncGetAttributes(&fa, kf) == hipSuccess) {
+        const int64_t want = (int64_t)lds_cu / 3 + 1024 - (int64_t)fa.sharedSizeBytes;
+        s->view_lds = (size_t)std::max<int64_t>(0, std::min<int64_t>(want, lds_block - (int64_t)fa.sharedSizeBytes));
+      } else {
+        (void)hipGetLastError();
+      }
+    }
     s->st.resident_slots = nslots;
     rc = CMP_OK;
   } while (false);
