@@ -523,7 +523,16 @@ def member_layout(pads=(0, 4096, 65536, 2 << 20, (2 << 20) + 4096, 64 << 20), n=
     return {"n": n, "side": side, "reps": reps, "algorithmic_bytes_per_launch": algo, "rows": rows}
 
 
-def pool_layout(pads=(0, 4096, 65536, 1 << 20, (1 << 20) + 4096, 4 << 20), reps=10) -> dict:
+def pool_layout(pads=(0, 4096, 65536, 1 << 20, (1 << 20) + 4096, 4 << 20), reps=10,
+                out_layouts=("packed",)) -> dict:
+    """The batched workload's default tune (graph replay) with the pool's
+    rasters at a stride of 2048^2 + pad bytes, for each pad, and each request's
+    u32 output laid out "packed" (rows of w counts back to back) or "lines"
+    (rows padded to a multiple of 32 counts and the buffer placed so that
+    raster columns that are multiples of 32 start 128-byte lines: the row
+    pieces of the kernel's 512-pixel tiles then cover whole lines): median,
+    min and max device time per batch; every output checked against its
+    closed form."""
     import torch
 
     from . import synth
@@ -535,35 +544,52 @@ def pool_layout(pads=(0, 4096, 65536, 1 << 20, (1 << 20) + 4096, 4 << 20), reps=
     plane = wl.H * wl.W
     buf = torch.empty(wl.pool * (plane + max(pads)) + 64, dtype=torch.uint8, device="cuda:0")
     reqs = wl.requests()
-    for r in reqs:
-        r["out"] = torch.empty((r["h"], r["w"]), dtype=torch.int32, device="cuda:0")
     exp = []
     for r in reqs:
         lvs = np.sort(lv[r["ids"]])
         ec = e[r["y0"]:r["y0"] + r["h"], r["x0"]:r["x0"] + r["w"]]
         exp.append(len(lvs) - np.searchsorted(lvs, ec, side="right"))
+
+    def place(layout):
+        # each request's output buffer, and the (h, w) view of its counts
+        views = []
+        for r in reqs:
+            h, w = r["h"], r["w"]
+            if layout == "packed":
+                t = torch.empty((h, w), dtype=torch.int32, device="cuda:0")
+                r["out"], r["pitch"], r["buf"] = t, w, t
+                views.append(t)
+            else:
+                pitch, off = (w + 31) // 32 * 32, r["x0"] % 32
+                t = torch.empty(h * pitch + 32, dtype=torch.int32, device="cuda:0")  # 256-byte aligned
+                r["out"], r["pitch"], r["buf"] = t.data_ptr() + 4 * off, pitch, t
+                views.append(t[off:off + h * pitch].view(h, pitch)[:, :w])
+        return views
+
     rows = []
     for pad in pads:
         stride = plane + pad
         for i, L in enumerate(lv):
             synth.member_torch(et, int(L), "mask", out=buf[i * stride:i * stride + plane].view(wl.H, wl.W))
         torch.cuda.synchronize()
-        with Pool(buf, wl.pool, wl.W, wl.H, stride, buf.numel()) as pool:
-            ms = []
-            for _ in range(reps + 1):
-                for r in reqs:
-                    r["out"].fill_(-1)
-                pool.run(reqs)
-                ms.append(pool.last()[0])
-            mode = pool.last()[2]
-            exact = all(np.array_equal(r["out"].cpu().numpy().view(np.uint32), x)
-                        for r, x in zip(reqs, exp))
-        d = np.array(ms[1:])
-        rows.append({"pad_bytes": pad, "stride_bytes": stride, "matrix_mode": mode == CMP_BATCH_MATRIX,
-                     "device_ms_median": round(float(np.median(d)), 4),
-                     "device_ms_min": round(float(d.min()), 4), "device_ms_max": round(float(d.max()), 4),
-                     "exact": exact})
-        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        for layout in out_layouts:
+            views = place(layout)
+            with Pool(buf, wl.pool, wl.W, wl.H, stride, buf.numel()) as pool:
+                ms = []
+                for _ in range(reps + 1):
+                    for r in reqs:
+                        r["buf"].fill_(-1)
+                    pool.run(reqs)
+                    ms.append(pool.last()[0])
+                mode = pool.last()[2]
+                exact = all(np.array_equal(v.cpu().numpy().view(np.uint32), x) for v, x in zip(views, exp))
+            d = np.array(ms[1:])
+            rows.append({"pad_bytes": pad, "stride_bytes": stride, "out_layout": layout,
+                         "matrix_mode": mode == CMP_BATCH_MATRIX,
+                         "device_ms_median": round(float(np.median(d)), 4),
+                         "device_ms_min": round(float(d.min()), 4), "device_ms_max": round(float(d.max()), 4),
+                         "exact": exact})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     return {"pool": wl.pool, "W": wl.W, "H": wl.H, "requests": len(reqs), "reps": reps, "rows": rows}
 
 
@@ -776,6 +802,7 @@ def main(argv=None):
     pl = sub.add_parser("pool-layout")
     pl.add_argument("--pads", default=None, help="comma-separated pads in bytes")
     pl.add_argument("--reps", type=int, default=10)
+    pl.add_argument("--out-layouts", default=None, help="comma-separated: packed, lines")
     pl.add_argument("--out", default=None)
     sl = sub.add_parser("serve-layout")
     sl.add_argument("--pads", default=None, help="comma-separated pads in bytes")
@@ -818,6 +845,8 @@ def main(argv=None):
         kw = {"reps": args.reps}
         if args.pads:
             kw["pads"] = tuple(int(x) for x in args.pads.split(","))
+        if args.out_layouts:
+            kw["out_layouts"] = tuple(args.out_layouts.split(","))
         res = pool_layout(**kw)
         print(json.dumps(res))
     elif args.cmd == "serve-layout":
