@@ -368,8 +368,9 @@ int composite_batch_last(const cmp_pool *pool, double *ms, int64_t *items, int32
  * all their composites, the kernel writing each viewport straight into the
  * caller's page-locked memory: the rows holding viewports in a first launch,
  * after which the step's requests are complete, and the other rows in a
- * second (one launch when a full step's worth of requests already waits).  Requests of one
- * session are applied in submission order; sessions interleave.  Session
+ * second beside it (one launch when a full step's worth of requests already
+ * waits).  Requests of one session are applied in submission order; sessions
+ * interleave.  Session
  * composites live in a device slab of hbm_budget_bytes; when a request needs
  * a session that is not resident and the slab is full, a session that is not
  * part of the step is evicted: the one with the lowest GreedyDual priority
@@ -463,12 +464,13 @@ int composite_session_open(cmp_server *srv, int64_t *sid_out);
 int composite_session_close(cmp_server *srv, int64_t sid);
 
 /* Queues one request: op (cmp_op) of n pool ids, then the viewport
- * (vx0, vy0, vw, vh) of the session's count composite copied to dst (host
+ * (vx0, vy0, vw, vh) of the session's count composite written to dst (host
  * memory allocated page-locked, vh rows of vw counts with dst_pitch elements
  * between rows; a count is a uint16 with count_bits = 16, else a uint32; the
  * update kernel writes it there directly).  CMP_EINVAL if dst is not
- * page-locked memory the device can address, or not aligned to a count.  The request is validated against the session's working set
- * as it will be after all its earlier requests: removing an id it will not
+ * page-locked memory the device can address, or not aligned to a count.  The
+ * request is validated against the session's working set as it will be after
+ * all its earlier requests: removing an id it will not
  * hold gives CMP_ENOTMEMBER, and with count_bits = 16 an add that would take
  * it past 65535 members gives CMP_ERANGE.  CMP_EBUSY when max_queue requests
  * are waiting.  A refused request changes nothing.  Thread-safe; returns
@@ -500,9 +502,9 @@ typedef struct cmp_server_stats {
   int64_t queue_peak;        /* most requests waiting for a step at once */
   /* Where the latency goes, summed over completed requests (divide by
    * `requests` for means): from submit until a step takes the request; from
-   * then until the step's last launch and copy are enqueued (residency,
-   * descriptors, launches); from then until its viewport is in host memory
-   * and the completion is seen. */
+   * then until the step's launches are enqueued (residency, descriptors,
+   * launches); from then until its viewport is in host memory and the
+   * completion is seen. */
   double wait_ms, host_ms, flight_ms;
   /* Device time summed over steps (divide by `steps`): from the step's start
    * until its viewports are in host memory (the end of the launch that writes
@@ -531,9 +533,10 @@ typedef struct cmp_replay_req {
 
 /* Submits the requests at their arrival times from the calling thread (an
  * open-loop Poisson schedule does not wait for completions), then waits for
- * all of them.  Request i copies its viewport to dst_ring[i % ring] (pinned
- * host buffers of at least vh * dst_pitch counts of the composite's width).  latency_ns[i] = completion
- * time - scheduled arrival time, or -1 for a request that did not complete.
+ * all of them.  Request i writes its viewport to dst_ring[i % ring] (pinned
+ * host buffers of at least vh * dst_pitch counts of the composite's width).
+ * latency_ns[i] = completion time - scheduled arrival time, or -1 for a
+ * request that did not complete.
  * status: NULL, or nreq entries that receive each request's status.  With
  * status, a request refused by submit with CMP_EBUSY, CMP_ENOTMEMBER (it
  * removes ids that only a refused request would have added) or CMP_ERANGE is
