@@ -470,10 +470,10 @@ int composite_session_close(cmp_server *srv, int64_t sid);
  * update kernel writes it there directly).  CMP_EINVAL if dst is not
  * page-locked memory the device can address, or not aligned to a count.  The
  * request is validated against the session's working set as it will be after
- * all its earlier requests: removing an id it will not
- * hold gives CMP_ENOTMEMBER, and with count_bits = 16 an add that would take
- * it past 65535 members gives CMP_ERANGE.  CMP_EBUSY when max_queue requests
- * are waiting.  A refused request changes nothing.  Thread-safe; returns
+ * all its earlier requests: removing an id it will not hold gives
+ * CMP_ENOTMEMBER, and with count_bits = 16 an add that would take it past
+ * 65535 members gives CMP_ERANGE.  CMP_EBUSY when max_queue requests are
+ * waiting.  A refused request changes nothing.  Thread-safe; returns
  * without waiting: the real-time add and remove of surfaces of Figure 1.
  * *ticket identifies the request to composite_session_wait.  dst must stay
  * valid and untouched until the request completes. */
