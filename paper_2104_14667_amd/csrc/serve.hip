@@ -74,13 +74,19 @@ struct ArenaStep {
   __device__ const SReq &req(int k) const { return reqs[k]; }
   __device__ int32_t id(int i) const { return ids[i]; }
 };
-constexpr int kArgReqs = 8, kArgIds = 512;
-struct ArgStep {
-  SReq reqs[kArgReqs];
-  int32_t ids[kArgIds];
+template <int NR, int NI>
+struct ArgStepT {
+  static constexpr int kReqs = NR, kIds = NI;
+  SReq reqs[NR];
+  int32_t ids[NI];
   __device__ const SReq &req(int k) const { return reqs[k]; }
   __device__ int32_t id(int i) const { return ids[i]; }
 };
+// the one-request steps of interactive serving (0.4 KiB of arguments), and
+// steps of up to 8 requests (2.6 KiB)
+typedef ArgStepT<2, 64> ArgStep1;
+typedef ArgStepT<8, 512> ArgStep;
+constexpr int kArgReqs = ArgStep::kReqs, kArgIds = ArgStep::kIds;
 static_assert(sizeof(ArgStep) <= 4096, "kernel arguments stay within 4 KiB");
 
 // Work items.  A session composite is nb blocks of `rows` rows.  A request's
@@ -644,10 +650,13 @@ void worker_body(cmp_server *s) {
     const bool persistent = s->o.blocks_per_cu > 0 || nids > kServeHeavy * (int64_t)step.size() ||
                             nall > (int64_t)kServeMaxGrid;
     const int bpc = s->o.blocks_per_cu > 0 ? s->o.blocks_per_cu : 2;
-    // descriptors: a small step's travel in the kernel arguments; a larger
-    // one's are uploaded (requests, then ids) ahead of its launches
+    // descriptors: a small step's travel in the kernel arguments (a block of
+    // the smallest size that holds them); a larger one's are uploaded
+    // (requests, then ids) ahead of its launches
     const bool small = (int64_t)step.size() <= kArgReqs && nids <= kArgIds;
     ArgStep as;
+    ArgStep1 as1;
+    const bool tiny = (int64_t)step.size() <= ArgStep1::kReqs && nids <= ArgStep1::kIds;
     ArenaStep ar{};
     auto put_ids = [&](int32_t *dst) {
       for (size_t k = 0; k < step.size(); ++k) {
@@ -655,7 +664,10 @@ void worker_body(cmp_server *s) {
         if (!v.empty()) std::memcpy(dst + rd[k].ids_off, v.data(), 4 * v.size());
       }
     };
-    if (small) {
+    if (tiny) {
+      std::memcpy(as1.reqs, rd.data(), sizeof(SReq) * rd.size());
+      put_ids(as1.ids);
+    } else if (small) {
       std::memcpy(as.reqs, rd.data(), sizeof(SReq) * rd.size());
       put_ids(as.ids);
     } else {
@@ -684,10 +696,12 @@ void worker_body(cmp_server *s) {
   k_serve<C16, D><<<g, 256, phase == kPhaseView ? s->view_lds : 0, st>>>(                          \
       s->pool->base, s->pool->stride, s->W, s->H, rows, nb, nreq, group, phase, ni, (int)nview, q, arg)
       if (s->o.count_bits == 16) {
-        if (small) CMP_SERVE(true, ArgStep, as);
+        if (tiny) CMP_SERVE(true, ArgStep1, as1);
+        else if (small) CMP_SERVE(true, ArgStep, as);
         else CMP_SERVE(true, ArenaStep, ar);
       } else {
-        if (small) CMP_SERVE(false, ArgStep, as);
+        if (tiny) CMP_SERVE(false, ArgStep1, as1);
+        else if (small) CMP_SERVE(false, ArgStep, as);
         else CMP_SERVE(false, ArenaStep, ar);
       }
 #undef CMP_SERVE
