@@ -41,19 +41,24 @@ def same_traffic_ceiling(torch, ptr, stride, n, npix, modes=((1, "rmw_ms"), (0, 
     return out
 
 
-def tile_read_ceiling(torch, ptr, stride, pitch, count, W, H, blocks, reps=6):
+def tile_read_ceiling(torch, ptr, stride, pitch, count, W, H, blocks, reps=6, write_segments=0):
     """Best time in ms of the batched matrix kernel's read pattern with trivial
     arithmetic over a pool of count rasters, raster k's row y at
-    ptr + k * stride + y * pitch."""
+    ptr + k * stride + y * pitch; with write_segments > 0 each 512-pixel tile
+    also writes that many 2 KiB pieces of u32 (the batch's output volume)."""
     lib = C.CDLL(LIB_PATH)
     lib.tile_read_ceiling.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
-                                      C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
-                                      C.POINTER(C.c_float)]
-    sink = torch.empty(H * ((W + 511) // 512) * 256, dtype=torch.int32, device="cuda:0")
+                                      C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_void_p, C.POINTER(C.c_float)]
+    ntiles = H * ((W + 511) // 512)
+    sink = torch.empty(ntiles * 256, dtype=torch.int32, device="cuda:0")
+    wout = (torch.empty(ntiles * write_segments * 512, dtype=torch.int32, device="cuda:0")
+            if write_segments > 0 else None)
     torch.cuda.synchronize()
     ms = C.c_float()
-    rc = lib.tile_read_ceiling(ptr, stride, pitch, count, W, H, sink.data_ptr(), blocks, reps,
-                               torch.cuda.current_stream().cuda_stream, C.byref(ms))
+    rc = lib.tile_read_ceiling(ptr, stride, pitch, count, W, H, sink.data_ptr(),
+                               wout.data_ptr() if wout is not None else None, int(write_segments),
+                               blocks, reps, torch.cuda.current_stream().cuda_stream, C.byref(ms))
     if rc != 0:
         raise RuntimeError(f"tile_read_ceiling failed: hip error {rc}")
     return ms.value

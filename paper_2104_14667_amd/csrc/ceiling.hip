@@ -187,7 +187,8 @@ __global__ __launch_bounds__(256) void k_phased(const uint8_t *__restrict__ mem,
 // 16-byte store per lane per tile keeps the loads live.
 __global__ __launch_bounds__(256) void k_tile_reads(const uint8_t *__restrict__ base, int64_t stride,
                                                     int64_t pitch, int32_t count, int32_t W, int32_t H,
-                                                    uint32_t *__restrict__ sink) {
+                                                    uint32_t *__restrict__ sink,
+                                                    uint32_t *__restrict__ wout, int32_t wsegs) {
   typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
   typedef const __attribute__((address_space(1))) u32x2 gu32x2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -219,6 +220,16 @@ __global__ __launch_bounds__(256) void k_tile_reads(const uint8_t *__restrict__ 
       }
     }
     sink[(int64_t)tile * 256 + threadIdx.x] = a0 ^ a1;
+    // then, with wsegs > 0, wsegs pieces of the tile's 512 pixels of u32
+    // (2 KiB each, a wave's 128 pixels as 8 bytes per lane): the output
+    // volume of the batched kernel's covering requests
+    if (xw < W) {
+      for (int s = 0; s < wsegs; ++s) {
+        typedef __attribute__((address_space(1))) u32x2 gw32x2;
+        *(gw32x2 *)(wout + ((int64_t)tile * wsegs + s) * 512 + 128 * wave + 2 * lane) =
+            u32x2{a0 + (uint32_t)s, a1 ^ (uint32_t)s};
+      }
+    }
   }
 }
 
@@ -370,11 +381,14 @@ int two_phase_ceiling(const uint8_t *members, int64_t stride, int32_t n, int64_t
 // pool of count rasters of W x H (W >= 8), raster k's row y at
 // base + k * stride + y * pitch, and returns the fastest run after the first
 // in *best_ms.  sink: H * ceil(W / 512) * 256 uint32 of device memory.
+// wsegs > 0: each 512-pixel tile also writes wsegs pieces of 2 KiB to wout
+// (H * ceil(W / 512) * wsegs * 512 uint32 of device memory; NULL with 0).
 // Returns 0 or a hipError_t.
 int tile_read_ceiling(const uint8_t *base, int64_t stride, int64_t pitch, int32_t count, int32_t W,
-                      int32_t H, void *sink, int32_t blocks, int32_t reps, void *stream, float *best_ms) {
+                      int32_t H, void *sink, void *wout, int32_t wsegs, int32_t blocks, int32_t reps,
+                      void *stream, float *best_ms) {
   if (!base || !sink || !best_ms || count < 32 || W < 8 || H < 1 || blocks < 1 || reps < 2 ||
-      stride < 1 || pitch < W)
+      stride < 1 || pitch < W || wsegs < 0 || (wsegs > 0 && !wout))
     return (int)hipErrorInvalidValue;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
@@ -389,7 +403,8 @@ int tile_read_ceiling(const uint8_t *base, int64_t stride, int64_t pitch, int32_
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
     e = hipEventRecord(e0, s);
     if (e != hipSuccess) break;
-    k_tile_reads<<<blocks, 256, 0, s>>>(base, stride, pitch, count, W, H, (uint32_t *)sink);
+    k_tile_reads<<<blocks, 256, 0, s>>>(base, stride, pitch, count, W, H, (uint32_t *)sink,
+                                        (uint32_t *)wout, wsegs);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);

@@ -176,3 +176,24 @@ def test_ceiling_library_checks_arguments():
         rc = f(a["members"], a["stride"], a["n"], a["npix"], a["count"], a["sum"], a["max"],
                a["rmw"], a["reps"], None, C.byref(ms))
         assert rc == 1, bad                                  # hipErrorInvalidValue
+
+
+def test_tile_read_reference_checks_arguments():
+    """The batched kernel's read-pattern reference (libceiling.so) rejects bad
+    arguments, a write volume without its buffer among them, before any
+    device call."""
+    from paper_2104_14667_amd import ceiling
+    lib = C.CDLL(ceiling.LIB_PATH)
+    f = lib.tile_read_ceiling
+    f.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                  C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_float)]
+    ms = C.c_float()
+    ok = dict(base=16, stride=4096, pitch=64, count=32, W=64, H=4, sink=16, wout=None, wsegs=0,
+              blocks=2, reps=3)
+    bads = [dict(base=None), dict(sink=None), dict(count=31), dict(W=7), dict(H=0), dict(blocks=0),
+            dict(reps=1), dict(stride=0), dict(pitch=63), dict(wsegs=-1), dict(wsegs=2)]
+    for bad in bads:
+        a = dict(ok, **bad)
+        rc = f(a["base"], a["stride"], a["pitch"], a["count"], a["W"], a["H"], a["sink"], a["wout"],
+               a["wsegs"], a["blocks"], a["reps"], None, C.byref(ms))
+        assert rc == 1, bad                                  # hipErrorInvalidValue
