@@ -661,12 +661,14 @@ def serve_layout(pads=(0, 4096, 65536, 1 << 20), seconds: float = 3.0, check: in
     return {"seconds": seconds, "sessions": wl.sessions, "rows": rows}
 
 
-def tile_reads(blocks_per_cu=(1, 2, 4), pads=(0, 4096)) -> dict:
+def tile_reads(blocks_per_cu=(1, 2, 4), pads=(0, 4096), write_segments=(0,)) -> dict:
     """The batched matrix kernel's read pattern (every pool raster's 512-pixel
     piece of every tile, 4 waves per tile) with trivial arithmetic, over the
     batched workload's pool shape (2048 rasters of 2048x2048): rasters stored
     one after another at 4 MiB + pad, or row-interleaved (row y of every
-    raster side by side: raster k's row y at (y * 2048 + k) * 2048)."""
+    raster side by side: raster k's row y at (y * 2048 + k) * 2048); with
+    each tile also writing each of `write_segments` pieces of 2 KiB (23 is
+    the 64-request batch's output volume, 0.386 GB)."""
     import torch
 
     from . import synth
@@ -678,14 +680,19 @@ def tile_reads(blocks_per_cu=(1, 2, 4), pads=(0, 4096)) -> dict:
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     layouts = [(f"raster-major, stride 4 MiB + {pad}", plane + pad, W) for pad in pads]
     layouts.append(("row-interleaved", W, P * W))
+    ntiles = H * ((W + 511) // 512)
     rows = []
-    for name, stride, pitch in layouts:
-        for b in blocks_per_cu:
-            ms = tile_read_ceiling(torch, buf.data_ptr(), stride, pitch, P, W, H, cus * b)
-            rows.append({"layout": name, "stride_bytes": stride, "row_pitch_bytes": pitch,
-                         "workgroups_per_cu": b, "ms": round(ms, 4),
-                         "GBps": round(P * plane / (ms * 1e-3) / 1e9, 1)})
-            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    for ws in write_segments:
+        for name, stride, pitch in layouts:
+            for b in blocks_per_cu:
+                ms = tile_read_ceiling(torch, buf.data_ptr(), stride, pitch, P, W, H, cus * b,
+                                       write_segments=ws)
+                moved = P * plane + ntiles * ws * 2048
+                rows.append({"layout": name, "stride_bytes": stride, "row_pitch_bytes": pitch,
+                             "workgroups_per_cu": b, "write_segments": ws,
+                             "written_bytes": ntiles * ws * 2048, "ms": round(ms, 4),
+                             "GBps": round(moved / (ms * 1e-3) / 1e9, 1)})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     return {"pool": P, "W": W, "H": H, "bytes": P * plane, "rows": rows}
 
 
@@ -811,6 +818,8 @@ def main(argv=None):
                     help="comma-separated view_group values (0: the library's choice)")
     sl.add_argument("--out", default=None)
     tr = sub.add_parser("tile-reads")
+    tr.add_argument("--write-segments", default=None,
+                    help="comma-separated 2 KiB pieces written per tile (23: the batch's outputs)")
     tr.add_argument("--out", default=None)
     tp = sub.add_parser("two-phase")
     tp.add_argument("--out", default=None)
@@ -858,7 +867,10 @@ def main(argv=None):
         res = serve_layout(**kw)
         print(json.dumps(res))
     elif args.cmd == "tile-reads":
-        res = tile_reads()
+        kw = {}
+        if args.write_segments:
+            kw["write_segments"] = tuple(int(x) for x in args.write_segments.split(","))
+        res = tile_reads(**kw)
         print(json.dumps(res))
     elif args.cmd == "two-phase":
         res = two_phase()
