@@ -497,6 +497,9 @@ def run_batched(torch, reps, tuned=True, cpu_seconds=3.0):
                           f"raster's piece, 2 workgroups per CU, trivial arithmetic, and {wsegs} pieces of "
                           f"2 KiB written per tile ({ntiles * wsegs * 2048 / 1e9:.3f} GB, the outputs' volume)",
                 "GBps": round(rw, 1), "frac": round(ach / rw, 4),
+                # the reference reads every raster's piece, the kernel only
+                # the listed chunks' (fewer bytes): its time over the kernel's
+                "ms": round(rw_ms, 4), "time_frac": round(rw_ms / p, 4),
                 "read_only_GBps": round(ref, 1), "read_only_frac": round(ach / ref, 4)}
     if cpu_seconds > 0:
         log("  batched cpu baseline")
