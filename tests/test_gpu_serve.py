@@ -552,3 +552,41 @@ def test_split_steps_with_evictions(cb, remat, vg):
             else:
                 assert st["drops"] + st["spills"] > 0
     _check_alone(wl, stack, sched, outs)
+
+
+@pytest.mark.parametrize("cb,vg", [(16, 0), (32, 0), (16, 3)])
+def test_one_step_of_mixed_viewports(cb, vg):
+    """Requests queued while the server is paused form one step: sessions whose
+    viewports differ in size and place (one pixel, one row, one column, a
+    square, the whole raster) are updated by one viewport launch and one
+    launch of the other rows, the requests' items found by the kernel's
+    search over unequal counts.  Each viewport equals the oracle's window."""
+    rng = np.random.default_rng(91 + cb + vg)
+    P, H, W = 8, 40, 96
+    stack = rng.integers(0, 3, size=(P, H, W), dtype=np.uint8)
+    buf = _pool(stack)
+    views = [(5, 7, 1, 1), (0, 13, W, 1), (50, 0, 1, H), (17, 9, 33, 21), (0, 0, W, H), (80, 39, 16, 1)]
+    say("serve one step mixed", cb, vg)
+    with Pool(buf, P, W, H, H * W, buf.numel()) as pool:
+        with Server(pool, max_batch=8, hbm_budget_bytes=8 * H * W * 4, max_view_pixels=H * W,
+                    tile_vecs=64, count_bits=cb, view_group=vg) as srv:
+            sids = [srv.open() for _ in views]
+            held = [{} for _ in views]
+            for rnd in range(3):
+                srv.pause(True)
+                tickets, outs = [], []
+                for k, (sid, v) in enumerate(zip(sids, views)):
+                    ids = [int(i) for i in rng.integers(0, P, size=1 + (k + rnd) % 5)]
+                    for i in ids:
+                        held[k][i] = held[k].get(i, 0) + 1
+                    dst = _vbuf(cb, (v[3], v[2]), -1)
+                    tickets.append(srv.submit(sid, CMP_OP_ADD, ids, v, dst))
+                    outs.append(dst)
+                steps0 = srv.stats()["steps"]
+                srv.pause(False)
+                for t in tickets:
+                    srv.wait(t)
+                assert srv.stats()["steps"] == steps0 + 1          # one step held them all
+                for k, v in enumerate(views):
+                    exp = _expect_view(stack, held[k], dict(vx0=v[0], vy0=v[1], vw=v[2], vh=v[3]))
+                    assert np.array_equal(_counts(outs[k]), exp), (rnd, k, v)
